@@ -1,0 +1,670 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-type the oracle's own formulas: each compares the oracle with a
+closed form derived independently (world-space forms, camera geometry, special
+cases), an invariant, or brute force.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_13397_amd import synth
+
+
+def one_gaussian_scene(mu, log_s, quat=(1, 0, 0, 0), logit=0.0, rgb=(1.0, 0.5, 0.25), rho2=0.0):
+    return {
+        "n": 1, "color_mode": 0,
+        "means": np.array(mu, np.float32).reshape(3, 1),
+        "log_scales": np.array(log_s, np.float32).reshape(3, 1),
+        "quats": np.array(quat, np.float32).reshape(4, 1),
+        "opacity_logits": np.array([logit], np.float32),
+        "color": np.array(rgb, np.float32).reshape(3, 1),
+        "rho2": np.array([rho2], np.float32),
+    }
+
+
+def sigmoid(x):
+    return 1.0 / (1.0 + math.exp(-x))
+
+
+def pinhole(w, h, f, cx=None, cy=None, origin=(0, 0, 0), R=None):
+    return synth.camera(synth.PINHOLE, w, h, fx=f, fy=f, cx=w / 2 if cx is None else cx,
+                        cy=h / 2 if cy is None else cy, R_c2w=np.eye(3) if R is None else R, origin=origin)
+
+
+def quat_to_R(q):
+    w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(q)
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+# ----------------------------------------------------------------------------- Eq. 2
+
+def test_eq2_dot_and_cross_forms_agree():
+    """Eq. 2 prints D^2 twice: |o_u + t* d_u|^2 and |d_u x o_u|^2 / |d_u|^2."""
+    scene = synth.make_scene(64, seed=11, layout="uniform", color="rgb")
+    cam = pinhole(32, 24, 30.0, origin=(0.0, 0.0, -3.0))
+    rays, valid = O.pixel_rays(cam)
+    rays = rays.reshape(-1, 9)
+    pre, W = O.preprocess(scene, cam["origin"])
+    o = np.array(cam["origin"])
+    worst = 0.0
+    for gi in range(0, 64, 7):
+        res = O.pair_batch(scene, gi, o, rays)
+        mu = scene["means"][:, gi].astype(np.float64)
+        ou = W[gi] @ (o - mu)
+        du = rays[:, :3] @ W[gi].T
+        cross = np.cross(du, ou)
+        D2_cross = np.sum(cross ** 2, 1) / np.sum(du ** 2, 1)
+        worst = max(worst, np.max(np.abs(res[:, 3] - D2_cross) / np.maximum(1.0, D2_cross)))
+    assert worst < 1e-10
+
+
+# ----------------------------------------------------------------------------- Eq. 6-9
+
+def iso_on_ray_T(sigma, t, s, d, dx, dy):
+    """Isotropic Gaussian (scale s) centred on the centre ray at distance t: q = 0 and
+    e_i = (t/s) (I - d d^T)(d_i - d), so T = sigma / sqrt(det(I + E^T E / 3))."""
+    P = np.eye(3) - np.outer(d, d)
+    ex = (t / s) * P @ (dx - d)
+    ey = (t / s) * P @ (dy - d)
+    K = np.array([[ex @ ex, ex @ ey], [ex @ ey, ey @ ey]]) / 3.0
+    return sigma / math.sqrt(np.linalg.det(np.eye(2) + K))
+
+
+@pytest.mark.parametrize("f", [60.0, 2.0])
+def test_eq9_on_axis_isotropic_closed_form(f):
+    """On the optical axis of a pinhole: |e_x| = |e_y| = (t/s) sin(atan(1/(2f))), e_x _|_ e_y,
+    so T = sigma / (1 + (t/s)^2 sin^2(alpha) / 3).  f = 2 makes the half-pixel angle large
+    (0.245 rad) so that a missing projector or a chord-for-sine slip is visible."""
+    t, s, logit = 3.0, math.exp(-3.0), 0.7
+    cam = pinhole(65, 49, f, cx=32.5, cy=24.5, origin=(0.0, 0.0, -3.0))
+    scene = one_gaussian_scene((0.0, 0.0, 0.0), (-3.0, -3.0, -3.0), quat=(0.3, -0.5, 0.1, 0.8), logit=logit)
+    rays, valid = O.pixel_rays(cam)
+    centre = rays[24, 32]
+    np.testing.assert_allclose(centre[:3], [0, 0, 1], atol=1e-15)
+    res = O.pair_batch(scene, 0, cam["origin"], centre[None])
+    sig = sigmoid(np.float32(logit))
+    s32 = math.exp(float(np.float32(-3.0)))
+    alpha = math.atan(1.0 / (2.0 * f))
+    expect = sig / (1.0 + (t / s32) ** 2 * math.sin(alpha) ** 2 / 3.0)
+    assert res[0, 0] == pytest.approx(expect, rel=1e-12)
+    if f == 60.0:  # the survey-time worked value T / sigma for f = 60, t = 3, s = e^-3
+        assert expect / sig == pytest.approx(0.922474, abs=5e-7)
+
+
+def test_eq9_off_axis_isotropic_closed_form_pinhole_and_kb():
+    """Off-axis pixels (spec check c): the same isotropic Gaussian on the centre ray of
+    pixel (u, v) gives T = sigma / sqrt(det(I + E^T E/3)) with E from each camera's own
+    rays.  The rays here come from the camera formulas written out in this test."""
+    t, s = 4.0, math.exp(-3.5)
+    f, cx, cy = 40.0, 40.0, 30.0
+    sig = sigmoid(0.0)
+    s32 = math.exp(float(np.float32(-3.5)))
+
+    def pin_dir(x, y):
+        v = np.array([(x - cx) / f, (y - cy) / f, 1.0])
+        return v / np.linalg.norm(v)
+
+    def kb0_dir(x, y):  # zero-distortion equidistant fisheye: theta = |m|
+        m = np.array([(x - cx) / f, (y - cy) / f])
+        th = np.linalg.norm(m)
+        if th == 0:
+            return np.array([0, 0, 1.0])
+        return np.array([math.sin(th) * m[0] / th, math.sin(th) * m[1] / th, math.cos(th)])
+
+    cams = {
+        "pin": (pinhole(80, 60, f, cx, cy), pin_dir),
+        "kb": (synth.camera(synth.FISHEYE_KB, 80, 60, fx=f, fy=f, cx=cx, cy=cy, theta_max=math.radians(95)), kb0_dir),
+    }
+    for name, (cam, fn) in cams.items():
+        rays, valid = O.pixel_rays(cam)
+        for (i, j) in [(40, 30), (70, 30), (75, 55), (5, 10), (52, 44)]:
+            px, py = i + 0.5, j + 0.5
+            d, dx, dy = fn(px, py), fn(px + 0.5, py), fn(px, py + 0.5)
+            np.testing.assert_allclose(rays[j, i, :3], d, atol=1e-12)
+            np.testing.assert_allclose(rays[j, i, 3:6], dx, atol=1e-12)
+            np.testing.assert_allclose(rays[j, i, 6:9], dy, atol=1e-12)
+            mu = t * d
+            scene = one_gaussian_scene(mu, (-3.5,) * 3, quat=(0.9, 0.1, -0.3, 0.2))
+            mu32 = scene["means"][:, 0].astype(np.float64)
+            tt = np.linalg.norm(mu32)
+            dd = mu32 / tt  # the ray through the float32 mean
+            res = O.pair_batch(scene, 0, (0.0, 0.0, 0.0), np.concatenate([dd, dx, dy])[None])
+            expect = iso_on_ray_T(sig, tt, s32, dd, dx, dy)
+            assert res[0, 0] == pytest.approx(expect, rel=1e-9), (name, i, j)
+
+
+def world_space_T(scene, gi, o, d, dx, dy, use_floor, fs=1.0):
+    """Eq. 9 + Eq. 12 evaluated entirely in world space (numpy.linalg), the second route:
+    Sigma_eff = R S'^2 R^T; t* = v^T S^-1 d / d^T S^-1 d; world half-edges
+    f_i = t* (delta_i - d (d^T S^-1 delta_i)/(d^T S^-1 d)) (the whitened e_i mapped back by W^-1);
+    Sigma_tot = Sigma_eff + [ (f_x f_x^T + f_y f_y^T)/3 - rho^2 I ]_+ ;
+    T = sigma_eff sqrt(det Sigma_eff / det Sigma_tot) exp(-m/2), m = min_t Mahalanobis^2 of
+    the ray to N(mu, Sigma_tot)."""
+    mu = scene["means"][:, gi].astype(np.float64)
+    s = np.exp(scene["log_scales"][:, gi].astype(np.float64))
+    rho2 = float(scene["rho2"][gi]) if use_floor else 0.0
+    sp = np.sqrt(s * s + rho2)
+    R = quat_to_R(scene["quats"][:, gi].astype(np.float64))
+    sig = sigmoid(float(scene["opacity_logits"][gi])) * np.prod(s / sp)
+    Se = R @ np.diag(sp ** 2) @ R.T
+    Si = np.linalg.inv(Se)
+    v = mu - o
+    tstar = (v @ Si @ d) / (d @ Si @ d)
+    F = []
+    for di in (dx, dy):
+        delta = fs * (di - d)
+        F.append(tstar * (delta - d * (d @ Si @ delta) / (d @ Si @ d)))
+    Sfp = (np.outer(F[0], F[0]) + np.outer(F[1], F[1])) / 3.0
+    if use_floor and rho2 > 0:
+        lam, V = np.linalg.eigh(Sfp - rho2 * np.eye(3))
+        Sfp = V @ np.diag(np.maximum(lam, 0)) @ V.T
+    St = Se + Sfp
+    Sti = np.linalg.inv(St)
+    m = v @ Sti @ v - (d @ Sti @ v) ** 2 / (d @ Sti @ d)
+    return sig * math.sqrt(np.linalg.det(Se) / np.linalg.det(St)) * math.exp(-0.5 * m), tstar
+
+
+@pytest.mark.parametrize("use_floor", [0, 1])
+def test_eq9_eq12_whitened_route_equals_world_route(use_floor):
+    """The oracle's whitened 3x3 route (Eq. 6, 8, 9 and the literal eigen-clamp of Eq. 12)
+    equals the world-space form of the same convolution on random anisotropic Gaussians,
+    sheared wide-angle pixels and floors that partly cover the footprint."""
+    rng = np.random.default_rng(5)
+    cam = synth.kb_camera(64, 64, 95.0, (0.02, -0.01, 0.004, -0.001), 32.0, np.eye(3), (0.0, 0.0, 0.0))
+    rays, valid = O.pixel_rays(cam)
+    n_checked = 0
+    worst = 0.0
+    for trial in range(300):
+        j, i = rng.integers(0, 64, 2)
+        if not valid[j, i]:
+            continue
+        r = rays[j, i]
+        t = rng.uniform(0.5, 4.0)
+        mu = t * r[:3] + rng.normal(0, 0.03, 3)
+        log_s = rng.normal(-3.5, 0.6, 3)
+        scene = one_gaussian_scene(mu, log_s, quat=rng.normal(size=4), logit=rng.normal())
+        # a floor between the footprint's two eigenvalues in about half the trials
+        foot = (t * np.linalg.norm(r[3:6] - r[:3])) ** 2 / 3
+        scene["rho2"][0] = np.float32(foot * rng.uniform(0.0, 2.0))
+        opts = O.Opts(use_floor=use_floor, t_near=0.0)
+        res = O.pair_batch(scene, 0, (0.0, 0.0, 0.0), r[None], opts)
+        ref, tstar = world_space_T(scene, 0, np.zeros(3), r[:3], r[3:6], r[6:9], use_floor)
+        assert res[0, 2] == pytest.approx(tstar, rel=1e-9)
+        if ref > 1e-12:
+            worst = max(worst, abs(res[0, 1] - ref) / ref)
+            n_checked += 1
+    assert n_checked > 100
+    assert worst < 1e-9
+
+
+def test_zero_footprint_limit_is_centre_ray_and_quadratic():
+    """North-star check (b): footprint_scale = 0 gives the centre-ray response of Eq. 3
+    (C = 1) exactly, and T(eps) - T(0) = O(eps^2)."""
+    scene = synth.make_scene(40, seed=12, layout="uniform", color="rgb")
+    cam = pinhole(24, 18, 20.0, origin=(0.0, 0.0, -3.0))
+    rays, valid = O.pixel_rays(cam)
+    rays = rays.reshape(-1, 9)
+    o = cam["origin"]
+    for gi in range(0, 40, 5):
+        T0 = O.pair_batch(scene, gi, o, rays, O.Opts(filter_mode=1, footprint_scale=0.0))[:, 1]
+        Tc = O.pair_batch(scene, gi, o, rays, O.Opts(filter_mode=0))[:, 1]
+        np.testing.assert_array_equal(T0, Tc)
+    # convergence order on pixels where the response is sizeable
+    counts = [(O.pair_batch(scene, k, o, rays, O.Opts(filter_mode=0))[:, 1] > 1e-2).sum() for k in range(40)]
+    gi = int(np.argmax(counts))
+    Tc = O.pair_batch(scene, gi, o, rays, O.Opts(filter_mode=0))[:, 1]
+    sel = Tc > 1e-2
+    assert sel.sum() > 3
+    eps = np.array([0.4, 0.2, 0.1, 0.05])
+    diffs = []
+    for e in eps:
+        Te = O.pair_batch(scene, gi, o, rays[sel], O.Opts(filter_mode=1, footprint_scale=e))[:, 1]
+        diffs.append(np.max(np.abs(Te - Tc[sel])))
+    slope = np.polyfit(np.log(eps), np.log(diffs), 1)[0]
+    assert 1.9 < slope < 2.1
+
+
+def test_isotropic_mode_closed_form():
+    """Isotropic mode: A = I + (tr Sigma_fp / 2) M_perp, so on the axis with equal half-edges
+    of whitened length a it equals the anisotropic result 1/(1 + a^2/3)."""
+    t, s = 3.0, math.exp(-3.0)
+    cam = pinhole(65, 49, 5.0, cx=32.5, cy=24.5, origin=(0.0, 0.0, -3.0))
+    scene = one_gaussian_scene((0.0, 0.0, 0.0), (-3.0,) * 3, logit=0.0)
+    rays, _ = O.pixel_rays(cam)
+    c = rays[24, 32][None]
+    ta = O.pair_batch(scene, 0, cam["origin"], c, O.Opts(filter_mode=1))[0, 0]
+    ti = O.pair_batch(scene, 0, cam["origin"], c, O.Opts(filter_mode=2))[0, 0]
+    assert ti == pytest.approx(ta, rel=1e-12)
+    # off-axis with a sheared footprint the two differ
+    c2 = rays[3, 60][None]
+    mu = t * c2[0, :3]
+    scene2 = one_gaussian_scene(mu + np.array([0, 0, -3.0]) * 0, (-3.0,) * 3)
+    scene2["means"][:, 0] = (np.array(cam["origin"]) + t * c2[0, :3]).astype(np.float32)
+    ta2 = O.pair_batch(scene2, 0, cam["origin"], c2, O.Opts(filter_mode=1))[0, 1]
+    ti2 = O.pair_batch(scene2, 0, cam["origin"], c2, O.Opts(filter_mode=2))[0, 1]
+    assert abs(ta2 - ti2) > 1e-4
+
+
+# ----------------------------------------------------------------------------- floor (Eq. 10-12)
+
+def test_floor_is_scale_substitution_with_volume_compensation():
+    """Eq. 10: the floor equals replacing s_i by sqrt(s_i^2 + rho^2) and sigma by
+    sigma * prod s_i / sqrt(s_i^2 + rho^2) (additive composition keeps the full footprint)."""
+    scene = synth.make_scene(60, seed=13, layout="uniform", color="rgb")
+    scene["rho2"] = np.full(60, 2e-3, np.float32)
+    cam = pinhole(32, 24, 30.0, origin=(0.0, 0.0, -3.0))
+    a = O.render(scene, cam, O.Opts(use_floor=1, composition=1))["rgba"]
+    s = np.exp(scene["log_scales"].astype(np.float64))
+    sp = np.sqrt(s * s + scene["rho2"].astype(np.float64)[None])
+    sig = 1 / (1 + np.exp(-scene["opacity_logits"].astype(np.float64))) * np.prod(s / sp, 0)
+    alt = dict(scene)
+    alt["log_scales"] = np.log(sp).astype(np.float32)
+    alt["opacity_logits"] = np.log(sig / (1 - sig)).astype(np.float32)
+    alt["rho2"] = np.zeros(60, np.float32)
+    b = O.render(alt, cam, O.Opts(use_floor=0))["rgba"]
+    # the substitution goes through float32 storage, hence the tolerance
+    assert np.max(np.abs(a - b)) < 2e-5
+
+
+def test_floor_with_zero_rho_equals_no_floor():
+    scene = synth.make_scene(60, seed=14, layout="uniform", color="rgb")
+    cam = pinhole(32, 24, 30.0, origin=(0.0, 0.0, -3.0))
+    a = O.render(scene, cam, O.Opts(use_floor=1))["rgba"]
+    b = O.render(scene, cam, O.Opts(use_floor=0))["rgba"]
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_floor_covering_footprint_removes_render_filter():
+    """Eq. 12: when rho^2 exceeds the world footprint variance in every direction, the
+    clamp removes the whole footprint and the response is the floored centre-ray one."""
+    scene = synth.make_scene(60, seed=15, layout="uniform", color="rgb")
+    cam = pinhole(32, 24, 30.0, origin=(0.0, 0.0, -3.0))
+    # world half-edge at depth <= 4.2: 4.2 * 0.5/30 = 0.07 -> variance < 0.07^2 * 2/3
+    scene["rho2"] = np.full(60, 0.07 ** 2, np.float32)
+    a = O.render(scene, cam, O.Opts(use_floor=1, filter_mode=1))["rgba"]
+    b = O.render(scene, cam, O.Opts(use_floor=1, filter_mode=0))["rgba"]
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_marginal_clamp_is_directionwise():
+    """Eq. 12 on a rank-2 footprint: a floor between the two footprint eigenvalues keeps
+    exactly one direction; the result lies strictly between 'no filter' and 'additive'."""
+    t = 3.0
+    cam = pinhole(65, 49, 3.0, cx=32.5, cy=24.5, origin=(0.0, 0.0, -3.0))
+    rays, _ = O.pixel_rays(cam)
+    r = rays[24, 60]
+    d = r[:3]
+    scene = one_gaussian_scene(np.array(cam["origin"]) + t * d + np.array([0.003, -0.002, 0.0]), (-2.5,) * 3)
+    P = np.eye(3) - np.outer(d, d)
+    ex, ey = t * P @ (r[3:6] - d), t * P @ (r[6:9] - d)
+    lam = np.linalg.eigvalsh((np.outer(ex, ex) + np.outer(ey, ey)) / 3)[1:]
+    scene["rho2"][0] = np.float32(np.sqrt(lam[0] * lam[1]))
+    o = cam["origin"]
+    Tm = O.pair_batch(scene, 0, o, r[None], O.Opts(use_floor=1, composition=0))[0, 0]
+    Ta = O.pair_batch(scene, 0, o, r[None], O.Opts(use_floor=1, composition=1))[0, 0]
+    T0 = O.pair_batch(scene, 0, o, r[None], O.Opts(use_floor=1, filter_mode=0))[0, 0]
+    assert Ta < Tm < T0
+
+
+# ----------------------------------------------------------------------------- compositing (Eq. 4)
+
+def test_compositing_invariants():
+    """North-star check (d): transmittance monotone, total alpha in [0, 1], colour bounded
+    by alpha times the largest colour; alpha = 1 - prod(1 - alpha_k)."""
+    scene, cam = synth.tiny_config()
+    out = O.render(scene, cam)
+    rgba = out["rgba"]
+    assert rgba[..., 3].min() >= 0 and rgba[..., 3].max() <= 1
+    cmax = scene["color"].max()
+    assert np.all(rgba[..., :3] <= rgba[..., 3:4] * cmax + 1e-12)
+    # T_min stop: transmittance never falls below T_min
+    assert np.all(1 - rgba[..., 3] >= 1e-4 - 1e-15)
+
+
+def test_permutation_invariance():
+    """Input order does not matter (depths are distinct): the order is the depth key's."""
+    scene, cam = synth.tiny_config()
+    perm = np.random.default_rng(3).permutation(scene["n"])
+    ps = synth.subset_scene(scene, perm)
+    a = O.render(scene, cam)["rgba"]
+    b = O.render(ps, cam)["rgba"]
+    assert np.max(np.abs(a - b)) == 0.0
+
+
+def test_rigid_rotation_invariance_exact():
+    """Rotating scene and camera by 180 degrees about z (exact in float32) leaves the image
+    unchanged."""
+    scene, cam = synth.tiny_config()
+    cam = dict(cam)
+    cam["origin"] = (0.3, -0.2, -3.0)
+    a = O.render(scene, cam)["rgba"]
+    rs = dict(scene)
+    rs["means"] = (scene["means"] * np.array([-1, -1, 1], np.float32)[:, None]).astype(np.float32)
+    w, x, y, z = scene["quats"]
+    rs["quats"] = np.stack([-z, -y, x, w]).astype(np.float32)  # (0,0,0,1) (x) q
+    Rz = np.diag([-1.0, -1.0, 1.0])
+    rc = dict(cam)
+    rc["origin"] = (-0.3, 0.2, -3.0)
+    rc["R_c2w"] = (Rz @ np.array(cam["R_c2w"])).tolist()
+    b = O.render(rs, rc)["rgba"]
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_uniform_scaling_invariance():
+    """Scaling positions, scales and the camera centre by c = 2 (exact) and rho^2, t_near
+    accordingly leaves the image unchanged."""
+    scene, cam = synth.tiny_config()
+    scene = dict(scene)
+    scene["rho2"] = np.full(scene["n"], 1e-4, np.float32)
+    a = O.render(scene, cam, O.Opts(use_floor=1))["rgba"]
+    s2 = dict(scene)
+    s2["means"] = scene["means"] * 2
+    s2["log_scales"] = (scene["log_scales"].astype(np.float64) + math.log(2.0)).astype(np.float32)
+    s2["rho2"] = scene["rho2"] * 4
+    c2 = dict(cam)
+    c2["origin"] = tuple(2 * v for v in cam["origin"])
+    b = O.render(s2, c2, O.Opts(use_floor=1, t_near=0.4))["rgba"]
+    # log-scales shifted through float32: relative scale error ~ 6e-8
+    assert np.max(np.abs(a - b)) < 1e-5
+
+
+# ----------------------------------------------------------------------------- cameras
+
+@pytest.mark.parametrize("which", ["pinhole", "kb", "equirect"])
+def test_camera_round_trip(which):
+    k, _ = synth.draw_kb_coeffs(31, math.radians(95))
+    cams = {
+        "pinhole": pinhole(640, 480, 500.0, 320.3, 241.7, R=synth.look_at((0, 0, 0), (1, 2, 0.5))),
+        "kb": synth.kb_camera(400, 400, 95.0, k, 200.0, synth.look_at((0, 0, 0), (1, -1, 0.2)), (0, 0, 0)),
+        "equirect": synth.camera(synth.EQUIRECT, 512, 256, R_c2w=synth.look_at((0, 0, 0), (0.3, 1, 0))),
+    }
+    cam = cams[which]
+    rng = np.random.default_rng(0)
+    px = rng.uniform(0, cam["full_w"], 4000)
+    py = rng.uniform(0, cam["full_h"], 4000)
+    d, v = O.unproject(cam, px, py)
+    assert np.allclose(np.linalg.norm(d[v], axis=1), 1.0, atol=1e-14)
+    x, y, v2 = O.project(cam, d[v])
+    assert v2.all()
+    assert np.max(np.abs(x - px[v])) < 1e-9 and np.max(np.abs(y - py[v])) < 1e-9
+    if which == "kb":
+        # the image circle: about pi/4 of the square is valid
+        assert 0.70 < v.mean() < 0.86
+
+
+def test_kb_zero_distortion_is_equidistant():
+    cam = synth.camera(synth.FISHEYE_KB, 200, 200, fx=50.0, fy=50.0, cx=100.0, cy=100.0,
+                       theta_max=math.radians(95))
+    rng = np.random.default_rng(1)
+    px = rng.uniform(0, 200, 500)
+    py = rng.uniform(0, 200, 500)
+    d, v = O.unproject(cam, px, py)
+    th = np.hypot((px - 100) / 50, (py - 100) / 50)
+    assert np.all(v == (th <= math.radians(95)))
+    np.testing.assert_allclose(np.arccos(np.clip(d[v, 2], -1, 1)), th[v], atol=1e-9)
+
+
+def test_kb_monotone_draw_and_newton():
+    """The generator's rejection gives increasing theta_d; the oracle's inverse then agrees
+    with a dense table lookup of the forward polynomial."""
+    k, tries = synth.draw_kb_coeffs(31, math.radians(95))
+    assert tries >= 1
+    cam = synth.kb_camera(300, 300, 95.0, k, 150.0, np.eye(3), (0, 0, 0))
+    th = np.linspace(0, math.radians(95), 200001)
+    t2 = th * th
+    thd = th * (1 + k[0] * t2 + k[1] * t2 ** 2 + k[2] * t2 ** 3 + k[3] * t2 ** 4)
+    assert np.all(np.diff(thd) > 0)
+    r = np.linspace(0, thd[-1] * cam["fx"], 50)
+    d, v = O.unproject(cam, cam["cx"] + r, np.full(50, cam["cy"]))
+    assert v.all()
+    theta = np.arccos(np.clip(d @ np.array([0, 0, 1.0]), -1, 1))
+    np.testing.assert_allclose(theta, np.interp(r / cam["fx"], thd, th), atol=1e-8)
+
+
+def test_equirect_rows_constant_latitude():
+    cam = synth.camera(synth.EQUIRECT, 64, 32)
+    rays, v = O.pixel_rays(cam)
+    assert v.all()
+    lat = np.arcsin(-rays[..., 1])
+    assert np.max(np.abs(lat - lat[:, :1])) < 1e-14
+    np.testing.assert_allclose(lat[:, 0], math.pi * (0.5 - (np.arange(32) + 0.5) / 32), atol=1e-14)
+
+
+def test_pinhole_vs_zero_distortion_fisheye_paraxial():
+    """North-star check (c): a pinhole and a zero-distortion fisheye with the same focal
+    length see the same rays near the axis (they differ by f |tan(theta) - theta| pixels),
+    so their renders agree there."""
+    scene, _ = synth.tiny_config()
+    f = 400.0
+    pin = pinhole(41, 41, f, 20.5, 20.5, origin=(0.0, 0.0, -3.0))
+    kb = synth.camera(synth.FISHEYE_KB, 41, 41, fx=f, fy=f, cx=20.5, cy=20.5,
+                      theta_max=math.radians(95), origin=(0.0, 0.0, -3.0))
+    a = O.render(scene, pin)["rgba"]
+    b = O.render(scene, kb)["rgba"]
+    jj, ii = np.mgrid[0:41, 0:41]
+    th = np.hypot(ii + 0.5 - 20.5, jj + 0.5 - 20.5) / f
+    disc = f * np.abs(np.tan(th) - th) < 1e-3
+    assert disc.sum() > 150
+    assert np.max(np.abs(a - b)[disc]) < 2e-4
+    assert np.max(np.abs(a - b)) > 0  # but they are different cameras
+
+
+# ----------------------------------------------------------------------------- colour
+
+def test_sh_basis_orthonormal_and_signs():
+    """The real SH basis is orthonormal on the sphere (Gauss-Legendre x uniform quadrature,
+    exact for these degrees); Y_00 = 1/(2 sqrt(pi)); Condon-Shortley: Y_{1,1}(+x) < 0."""
+    xs, ws = np.polynomial.legendre.leggauss(16)
+    phis = np.linspace(0, 2 * np.pi, 32, endpoint=False)
+    G = np.zeros((16, 16))
+    for z, wz in zip(xs, ws):
+        for ph in phis:
+            r = math.sqrt(1 - z * z)
+            Y = O.sh_basis(np.array([r * math.cos(ph), r * math.sin(ph), z]))
+            G += np.outer(Y, Y) * wz * (2 * np.pi / 32)
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+    Y = O.sh_basis(np.array([1.0, 0, 0]))
+    assert Y[0] == pytest.approx(0.5 / math.sqrt(math.pi), rel=1e-14)
+    assert Y[3] == pytest.approx(-math.sqrt(3 / (4 * math.pi)), rel=1e-14)
+    Y = O.sh_basis(np.array([0, 0, 1.0]))
+    assert Y[2] == pytest.approx(math.sqrt(3 / (4 * math.pi)), rel=1e-14)
+    Y = O.sh_basis(np.array([0, 1.0, 0]))
+    assert Y[1] == pytest.approx(-math.sqrt(3 / (4 * math.pi)), rel=1e-14)
+
+
+def test_sh_colour_offset_and_clamp():
+    scene = synth.make_scene(50, seed=16, layout="uniform", color="sh3", sh_std=1.0)
+    o = np.array([0.0, 0.0, -3.0], np.float32)
+    pre, _ = O.preprocess(scene, o)
+    for i in range(50):
+        d = scene["means"][:, i].astype(np.float64) - o
+        Y = O.sh_basis(d)
+        c = scene["color"][:, i].astype(np.float64).reshape(16, 3)
+        expect = np.maximum(Y @ c + 0.5, 0)
+        np.testing.assert_allclose(pre[i, 4:7], expect, atol=1e-13)
+    assert (pre[:, 4:7] == 0).any()
+
+
+# ----------------------------------------------------------------------------- Eq. 5 vs Eq. 9
+
+@pytest.mark.parametrize("a", [0.25, 0.5, 1.0])
+def test_moment_matching_against_uniform_footprint(a):
+    """Assumption 3 in isolation: for orthogonal equal half-edges of whitened length a and
+    q = 0, the exact average of the unit Gaussian over the square footprint is
+    (sqrt(2 pi) erf(a / sqrt 2) / (2 a))^2 and Eq. 9 gives 1 / (1 + a^2 / 3).  A far
+    isotropic Gaussian on the axis of a narrow pinhole realises this; the oracle's sub-ray
+    average approaches the erf value and its closed form the moment-matched one."""
+    f, t = 2000.0, 10.0
+    s = t * math.sin(math.atan(1 / (2 * f))) / a
+    cam = pinhole(65, 65, f, 32.5, 32.5, origin=(0.0, 0.0, 0.0))
+    scene = one_gaussian_scene((0.0, 0.0, t), (math.log(s),) * 3, logit=8.0)
+    s32 = math.exp(float(np.float32(math.log(s))))
+    a32 = t * math.sin(math.atan(1 / (2 * f))) / s32
+    rays, _ = O.pixel_rays(cam)
+    sig = sigmoid(np.float32(8.0))
+    closed = O.pair_batch(scene, 0, (0, 0, 0), rays[32, 32][None])[0, 0] / sig
+    assert closed == pytest.approx(1 / (1 + a32 ** 2 / 3), rel=1e-9)
+    k = 64
+    g = (np.arange(k) + 0.5) / k - 0.5
+    xs, ys = np.meshgrid(32.5 + g, 32.5 + g)
+    d, _ = O.unproject(cam, xs.ravel(), ys.ravel())
+    rr = np.concatenate([d, d, d], 1)
+    mc = O.pair_batch(scene, 0, (0, 0, 0), rr, O.Opts(filter_mode=0))[:, 0].mean() / sig
+    exact = (math.sqrt(2 * math.pi) * math.erf(a32 / math.sqrt(2)) / (2 * a32)) ** 2
+    assert mc == pytest.approx(exact, rel=2e-4)
+    # moment matching error is small and of the expected sign
+    assert closed >= exact
+
+
+def test_fig2_protocol_single_gaussian_error_ranking():
+    """Fig. 2 protocol: single-Gaussian response against a 32x32 supersampled pixel on a
+    wide fisheye.  In aggregate err(aniso) < err(iso) < err(centre), and on the sheared
+    periphery err(aniso) <= err(centre) / 5.  (With the Gaussian centred on the centre ray
+    the isotropic form can come out closer: both over-estimate the box average there and
+    the isotropic determinant is the larger; the ranking is a statement about pixels
+    spread over the Gaussian.)"""
+    rng = np.random.default_rng(7)
+    cam = synth.kb_camera(48, 48, 95.0, (0.0, 0.0, 0.0, 0.0), 24.0, np.eye(3), (0.0, 0.0, 0.0))
+    rays, valid = O.pixel_rays(cam)
+    k = 32
+    g = (np.arange(k) + 0.5) / k - 0.5
+    errs = {0: [], 1: [], 2: []}
+    periph = {0: [], 1: []}
+    n = 0
+    while n < 60:
+        j, i = rng.integers(0, 48, 2)
+        if not valid[j, i]:
+            continue
+        r = rays[j, i]
+        t = rng.uniform(1.0, 3.0)
+        foot = t * np.linalg.norm(r[3:6] - r[:3])
+        # a Gaussian comparable to the footprint, seen across its extent (the pixel lands
+        # on the Gaussian's flank as often as on its centre)
+        mu = t * r[:3] + rng.normal(0, 1.0 * foot, 3)
+        scene = one_gaussian_scene(mu, np.log(foot * rng.uniform(0.4, 1.2, 3)), quat=rng.normal(size=4), logit=3.0)
+        xs, ys = np.meshgrid(i + 0.5 + g, j + 0.5 + g)
+        d, v = O.unproject(cam, xs.ravel(), ys.ravel())
+        if not v.all():
+            continue
+        ref = O.pair_batch(scene, 0, (0, 0, 0), np.concatenate([d, d, d], 1), O.Opts(filter_mode=0, t_near=0))[:, 0].mean()
+        if ref < 0.02:
+            continue
+        n += 1
+        vals = {m: O.pair_batch(scene, 0, (0, 0, 0), r[None], O.Opts(filter_mode=m, t_near=0))[0, 0] for m in (0, 1, 2)}
+        for m in (0, 1, 2):
+            errs[m].append(abs(vals[m] - ref))
+        th = math.acos(np.clip(r[2], -1, 1))
+        if th > math.radians(60):
+            for m in (0, 1):
+                periph[m].append(abs(vals[m] - ref))
+    e = {m: np.mean(v) for m, v in errs.items()}
+    assert e[1] < e[2] < e[0]
+    assert len(periph[0]) >= 5
+    assert np.mean(periph[1]) <= np.mean(periph[0]) / 5
+
+
+@pytest.mark.slow
+def test_tiny_scene_against_64spp_supersampling():
+    """Multi-Gaussian occlusion check on the tiny configuration: the anisotropic render is
+    closer to the 8x8 stratified supersampled reference than the centre-ray render (by at
+    least 2x in RMSE) and than the isotropic one, and within 3e-3 RMSE."""
+    scene, cam = synth.tiny_config()
+    jit = synth.mc_jitter(8, seed=101)
+    ref = O.render_supersampled(scene, cam, jit)
+    rm = {}
+    for m in (0, 1, 2):
+        img = O.render(scene, cam, O.Opts(filter_mode=m))["rgba"]
+        rm[m] = math.sqrt(np.mean((img - ref) ** 2))
+    assert rm[1] <= 0.5 * rm[0]
+    assert rm[1] <= rm[2]
+    assert rm[1] <= 3e-3
+
+
+# ----------------------------------------------------------------------------- Eq. 11
+
+def test_rho2_bake_closed_form_and_min():
+    """Eq. 11 on the optical axis of a pinhole: half-edges of length t sin(atan(1/(2f))), so
+    rho^2 = t^2 sin^2(atan(1/(2f))) / 3; the minimum over views is taken; a Gaussian behind
+    every camera gets 0."""
+    f = 100.0
+    cam1 = pinhole(101, 101, f, 50.5, 50.5, origin=(0.0, 0.0, 0.0))
+    cam2 = pinhole(101, 101, f, 50.5, 50.5, origin=(0.0, 0.0, -2.0))
+    scene = synth.make_scene(2, seed=1)
+    scene["means"] = np.array([[0.0, 0.0], [0.0, 0.0], [4.0, -3.0]], np.float32)
+    r = O.bake_rho2(scene, [cam1, cam2])
+    a = math.sin(math.atan(1 / (2 * f)))
+    assert r[0] == pytest.approx(16 * a * a / 3, rel=1e-12)
+    assert r[1] == 0.0
+    r2 = O.bake_rho2(scene, [cam2])
+    assert r2[0] == pytest.approx(36 * a * a / 3, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------- culled mode
+
+def test_culled_mode_equals_brute_force():
+    """The oracle's lat-long culling drops only pairs below alpha_min: images are identical
+    (medium scene, wide fisheye, with the filter and the floor)."""
+    scene = synth.make_scene(3000, seed=17, layout="clusters", color="sh3", log_scale_mean=-3.0, log_scale_std=0.6)
+    scene["means"] *= 0.3
+    cams = synth.fisheye_cameras()
+    kb = synth.scale_camera(cams[0], 1 / 32)
+    eq = synth.scale_camera(cams[1], 1 / 32)
+    for cam in (kb, eq):
+        cam = dict(cam)
+        cam["origin"] = (0.0, -1.0, 0.3)
+        rho = O.bake_rho2(scene, [cam])
+        sc = dict(scene)
+        sc["rho2"] = rho.astype(np.float32)
+        for opts in (O.Opts(), O.Opts(use_floor=1), O.Opts(filter_mode=2)):
+            a = O.render(sc, cam, opts, mode="brute")
+            b = O.render(sc, cam, opts, mode="culled")
+            np.testing.assert_array_equal(a["rgba"], b["rgba"])
+            assert a["n_contrib"].sum() > 1000
+
+
+# ----------------------------------------------------------------------------- ambiguity
+
+def test_alternatives_only_where_flagged():
+    scene, cam = synth.tiny_config()
+    out = O.render(scene, cam, with_alt=True)
+    for f in range(O.N_ALT):
+        same = np.all(out["alt"][:, :, f] == out["rgba"], axis=-1)
+        assert np.all(same | (out["n_dec"] > f))
+
+
+# ----------------------------------------------------------------------------- gradients
+
+def test_oracle_gradient_matches_finite_differences():
+    """The oracle's gradient (exact compositing chain + per-pair Richardson differences)
+    against central differences of whole renders, in the smooth mode (no cut-offs)."""
+    scene = synth.make_scene(12, seed=18, layout="uniform", color="sh3", log_scale_mean=-2.2, log_scale_std=0.3)
+    scene["means"] *= 0.5
+    scene["rho2"] = np.full(12, 5e-4, np.float32)
+    cam = pinhole(16, 12, 10.0, origin=(0.0, 0.0, -3.0))
+    G = synth.seeded_image((12, 16, 4), seed=5)
+    opts = O.Opts.smooth(use_floor=1, t_near=0.2)
+    g = O.grad(scene, cam, G, opts)
+
+    def loss(sc):
+        return float(np.sum(O.render(sc, cam, opts)["rgba"] * G))
+
+    checks = [("means", (0, 3)), ("means", (2, 5)), ("log_scales", (1, 2)), ("quats", (0, 7)),
+              ("quats", (3, 1)), ("opacity_logits", (4,)), ("color", (0, 6)), ("color", (17, 9))]
+    for name, idx in checks:
+        h = 1e-3
+        sp = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in scene.items()}
+        sm = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in scene.items()}
+        # perturb in float64 then store: use the exactly representable step on the float32 value
+        x = np.float64(scene[name][idx])
+        xp, xm = np.float32(x + h), np.float32(x - h)
+        sp[name][idx] = xp
+        sm[name][idx] = xm
+        fd = (loss(sp) - loss(sm)) / (np.float64(xp) - np.float64(xm))
+        an = g[name][idx]
+        assert an == pytest.approx(fd, rel=2e-4, abs=1e-6), (name, idx, an, fd)
