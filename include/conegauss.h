@@ -1,0 +1,204 @@
+/*
+ * conegauss.h -- C ABI of the MI355X (gfx950) ConeGaussian renderer.
+ *
+ * Per-pixel anti-aliased Gaussian ray rendering for generic central cameras
+ * (ConeGaussian, arXiv 2609.13397).  A camera is its inverse mapping Pi^{-1} plus an
+ * optical centre (Sec. 3); every pixel is a bundle of rays (Sec. 4.1, Eq. 5) whose
+ * centre ray and two half-pixel edge rays define an anisotropic footprint covariance
+ * (Eq. 6, 8).  Each Gaussian's closed-form filtered response (Eq. 9), with the
+ * per-Gaussian frequency floor (Eq. 10) and marginal composition (Eq. 12), is
+ * alpha-composited front to back (Eq. 4).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless marked (host).  Floating point is float32.
+ *   - Arrays are component-major: a "[C][N]" array holds component c of item i at
+ *     index c*N + i, contiguous.
+ *   - The caller owns every input and output buffer.  Scratch memory is taken from
+ *     the cg_allocator passed in, or, when that is NULL, from the library's own
+ *     stream-ordered caching pool (device memory that stays cached until
+ *     cg_release_cached_memory is called).
+ *   - All device work is enqueued on `stream` and is asynchronous unless stated.
+ *   - Every call returns a cg_status and never throws; on failure cg_last_error()
+ *     gives a message (thread-local).  Arguments are validated on the host (sizes,
+ *     enums, camera intrinsics, crop windows, Kannala-Brandt monotonicity).  Values
+ *     inside device arrays are not scanned: NaN in gives NaN out.
+ *   - Calls are thread-safe when different threads use different streams.
+ */
+#ifndef CONEGAUSS_H
+#define CONEGAUSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CG_VERSION 1
+
+typedef enum {
+  CG_OK = 0,
+  CG_ERR_INVALID_ARG = -1,
+  CG_ERR_UNSUPPORTED = -2,
+  CG_ERR_OUT_OF_MEMORY = -3,
+  CG_ERR_HIP = -4,
+  CG_ERR_STATE = -5
+} cg_status;
+
+/* Camera models.  The paper names pinhole and fisheye cameras only (Sec. 5); the
+ * equations below are this library's readings.  Camera axes follow OpenCV (x right,
+ * y down, z forward); d_world = R_c2w d_cam.  For pinhole and fisheye,
+ * m = ((x - cx)/fx, (y - cy)/fy) with (x, y) continuous coordinates of the full image.
+ *   CG_PINHOLE:    d_cam = (m_x, m_y, 1) / |.|
+ *   CG_FISHEYE_KB: equidistant Kannala-Brandt, theta_d = |m| solves
+ *                  theta (1 + k1 theta^2 + k2 theta^4 + k3 theta^6 + k4 theta^8) = theta_d
+ *                  on [0, theta_max]; d_cam = (sin(theta) m / theta_d, cos(theta)).
+ *                  Pixels with theta_d beyond theta_d(theta_max) are invalid.
+ *   CG_EQUIRECT:   phi = 2 pi (x / full_w - 1/2), lambda = pi (1/2 - y / full_h),
+ *                  d_cam = (cos(lambda) sin(phi), -sin(lambda), cos(lambda) cos(phi)). */
+typedef enum { CG_PINHOLE = 0, CG_FISHEYE_KB = 1, CG_EQUIRECT = 2 } cg_camera_model;
+
+/* One view (host struct, passed by pointer, read during the call only).
+ * Pixel (i, j) of the crop window has centre (crop_x0 + i + 1/2, crop_y0 + j + 1/2)
+ * in the full virtual image of full_w x full_h pixels.  A zoomed view (the paper's
+ * scale convention, Sec. 5: calibration scaled with resolution) is a crop of a large
+ * virtual image.  The crop must lie inside the full image. */
+typedef struct {
+  int32_t model;                            /* cg_camera_model                          */
+  int32_t full_w, full_h;                   /* virtual image size                       */
+  int32_t crop_x0, crop_y0, crop_w, crop_h; /* rendered window                          */
+  float fx, fy, cx, cy;                     /* pixels (pinhole, fisheye); unused equirect */
+  float k[4];                               /* fisheye k1..k4; 0 otherwise              */
+  float R_c2w[9];                           /* row-major camera-to-world rotation       */
+  float origin[3];                          /* optical centre o (world)                 */
+  float theta_max;                          /* fisheye valid half field of view (rad)   */
+} cg_camera;
+
+/* Gaussians (Sec. 3): raw parameters, SoA [C][n] float32 device arrays.
+ *   means [3][n]; log_scales [3][n] (s = exp); quats [4][n] (w, x, y, z; normalised
+ *   inside); opacity_logits [n] (sigma = sigmoid); color: color_mode 0 -> rgb [3][n],
+ *   color_mode 3 -> degree-3 real SH [48][n] with index 3*coef + channel, coefficients
+ *   in (l, m) order, m = -l..l, Condon-Shortley phase; colour = max(sum + 1/2, 0);
+ *   rho2 [n] floor variance of Eq. 10 (NULL = 0). */
+typedef struct {
+  int64_t n;
+  int32_t color_mode;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* color;
+  const float* rho2;
+} cg_gaussians;
+
+enum { CG_FILTER_CENTER_RAY = 0, CG_FILTER_ANISOTROPIC = 1, CG_FILTER_ISOTROPIC = 2 };
+enum { CG_COMPOSE_MARGINAL = 0, CG_COMPOSE_ADDITIVE = 1 };
+
+/* Render options.  cg_default_opts fills the defaults given in brackets.
+ *   filter_mode     CG_FILTER_* [ANISOTROPIC]: centre ray = Eq. 3 with C = 1;
+ *                   anisotropic = Eq. 9; isotropic = Eq. 9 with the footprint replaced
+ *                   by the in-plane isotropic covariance of equal trace.
+ *   use_floor       [0] apply Eq. 10 with rho2; the render footprint is then composed
+ *                   with the floor by `composition`.
+ *   composition     CG_COMPOSE_* [MARGINAL]: Eq. 12, or the plain sum (ablation).
+ *   alpha_min       [1/255] pairs with alpha = min(T, alpha_max) below it are skipped.
+ *   alpha_max       [0.99]
+ *   T_min           [1e-4]  a pixel stops before the pair that would take its
+ *                   transmittance below T_min.
+ *   t_near          [0.2]   pairs with max-response depth t* <= t_near give T = 0.
+ *   bg[3]           [0]     background, added as T_final * bg.
+ *   footprint_scale [1]     multiplies the neighbour-ray differentials (0 = centre ray). */
+typedef struct {
+  int32_t filter_mode;
+  int32_t use_floor;
+  int32_t composition;
+  float alpha_min, alpha_max, T_min, t_near;
+  float bg[3];
+  float footprint_scale;
+} cg_render_opts;
+
+/* Scratch allocator.  alloc returns device memory usable in stream order on `stream`
+ * (NULL on failure -> CG_ERR_OUT_OF_MEMORY); free releases it in stream order. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, hipStream_t stream);
+  void (*free)(void* ctx, void* ptr, hipStream_t stream);
+} cg_allocator;
+
+/* Opaque forward state kept for cg_render_backward (the sorted per-tile lists, the
+ * per-view Gaussian records and the per-pixel stopping points).  It refers to the
+ * Gaussian arrays passed to cg_render_forward, which must stay alive and unchanged
+ * until the backward call.  Owned by the caller; release with cg_fwd_state_release. */
+typedef struct cg_fwd_state cg_fwd_state;
+
+/* Counters of one forward call (host struct). */
+typedef struct {
+  int64_t n_pairs;          /* (tile, Gaussian) pairs after binning                  */
+  int64_t n_tiles;          /* tiles over all views                                  */
+  int64_t n_pixels;         /* pixels over all views                                 */
+  int64_t n_gaussian_views; /* n * n_views                                           */
+  int32_t sort_bits;        /* radix-sort key width                                  */
+  int32_t reserved;
+} cg_fwd_stats;
+
+int cg_version(void);
+const char* cg_last_error(void);
+void cg_default_opts(cg_render_opts* opts /* host */);
+
+/* Forward render of n_views views of one set of Gaussians (Eq. 4-12).
+ *   cams       host array [n_views].
+ *   out_rgba   device [sum_v crop_h_v * crop_w_v][4], view-major, row-major within a
+ *              view: premultiplied RGB plus the background term, and alpha = 1 - T_final.
+ *   state_out  NULL for inference; otherwise receives a state for cg_render_backward.
+ *   stats_out  host, may be NULL.
+ * The call synchronises `stream` once, to read back the number of pairs. */
+cg_status cg_render_forward(const cg_gaussians* g /* host struct, device arrays */, const cg_camera* cams,
+                            int32_t n_views, const cg_render_opts* opts /* host */, const cg_allocator* alloc,
+                            float* out_rgba, cg_fwd_state** state_out, cg_fwd_stats* stats_out,
+                            hipStream_t stream);
+
+/* Gradients of L = sum(grad_rgba * out_rgba) with respect to the raw Gaussian
+ * parameters of the forward call that produced `st` (summed over its views).  The
+ * outputs have the shapes of the inputs and are OVERWRITTEN; rho2 gets no gradient.
+ * Pairs are reduced per tile and then per Gaussian without atomics, so the result is
+ * deterministic.  grad_rgba has the layout of out_rgba. */
+cg_status cg_render_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, float* d_log_scales,
+                             float* d_quats, float* d_opacity_logits, float* d_color, hipStream_t stream);
+
+void cg_fwd_state_release(cg_fwd_state* st);
+
+/* Inverse mapping Pi^{-1} (Sec. 3) of n continuous full-image pixel coordinates.
+ *   pix_xy [2][n] device; dirs [3][n] unit world directions (0 where invalid);
+ *   valid [n] 1/0. */
+cg_status cg_camera_unproject(const cg_camera* cam /* host */, int64_t n, const float* pix_xy, float* dirs,
+                              uint8_t* valid, hipStream_t stream);
+
+/* Per-Gaussian floor variance of Eq. 11: the minimum over the views in which a
+ * Gaussian is visible of half the trace of the world-space footprint covariance at
+ * the pixel its mean projects to (half-pixel neighbour rays from Pi^{-1}, projected
+ * orthogonally to the ray through the mean, at the mean's distance).  Visible: the
+ * projection is valid and inside the full image, and the distance exceeds t_near.
+ * A Gaussian visible in no view gets 0.  rho2_out [n] device. */
+cg_status cg_bake_rho2(const cg_gaussians* g /* host struct, device arrays */, const cg_camera* cams /* host */,
+                       int32_t n_views, float t_near, float* rho2_out, hipStream_t stream);
+
+/* Per-stage GPU timing.  When enabled, every kernel launch of the library is
+ * bracketed with HIP events on its stream.  cg_profile_collect synchronises on the
+ * recorded events and adds their durations to per-stage totals; cg_profile_read
+ * copies the totals (host arrays of length cg_profile_num_stages()) and resets them. */
+int cg_profile_num_stages(void);
+const char* cg_profile_stage_name(int stage);
+void cg_profile_enable(int on);
+cg_status cg_profile_collect(void);
+void cg_profile_read(double* total_ms /* host */, int64_t* launches /* host */);
+
+/* Returns the library's cached scratch memory to the device. */
+cg_status cg_release_cached_memory(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONEGAUSS_H */

@@ -1,0 +1,157 @@
+// Camera kernels: Pi^{-1} for a list of coordinates, and the per-tile / per-group
+// ray cones used by the angular binning (camera-agnostic: only unit ray directions
+// are compared, so the same code serves fields of view beyond 180 degrees).
+#include "camera_dev.hpp"
+
+namespace cg {
+
+__global__ void k_unproject(const DevCamera* cam, int64_t n, const float* __restrict__ pix_xy,
+                            float* __restrict__ dirs, uint8_t* __restrict__ valid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d[3];
+  const bool ok = cam_unproject(*cam, (double)pix_xy[i], (double)pix_xy[n + i], d);
+  for (int k = 0; k < 3; ++k) dirs[k * n + i] = ok ? (float)d[k] : 0.f;
+  valid[i] = ok ? 1 : 0;
+}
+
+hipError_t launch_unproject(const DevCamera* cam, int64_t n, const float* pix_xy, float* dirs, uint8_t* valid,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  k_unproject<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(cam, n, pix_xy, dirs, valid);
+  return hipGetLastError();
+}
+
+// Block-wide reductions over 256 threads (4 waves) through LDS.
+__device__ __forceinline__ float block_sum(float v, float* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  const float r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ float block_max(float v, float* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  const float r = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per 16x16 tile: the cone around the tile's pixel-centre rays (axis =
+// normalised mean direction, half-angle = largest angle to a pixel ray plus a small
+// margin) and the tile's largest footprint coefficient (|d_x-d|^2 + |d_y-d|^2) / 3,
+// whose per-view maximum bounds every pixel's footprint in the Gaussian cones.
+__global__ __launch_bounds__(256) void k_tile_cones(const DevCamera* __restrict__ cams, int n_views, float fs,
+                                                    TileCone* __restrict__ tiles, float* __restrict__ view_cmax) {
+  __shared__ float sh[4];
+  const int t = blockIdx.x;
+  const int v = view_of_tile(cams, n_views, t);
+  const DevCamera& c = cams[v];
+  const int lt = t - c.tile_offset;
+  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
+  const int i = tx * kTile + (threadIdx.x & (kTile - 1));
+  const int j = ty * kTile + (threadIdx.x / kTile);
+  PixelRay r;
+  r.valid = false;
+  if (i < c.crop_w && j < c.crop_h) r = pixel_ray(c, i, j, fs);
+  const float w = r.valid ? 1.f : 0.f;
+  const float sx = block_sum(r.valid ? r.df[0] : 0.f, sh);
+  const float sy = block_sum(r.valid ? r.df[1] : 0.f, sh);
+  const float sz = block_sum(r.valid ? r.df[2] : 0.f, sh);
+  const float cnt = block_sum(w, sh);
+  const float cm = block_max(r.valid ? r.cpix : 0.f, sh);
+  TileCone tc;
+  if (cnt == 0.f) {
+    tc = TileCone{0.f, 0.f, 1.f, -1.f, 0.f, 1.f, 0.f, 0.f};
+  } else {
+    const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
+    const float ax = sx / nrm, ay = sy / nrm, az = sz / nrm;
+    float ang = 0.f;
+    if (r.valid) {
+      const float dx = ax - r.df[0], dy = ay - r.df[1], dz = az - r.df[2];
+      ang = 2.f * asinf(fminf(1.f, 0.5f * sqrtf(dx * dx + dy * dy + dz * dz)));
+    }
+    float beta = block_max(ang, sh) * 1.0001f + 2e-6f;
+    if (nrm < 0.5f * cnt) beta = kPiF;  // rays spread too widely for a mean axis
+    tc = TileCone{ax, ay, az, beta, sinf(0.5f * beta), cosf(0.5f * beta), cm, 0.f};
+  }
+  if (threadIdx.x == 0) {
+    tiles[t] = tc;
+    // positive floats order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned int*>(&view_cmax[v]), __float_as_uint(cm));
+  }
+}
+
+hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles, float fs, TileCone* tiles,
+                             float* view_cmax, hipStream_t s) {
+  if (total_tiles == 0) return hipSuccess;
+  k_tile_cones<<<dim3(total_tiles), dim3(256), 0, s>>>(cams, n_views, fs, tiles, view_cmax);
+  return hipGetLastError();
+}
+
+// One wave per 8x8 group of tiles: a cone containing every member tile's cone.
+__global__ __launch_bounds__(64) void k_group_cones(const DevCamera* __restrict__ cams, int n_views,
+                                                   const TileCone* __restrict__ tiles, TileCone* __restrict__ groups) {
+  const int g = blockIdx.x;
+  const int v = view_of_group(cams, n_views, g);
+  const DevCamera& c = cams[v];
+  const int lg = g - c.group_offset;
+  const int gx = lg % c.groups_x, gy = lg / c.groups_x;
+  const int tx = gx * kGroup + (threadIdx.x % kGroup), ty = gy * kGroup + (threadIdx.x / kGroup);
+  TileCone tc{0.f, 0.f, 1.f, -1.f, 0.f, 1.f, 0.f, 0.f};
+  if (tx < c.tiles_x && ty < c.tiles_y) tc = tiles[c.tile_offset + ty * c.tiles_x + tx];
+  const bool live = tc.beta >= 0.f;
+  float sx = live ? tc.ax : 0.f, sy = live ? tc.ay : 0.f, sz = live ? tc.az : 0.f, cnt = live ? 1.f : 0.f;
+  float bmax = live ? tc.beta : -1.f;
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+    sz += __shfl_xor(sz, o);
+    cnt += __shfl_xor(cnt, o);
+    bmax = fmaxf(bmax, __shfl_xor(bmax, o));
+  }
+  TileCone out{0.f, 0.f, 1.f, -1.f, 0.f, 1.f, 0.f, 0.f};
+  if (cnt > 0.f) {
+    const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
+    const float ax = sx / nrm, ay = sy / nrm, az = sz / nrm;
+    float ang = -1.f;
+    if (live) {
+      const float dx = ax - tc.ax, dy = ay - tc.ay, dz = az - tc.az;
+      ang = 2.f * asinf(fminf(1.f, 0.5f * sqrtf(dx * dx + dy * dy + dz * dz))) + tc.beta;
+    }
+    for (int o = 32; o > 0; o >>= 1) ang = fmaxf(ang, __shfl_xor(ang, o));
+    float beta = ang * 1.0001f + 2e-6f;
+    if (bmax >= kPiF || nrm < 0.5f * cnt) beta = kPiF;
+    out = TileCone{ax, ay, az, beta, sinf(0.5f * beta), cosf(0.5f * beta), 0.f, 0.f};
+  }
+  if (threadIdx.x == 0) groups[g] = out;
+}
+
+hipError_t launch_group_cones(const DevCamera* cams, int n_views, int total_groups, const TileCone* tiles,
+                              TileCone* groups, hipStream_t s) {
+  if (total_groups == 0) return hipSuccess;
+  k_group_cones<<<dim3(total_groups), dim3(64), 0, s>>>(cams, n_views, tiles, groups);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fill_u32<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace cg

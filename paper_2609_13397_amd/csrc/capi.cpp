@@ -1,0 +1,401 @@
+// The C ABI: argument validation, camera set-up and the orchestration of the
+// forward pipeline
+//   tile cones -> group cones -> preprocess -> bin count -> scan -> (read back P)
+//   -> bin emit -> radix sort on (tile, depth) -> tile ranges -> tile render.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fwd_state.hpp"
+
+using namespace cg;
+
+namespace {
+
+double kb_poly(const cg_camera& c, double th) {
+  const double t2 = th * th;
+  return th * (1.0 + t2 * (c.k[0] + t2 * (c.k[1] + t2 * (c.k[2] + t2 * c.k[3]))));
+}
+
+void check_camera(const cg_camera& c, int idx) {
+  const std::string w = "camera " + std::to_string(idx) + ": ";
+  CG_CHECK_ARG(c.model == CG_PINHOLE || c.model == CG_FISHEYE_KB || c.model == CG_EQUIRECT, w + "unknown model");
+  CG_CHECK_ARG(c.full_w > 0 && c.full_h > 0, w + "full image size must be positive");
+  CG_CHECK_ARG(c.crop_w >= 0 && c.crop_h >= 0 && c.crop_x0 >= 0 && c.crop_y0 >= 0 &&
+                   (int64_t)c.crop_x0 + c.crop_w <= c.full_w && (int64_t)c.crop_y0 + c.crop_h <= c.full_h,
+               w + "crop window outside the image");
+  for (int k = 0; k < 9; ++k) CG_CHECK_ARG(std::isfinite(c.R_c2w[k]), w + "non-finite rotation");
+  for (int k = 0; k < 3; ++k) CG_CHECK_ARG(std::isfinite(c.origin[k]), w + "non-finite origin");
+  if (c.model != CG_EQUIRECT) {
+    CG_CHECK_ARG(std::isfinite(c.fx) && std::isfinite(c.fy) && c.fx > 0 && c.fy > 0, w + "focal lengths must be > 0");
+    CG_CHECK_ARG(std::isfinite(c.cx) && std::isfinite(c.cy), w + "non-finite principal point");
+  }
+  if (c.model == CG_FISHEYE_KB) {
+    CG_CHECK_ARG(c.theta_max > 0 && c.theta_max <= 3.14159265f, w + "theta_max must be in (0, pi]");
+    for (int k = 0; k < 4; ++k) CG_CHECK_ARG(std::isfinite(c.k[k]), w + "non-finite distortion");
+    // theta_d must increase on [0, theta_max] for the inverse to exist
+    const int steps = 4096;
+    double prev = 0.0;
+    for (int s = 1; s <= steps; ++s) {
+      const double th = c.theta_max * s / steps;
+      const double v = kb_poly(c, th);
+      CG_CHECK_ARG(v > prev, w + "Kannala-Brandt polynomial is not increasing on [0, theta_max]");
+      prev = v;
+    }
+  }
+  // rotation must be invertible
+  const float* R = c.R_c2w;
+  const double det = (double)R[0] * ((double)R[4] * R[8] - (double)R[5] * R[7]) -
+                     (double)R[1] * ((double)R[3] * R[8] - (double)R[5] * R[6]) +
+                     (double)R[2] * ((double)R[3] * R[7] - (double)R[4] * R[6]);
+  CG_CHECK_ARG(std::fabs(det) > 1e-3, w + "rotation is singular");
+}
+
+void inv3(const double* A, double* I) {
+  const double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                   A[2] * (A[3] * A[7] - A[4] * A[6]);
+  I[0] = (A[4] * A[8] - A[5] * A[7]) / d;
+  I[1] = (A[2] * A[7] - A[1] * A[8]) / d;
+  I[2] = (A[1] * A[5] - A[2] * A[4]) / d;
+  I[3] = (A[5] * A[6] - A[3] * A[8]) / d;
+  I[4] = (A[0] * A[8] - A[2] * A[6]) / d;
+  I[5] = (A[2] * A[3] - A[0] * A[5]) / d;
+  I[6] = (A[3] * A[7] - A[4] * A[6]) / d;
+  I[7] = (A[1] * A[6] - A[0] * A[7]) / d;
+  I[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+}
+
+DevCamera make_dev_camera(const cg_camera& c) {
+  DevCamera d;
+  std::memset(&d, 0, sizeof(d));
+  d.model = c.model;
+  d.full_w = c.full_w;
+  d.full_h = c.full_h;
+  d.crop_x0 = c.crop_x0;
+  d.crop_y0 = c.crop_y0;
+  d.crop_w = c.crop_w;
+  d.crop_h = c.crop_h;
+  d.tiles_x = (c.crop_w + kTile - 1) / kTile;
+  d.tiles_y = (c.crop_h + kTile - 1) / kTile;
+  d.groups_x = (d.tiles_x + kGroup - 1) / kGroup;
+  d.groups_y = (d.tiles_y + kGroup - 1) / kGroup;
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  d.inv_fx = c.model == CG_EQUIRECT ? 0.0 : 1.0 / (double)c.fx;
+  d.inv_fy = c.model == CG_EQUIRECT ? 0.0 : 1.0 / (double)c.fy;
+  d.inv_w = 1.0 / (double)c.full_w;
+  d.inv_h = 1.0 / (double)c.full_h;
+  for (int k = 0; k < 4; ++k) d.k[k] = c.k[k];
+  for (int k = 0; k < 9; ++k) d.R[k] = c.R_c2w[k];
+  inv3(d.R, d.Rinv);
+  for (int k = 0; k < 3; ++k) {
+    d.o[k] = c.origin[k];
+    d.of[k] = c.origin[k];
+  }
+  d.theta_max = c.theta_max;
+  d.thd_max = c.model == CG_FISHEYE_KB ? kb_poly(c, (double)c.theta_max) : 0.0;
+  return d;
+}
+
+Opts make_opts(const cg_render_opts& o) {
+  CG_CHECK_ARG(o.filter_mode >= 0 && o.filter_mode <= 2, "filter_mode must be 0, 1 or 2");
+  CG_CHECK_ARG(o.composition == CG_COMPOSE_MARGINAL || o.composition == CG_COMPOSE_ADDITIVE,
+               "composition must be 0 or 1");
+  CG_CHECK_ARG(std::isfinite(o.alpha_min) && std::isfinite(o.alpha_max) && o.alpha_min > 0.f &&
+                   o.alpha_min < o.alpha_max && o.alpha_max <= 1.f,
+               "need 0 < alpha_min < alpha_max <= 1");
+  CG_CHECK_ARG(std::isfinite(o.T_min) && o.T_min >= 0.f && o.T_min < 1.f, "T_min must be in [0, 1)");
+  CG_CHECK_ARG(std::isfinite(o.t_near) && o.t_near >= 0.f, "t_near must be >= 0");
+  CG_CHECK_ARG(std::isfinite(o.footprint_scale) && o.footprint_scale >= 0.f, "footprint_scale must be >= 0");
+  Opts r;
+  r.filter_mode = o.filter_mode;
+  r.use_floor = o.use_floor ? 1 : 0;
+  r.composition = o.composition;
+  r.alpha_min = o.alpha_min;
+  r.alpha_max = o.alpha_max;
+  r.T_min = o.T_min;
+  r.t_near = o.t_near;
+  for (int k = 0; k < 3; ++k) r.bg[k] = o.bg[k];
+  r.fs = o.footprint_scale;
+  return r;
+}
+
+GaussPtrs make_gauss(const cg_gaussians& g) {
+  CG_CHECK_ARG(g.n >= 0, "negative Gaussian count");
+  CG_CHECK_ARG(g.color_mode == 0 || g.color_mode == 3, "color_mode must be 0 (rgb) or 3 (SH degree 3)");
+  if (g.n > 0)
+    CG_CHECK_ARG(g.means && g.log_scales && g.quats && g.opacity_logits && g.color,
+                 "null Gaussian parameter pointer");
+  GaussPtrs p;
+  p.n = g.n;
+  p.color_mode = g.color_mode;
+  p.means = g.means;
+  p.log_scales = g.log_scales;
+  p.quats = g.quats;
+  p.logits = g.opacity_logits;
+  p.color = g.color;
+  p.rho2 = g.rho2;
+  return p;
+}
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while (b < 63 && (int64_t(1) << b) <= v) ++b;
+  return b;
+}
+
+template <class F>
+cg_status guarded(F&& f) {
+  try {
+    f();
+    return CG_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host out of memory");
+    return CG_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return CG_ERR_STATE;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- forward
+
+namespace cg {
+
+void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, const cg_render_opts* opts_in,
+                 const cg_allocator* alloc, float* out_rgba, cg_fwd_state** state_out, cg_fwd_stats* stats,
+                 hipStream_t s) {
+  CG_CHECK_ARG(g_in && cams && opts_in, "null argument");
+  CG_CHECK_ARG(n_views >= 1 && n_views <= 4096, "n_views must be in [1, 4096]");
+  const GaussPtrs g = make_gauss(*g_in);
+  const Opts o = make_opts(*opts_in);
+  std::vector<DevCamera> hc(n_views);
+  int64_t total_tiles = 0, total_groups = 0, total_px = 0;
+  for (int v = 0; v < n_views; ++v) {
+    check_camera(cams[v], v);
+    hc[v] = make_dev_camera(cams[v]);
+    hc[v].tile_offset = (int32_t)total_tiles;
+    hc[v].group_offset = (int32_t)total_groups;
+    hc[v].px_offset = total_px;
+    CG_CHECK_ARG((int64_t)hc[v].groups_x * hc[v].groups_y <= 65535, "view too large (more than 65535 tile groups)");
+    total_tiles += (int64_t)hc[v].tiles_x * hc[v].tiles_y;
+    total_groups += (int64_t)hc[v].groups_x * hc[v].groups_y;
+    total_px += (int64_t)cams[v].crop_w * cams[v].crop_h;
+  }
+  CG_CHECK_ARG(total_tiles < (int64_t(1) << 31) / 8 - 8, "too many tiles");
+  CG_CHECK_ARG(total_px == 0 || out_rgba, "null out_rgba");
+  const int64_t n = g.n;
+  const int64_t nv = n * n_views;
+  CG_CHECK_ARG(nv < (int64_t(1) << 31), "n * n_views must be below 2^31");
+
+  Scratch sc(alloc, s);
+  cg_fwd_state* st = nullptr;
+  if (state_out) {
+    st = new cg_fwd_state();
+    st->alloc = sc.allocator();
+    st->stream = s;
+  }
+  try {
+    DevCamera* dcams = sc.get_n<DevCamera>(n_views);
+    CG_HIP(hipMemcpyAsync(dcams, hc.data(), sizeof(DevCamera) * n_views, hipMemcpyHostToDevice, s));
+    TileCone* tiles = sc.get_n<TileCone>(total_tiles);
+    TileCone* groups = sc.get_n<TileCone>(total_groups);
+    float* view_cmax = sc.get_n<float>(n_views);
+    Record* rec = sc.get_n<Record>(std::max<int64_t>(nv, 1));
+    uint32_t* depth_key = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
+    float4* cone = sc.get_n<float4>(std::max<int64_t>(nv, 1));
+    uint32_t* counts = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
+    uint32_t* offsets = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
+    void* scan_tmp = sc.get(scan_temp_bytes(nv));
+
+    {
+      ProfScope ps(ST_CAMERA, s);
+      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(view_cmax), 0u, n_views, s));
+      CG_HIP(launch_tile_cones(dcams, n_views, (int)total_tiles, o.fs, tiles, view_cmax, s));
+      CG_HIP(launch_group_cones(dcams, n_views, (int)total_groups, tiles, groups, s));
+    }
+    {
+      ProfScope ps(ST_PREPROCESS, s);
+      CG_HIP(launch_preprocess(g, dcams, n_views, view_cmax, o, rec, depth_key, cone, s));
+    }
+    {
+      ProfScope ps(ST_BIN_COUNT, s);
+      CG_HIP(launch_bin_count(n, n_views, dcams, cone, tiles, groups, counts, s));
+    }
+    uint32_t host_last[2] = {0, 0};
+    if (nv > 0) {
+      {
+        ProfScope ps(ST_SCAN, s);
+        CG_HIP(launch_exclusive_scan(counts, offsets, nv, scan_tmp, s));
+      }
+      CG_HIP(hipMemcpyAsync(&host_last[0], offsets + (nv - 1), 4, hipMemcpyDeviceToHost, s));
+      CG_HIP(hipMemcpyAsync(&host_last[1], counts + (nv - 1), 4, hipMemcpyDeviceToHost, s));
+    }
+    CG_HIP(hipStreamSynchronize(s));
+    const uint64_t P64 = (uint64_t)host_last[0] + host_last[1];
+    CG_CHECK_ARG(P64 < 0xF0000000ull, "too many (tile, Gaussian) pairs for 32-bit indices");
+    const int64_t P = (int64_t)P64;
+
+    uint64_t* keys = sc.get_n<uint64_t>(std::max<int64_t>(P, 1));
+    uint32_t* slots = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint64_t* keys_alt = sc.get_n<uint64_t>(std::max<int64_t>(P, 1));
+    uint32_t* slots_alt = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint32_t* slot_gid = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint32_t* sorted_gid = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint2* ranges = sc.get_n<uint2>(std::max<int64_t>(total_tiles, 1));
+    void* sort_tmp = sc.get(radix_temp_bytes(P));
+    float* final_T = st ? sc.get_n<float>(std::max<int64_t>(total_px, 1)) : nullptr;
+    uint32_t* n_last = st ? sc.get_n<uint32_t>(std::max<int64_t>(total_px, 1)) : nullptr;
+
+    const int tile_bits = bits_for(std::max<int64_t>(total_tiles - 1, 1));
+    const int end_bit = 31 + tile_bits;
+    int in_alt = 0;
+    if (P > 0) {
+      {
+        ProfScope ps(ST_BIN_EMIT, s);
+        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, tiles, groups, offsets, depth_key, keys, slots, slot_gid, s));
+      }
+      {
+        ProfScope ps(ST_SORT, s);
+        CG_HIP(launch_radix_sort(keys, slots, keys_alt, slots_alt, P, end_bit, sort_tmp, &in_alt, s));
+      }
+    }
+    uint64_t* skeys = in_alt ? keys_alt : keys;
+    uint32_t* sslots = in_alt ? slots_alt : slots;
+    {
+      ProfScope ps(ST_RANGES, s);
+      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
+      CG_HIP(launch_tile_ranges(skeys, sslots, slot_gid, P, 31, ranges, sorted_gid, s));
+    }
+    {
+      ProfScope ps(ST_RENDER, s);
+      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sorted_gid, out_rgba, final_T,
+                               n_last, s));
+    }
+    if (stats) {
+      stats->n_pairs = P;
+      stats->n_tiles = total_tiles;
+      stats->n_pixels = total_px;
+      stats->n_gaussian_views = nv;
+      stats->sort_bits = end_bit;
+      stats->reserved = 0;
+    }
+    if (st) {
+      st->g = g;
+      st->opts = o;
+      st->n_views = n_views;
+      st->hcams = hc;
+      st->dcams = dcams;
+      st->total_tiles = total_tiles;
+      st->total_px = total_px;
+      st->P = P;
+      st->rec = rec;
+      st->counts = counts;
+      st->offsets = offsets;
+      st->sorted_slots = sslots;
+      st->sorted_gid = sorted_gid;
+      st->ranges = ranges;
+      st->final_T = final_T;
+      st->n_last = n_last;
+      st->out_rgba = out_rgba;
+      sc.transfer(st->blocks);
+      *state_out = st;
+    }
+  } catch (...) {
+    if (st) {
+      sc.transfer(st->blocks);
+      cg_fwd_state_release(st);
+    }
+    throw;
+  }
+}
+
+}  // namespace cg
+
+// ---------------------------------------------------------------------------- C entry points
+
+extern "C" {
+
+int cg_version(void) { return CG_VERSION; }
+
+void cg_default_opts(cg_render_opts* o) {
+  if (!o) return;
+  o->filter_mode = CG_FILTER_ANISOTROPIC;
+  o->use_floor = 0;
+  o->composition = CG_COMPOSE_MARGINAL;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->T_min = 1e-4f;
+  o->t_near = 0.2f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.f;
+  o->footprint_scale = 1.f;
+}
+
+cg_status cg_render_forward(const cg_gaussians* g, const cg_camera* cams, int32_t n_views,
+                            const cg_render_opts* opts, const cg_allocator* alloc, float* out_rgba,
+                            cg_fwd_state** state_out, cg_fwd_stats* stats_out, hipStream_t stream) {
+  if (state_out) *state_out = nullptr;
+  return guarded([&] { run_forward(g, cams, n_views, opts, alloc, out_rgba, state_out, stats_out, stream); });
+}
+
+void cg_fwd_state_release(cg_fwd_state* st) {
+  if (!st) return;
+  for (void* p : st->blocks) free_block(st->alloc, p, st->stream);
+  delete st;
+}
+
+cg_status cg_camera_unproject(const cg_camera* cam, int64_t n, const float* pix_xy, float* dirs, uint8_t* valid,
+                              hipStream_t stream) {
+  return guarded([&] {
+    CG_CHECK_ARG(cam, "null camera");
+    CG_CHECK_ARG(n >= 0, "negative count");
+    check_camera(*cam, 0);
+    if (n == 0) return;
+    CG_CHECK_ARG(pix_xy && dirs && valid, "null array");
+    const DevCamera hc = make_dev_camera(*cam);
+    Scratch sc(nullptr, stream);
+    DevCamera* dc = sc.get_n<DevCamera>(1);
+    CG_HIP(hipMemcpyAsync(dc, &hc, sizeof(hc), hipMemcpyHostToDevice, stream));
+    {
+      ProfScope ps(ST_CAMERA, stream);
+      CG_HIP(launch_unproject(dc, n, pix_xy, dirs, valid, stream));
+    }
+    // keep the host copy alive until the upload has happened
+    CG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+cg_status cg_bake_rho2(const cg_gaussians* g, const cg_camera* cams, int32_t n_views, float t_near, float* rho2_out,
+                       hipStream_t stream) {
+  return guarded([&] {
+    CG_CHECK_ARG(g && cams, "null argument");
+    CG_CHECK_ARG(n_views >= 1, "need at least one view");
+    CG_CHECK_ARG(std::isfinite(t_near) && t_near >= 0.f, "t_near must be >= 0");
+    const GaussPtrs gp = make_gauss(*g);
+    if (gp.n == 0) return;
+    CG_CHECK_ARG(rho2_out, "null output");
+    std::vector<DevCamera> hc(n_views);
+    for (int v = 0; v < n_views; ++v) {
+      check_camera(cams[v], v);
+      hc[v] = make_dev_camera(cams[v]);
+    }
+    Scratch sc(nullptr, stream);
+    DevCamera* dc = sc.get_n<DevCamera>(n_views);
+    CG_HIP(hipMemcpyAsync(dc, hc.data(), sizeof(DevCamera) * n_views, hipMemcpyHostToDevice, stream));
+    {
+      ProfScope ps(ST_BAKE, stream);
+      CG_HIP(launch_bake_rho2(gp, dc, n_views, t_near, rho2_out, stream));
+    }
+    CG_HIP(hipStreamSynchronize(stream));
+  });
+}
+
+}  // extern "C"

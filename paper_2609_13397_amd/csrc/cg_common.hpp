@@ -1,0 +1,129 @@
+// Shared declarations of the ConeGaussian HIP library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "conegauss.h"
+
+namespace cg {
+
+constexpr int kTile = 16;             // tile edge in pixels (one workgroup of 256 threads)
+constexpr int kTilePx = kTile * kTile;
+constexpr int kGroup = 8;             // tile group edge in tiles (64 tiles = one wave64)
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr double kPi = 3.14159265358979323846;
+
+// Device-side copy of a cg_camera, with the derived quantities the kernels need.
+// Ray arithmetic is FP64 (see the ray section of camera_dev.hpp), so the intrinsics
+// are kept in double.
+struct DevCamera {
+  int32_t model, full_w, full_h, crop_x0, crop_y0, crop_w, crop_h;
+  int32_t tiles_x, tiles_y, groups_x, groups_y;
+  int32_t tile_offset;   // first global tile index of this view
+  int32_t group_offset;  // first global group index of this view
+  int32_t pad0;
+  int64_t px_offset;     // first output pixel of this view
+  double fx, fy, cx, cy, inv_fx, inv_fy, inv_w, inv_h;
+  double k[4];
+  double R[9];           // row-major camera-to-world
+  double Rinv[9];        // inverse of R (world-to-camera)
+  double o[3];
+  double theta_max, thd_max;
+  float of[3];           // origin as given (float32), for the float32 depth key
+  float pad1;
+};
+
+// Bounding cone of the pixel-centre rays of a tile or tile group: unit axis, half
+// angle beta (< 0: empty; >= pi: everything) and sin/cos of beta/2.
+struct TileCone {
+  float ax, ay, az, beta;
+  float sb, cb, cmax, pad;
+};
+
+// Per (view, Gaussian) record read by the render kernels (96 bytes, 16-byte aligned).
+struct alignas(16) Record {
+  float W[9];      // whitening diag(1/s') R^T, row-major
+  float mu[3];     // mean
+  float sigma;     // effective opacity sigma_eff (Eq. 10)
+  float rgb[3];    // view-dependent colour
+  float sp2[3];    // s'^2 (floored squared scales)
+  float rho2;      // floor variance (0 when the floor is off)
+  float Lg;        // 2 ln(sigma_eff / alpha_min): cull bound of the pre-rejection
+  float kg;        // 1 / min(s'^2)
+  float pad[2];
+};
+static_assert(sizeof(Record) == 96, "Record layout");
+
+struct Opts {
+  int filter_mode, use_floor, composition;
+  float alpha_min, alpha_max, T_min, t_near;
+  float bg[3];
+  float fs;  // footprint scale
+};
+
+struct GaussPtrs {
+  int64_t n;
+  int color_mode;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* logits;
+  const float* color;
+  const float* rho2;
+};
+
+// ---------------------------------------------------------------- host-side launch API
+// (each wraps kernels defined in one .hip translation unit)
+
+// camera.hip
+hipError_t launch_unproject(const DevCamera* cam, int64_t n, const float* pix_xy, float* dirs, uint8_t* valid,
+                            hipStream_t s);
+hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles, float fs, TileCone* tiles,
+                             float* view_cmax, hipStream_t s);
+hipError_t launch_group_cones(const DevCamera* cams, int n_views, int total_groups, const TileCone* tiles,
+                              TileCone* groups, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+// preprocess.hip
+hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,
+                             const Opts& o, Record* rec, uint32_t* depth_key, float4* cone, hipStream_t s);
+
+// binning.hip
+hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone,
+                            const TileCone* tiles, const TileCone* groups, uint32_t* counts, hipStream_t s);
+hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const TileCone* tiles,
+                           const TileCone* groups, const uint32_t* offsets, const uint32_t* depth_key,
+                           uint64_t* keys, uint32_t* slots, uint32_t* slot_gid, hipStream_t s);
+hipError_t launch_tile_ranges(const uint64_t* keys, const uint32_t* slots, const uint32_t* slot_gid, int64_t n,
+                              int key_shift, uint2* ranges, uint32_t* sorted_gid, hipStream_t s);
+
+// sort.hip
+size_t scan_temp_bytes(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s);
+size_t radix_temp_bytes(int64_t n);
+// Sorts (keys, vals) stably on bits [0, end_bit); returns 0 if the result is in
+// (keys, vals) and 1 if it is in (keys_alt, vals_alt).
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                             int end_bit, void* temp, int* result_in_alt, hipStream_t s);
+
+// render_fwd.hip
+hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* out_rgba,
+                             float* final_T, uint32_t* n_last, hipStream_t s);
+
+// bake.hip
+hipError_t launch_bake_rho2(const GaussPtrs& g, const DevCamera* cams, int n_views, float t_near, float* rho2,
+                            hipStream_t s);
+
+// ---------------------------------------------------------------- profiling (pool.cpp)
+enum Stage {
+  ST_CAMERA = 0, ST_PREPROCESS, ST_BIN_COUNT, ST_SCAN, ST_BIN_EMIT, ST_SORT, ST_RANGES, ST_RENDER,
+  ST_BWD_RENDER, ST_BWD_REDUCE, ST_BWD_PREPROCESS, ST_BAKE, ST_NUM
+};
+void prof_begin(int stage, hipStream_t s);
+void prof_end(int stage, hipStream_t s);
+
+}  // namespace cg

@@ -1,0 +1,166 @@
+// Per (view, Gaussian) preprocessing: activations (Sec. 3), the floor of Eq. 10,
+// whitening W = diag(1/s') R^T (Eq. 1 with Sigma_eff), view-dependent colour, the
+// float32 compositing key and the angular influence cone used by the binning.
+#include "camera_dev.hpp"
+
+namespace cg {
+
+// Real spherical harmonics of degree <= 3 at a unit direction (x, y, z): orthonormal
+// on the sphere, Condon-Shortley phase, (l, m) order with m = -l..l.  Each constant is
+// the normalisation sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (times sqrt 2 for m != 0)
+// multiplied by the integer factor of the associated Legendre function written as a
+// polynomial in x, y, z.
+__device__ __forceinline__ void sh_basis3(float x, float y, float z, float Y[16]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = 0.28209479177387814f;                        // 1 / (2 sqrt(pi))
+  Y[1] = -0.4886025119029199f * y;                    // sqrt(3 / (4 pi))
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = -0.4886025119029199f * x;
+  Y[4] = 1.0925484305920792f * x * y;                 // (1/2) sqrt(15 / pi)
+  Y[5] = -1.0925484305920792f * y * z;
+  Y[6] = 0.31539156525252005f * (3.f * zz - 1.f);     // (1/4) sqrt(5 / pi)
+  Y[7] = -1.0925484305920792f * x * z;
+  Y[8] = 0.5462742152960396f * (xx - yy);             // (1/4) sqrt(15 / pi)
+  Y[9] = -0.5900435899266435f * y * (3.f * xx - yy);  // (1/4) sqrt(35 / (2 pi))
+  Y[10] = 2.890611442640554f * x * y * z;             // (1/2) sqrt(105 / pi)
+  Y[11] = -0.4570457994644658f * y * (5.f * zz - 1.f);  // (1/4) sqrt(21 / (2 pi))
+  Y[12] = 0.3731763325901154f * z * (5.f * zz - 3.f);   // (1/4) sqrt(7 / pi)
+  Y[13] = -0.4570457994644658f * x * (5.f * zz - 1.f);
+  Y[14] = 1.445305721320277f * z * (xx - yy);           // (1/4) sqrt(105 / pi)
+  Y[15] = -0.5900435899266435f * x * (xx - 3.f * yy);
+}
+
+// |mu - o|^2 in float32 with the operation order ((vx*vx + vy*vy) + vz*vz) and no
+// fused multiply-add: the compositing key, identical on every platform that rounds
+// float32 to nearest.
+__device__ __noinline__ float depth_key_f32(float mx, float my, float mz, float ox, float oy, float oz) {
+#pragma clang fp contract(off)
+  const float vx = mx - ox;
+  const float vy = my - oy;
+  const float vz = mz - oz;
+  const float sx = vx * vx;
+  const float sy = vy * vy;
+  const float sz = vz * vz;
+  float s = sx + sy;
+  s = s + sz;
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera* __restrict__ cams,
+                                                    const float* __restrict__ view_cmax, Opts o,
+                                                    Record* __restrict__ rec, uint32_t* __restrict__ depth_key,
+                                                    float4* __restrict__ cone) {
+  const int v = blockIdx.y;
+  const int64_t n = g.n;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const DevCamera& c = cams[v];
+  const int64_t out = (int64_t)v * n + i;
+
+  const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+  float q[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
+  const float qn = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float w = q[0] * qn, x = q[1] * qn, y = q[2] * qn, z = q[3] * qn;
+  // R: columns are the principal axes
+  const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                      2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                      2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+  const float sigma = 1.f / (1.f + expf(-g.logits[i]));
+  const float rho2 = (o.use_floor && g.rho2) ? g.rho2[i] : 0.f;
+  float sp[3], sp2[3];
+  float ratio = 1.f;
+  for (int k = 0; k < 3; ++k) {
+    const float s = expf(g.log_scales[k * n + i]);
+    if (rho2 > 0.f) {
+      sp2[k] = s * s + rho2;
+      sp[k] = sqrtf(sp2[k]);
+      ratio *= s / sp[k];
+    } else {
+      sp[k] = s;
+      sp2[k] = s * s;
+    }
+  }
+  const float sig_eff = sigma * ratio;
+
+  Record r;
+  for (int a = 0; a < 3; ++a) {
+    const float inv = 1.f / sp[a];
+    for (int b = 0; b < 3; ++b) r.W[3 * a + b] = R[3 * b + a] * inv;
+  }
+  r.mu[0] = mu[0]; r.mu[1] = mu[1]; r.mu[2] = mu[2];
+  r.sigma = sig_eff;
+  r.sp2[0] = sp2[0]; r.sp2[1] = sp2[1]; r.sp2[2] = sp2[2];
+  r.rho2 = rho2;
+  const float sp2min = fminf(sp2[0], fminf(sp2[1], sp2[2]));
+  r.kg = 1.f / sp2min;
+  r.pad[0] = 0.f;
+  r.pad[1] = 0.f;
+
+  // direction and distance from the camera centre in FP64
+  const double vd[3] = {(double)mu[0] - c.o[0], (double)mu[1] - c.o[1], (double)mu[2] - c.o[2]};
+  const double dist = sqrt(vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]);
+  const float vx = (float)(vd[0] / dist), vy = (float)(vd[1] / dist), vz = (float)(vd[2] / dist);
+
+  if (g.color_mode == 0) {
+    for (int ch = 0; ch < 3; ++ch) r.rgb[ch] = g.color[ch * n + i];
+  } else {
+    float Y[16];
+    sh_basis3(vx, vy, vz, Y);
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.f;
+      for (int k = 0; k < 16; ++k) acc += g.color[(3 * k + ch) * n + i] * Y[k];
+      r.rgb[ch] = fmaxf(acc + 0.5f, 0.f);
+    }
+  }
+
+  depth_key[out] = __float_as_uint(depth_key_f32(mu[0], mu[1], mu[2], c.of[0], c.of[1], c.of[2]));
+
+  // Influence cone.  If T >= alpha_min then (i) the perpendicular distance p of the
+  // mean from the ray satisfies p^2 <= L (s'_max^2 + t*^2 c) with L = 2 ln(sigma_eff /
+  // alpha_min) and c the pixel footprint coefficient (the filtered exponent is the
+  // ray's Mahalanobis distance to N(mu, Sigma_eff + footprint), whose marginal across
+  // the ray is bounded by s'_max^2 + t*^2 c), and (ii) t* <= |v| + p r / 2 with
+  // r = s'_max / s'_min.  Together they bound p by the root of a quadratic; the cone
+  // half-angle is asin(p / |v|).  Computed in FP64 with relative margins.
+  float gamma = -1.f;
+  if (dist > 0.0 && sig_eff > o.alpha_min) {
+    const double L = 2.0 * log((double)sig_eff / (double)o.alpha_min);
+    r.Lg = (float)L;
+    const double smax = sqrt((double)fmaxf(sp2[0], fmaxf(sp2[1], sp2[2])));
+    const double smin = sqrt((double)sp2min);
+    const double rr = smax / smin;
+    double cw = (double)view_cmax[v] * 1.01;
+    if (o.filter_mode == CG_FILTER_CENTER_RAY) cw = 0.0;
+    else if (o.filter_mode == CG_FILTER_ISOTROPIC) cw *= rr * rr * 0.5;
+    const double A2 = 1.0 - L * cw * rr * rr * 0.25;
+    if (A2 <= 1e-3) {
+      gamma = kPiF;
+    } else {
+      const double B2 = L * cw * dist * rr;
+      const double C2 = L * (smax * smax + cw * dist * dist);
+      const double p = (B2 + sqrt(B2 * B2 + 4.0 * A2 * C2)) / (2.0 * A2) * 1.001 + 1e-9;
+      if (dist + p * rr * 0.5 <= (double)o.t_near * 0.999) {
+        gamma = -1.f;  // every t* is at most t_near
+      } else if (p >= dist) {
+        gamma = kPiF;
+      } else {
+        const double gm = asin(p / dist) * 1.0001 + 1e-6;
+        gamma = (dist * cos(gm) > p * rr * 0.5 - (double)o.t_near && gm < kPi) ? (float)gm : kPiF;
+      }
+    }
+  } else {
+    r.Lg = 0.f;
+  }
+  rec[out] = r;
+  cone[out] = make_float4(vx, vy, vz, gamma);
+}
+
+hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,
+                             const Opts& o, Record* rec, uint32_t* depth_key, float4* cone, hipStream_t s) {
+  if (g.n == 0 || n_views == 0) return hipSuccess;
+  const dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)n_views);
+  k_preprocess<<<grid, dim3(256), 0, s>>>(g, cams, view_cmax, o, rec, depth_key, cone);
+  return hipGetLastError();
+}
+
+}  // namespace cg

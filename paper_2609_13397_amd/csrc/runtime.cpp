@@ -1,0 +1,229 @@
+// Error reporting, the scratch-memory pool and per-stage profiling.
+#include "runtime.hpp"
+
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+namespace cg {
+
+// ------------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace cg
+
+extern "C" const char* cg_last_error(void) { return cg::g_last_error.c_str(); }
+
+namespace cg {
+
+// ------------------------------------------------------------------------ pool
+
+namespace {
+
+struct PoolBlock {
+  size_t bytes;
+  hipStream_t stream;
+  int device;
+};
+
+std::mutex g_pool_mu;
+std::multimap<size_t, std::pair<void*, PoolBlock>> g_pool_free;  // by size
+std::unordered_map<void*, PoolBlock> g_pool_live;
+
+size_t round_bytes(size_t b) {
+  if (b <= (1u << 20)) {
+    size_t r = 256;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t g = 2u << 20;
+  return (b + g - 1) / g * g;
+}
+
+}  // namespace
+
+void* pool_alloc(size_t bytes, hipStream_t s) {
+  int dev = 0;
+  CG_HIP(hipGetDevice(&dev));
+  const size_t want = round_bytes(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto it = g_pool_free.lower_bound(want); it != g_pool_free.end() && it->first <= want + want / 4 + (2u << 20);
+         ++it) {
+      if (it->second.second.stream == s && it->second.second.device == dev) {
+        void* p = it->second.first;
+        g_pool_live[p] = it->second.second;
+        g_pool_free.erase(it);
+        return p;
+      }
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    // give cached blocks back and retry once
+    (void)hipGetLastError();
+    pool_release_all();
+    e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(CG_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool_live[p] = PoolBlock{want, s, dev};
+  return p;
+}
+
+void pool_free(void* p, hipStream_t s) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pool_live.find(p);
+  if (it == g_pool_live.end()) return;
+  PoolBlock b = it->second;
+  b.stream = s;
+  g_pool_live.erase(it);
+  g_pool_free.emplace(b.bytes, std::make_pair(p, b));
+}
+
+void pool_release_all() {
+  std::multimap<size_t, std::pair<void*, PoolBlock>> blocks;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    blocks.swap(g_pool_free);
+  }
+  if (blocks.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : blocks) (void)hipFree(kv.second.first);
+}
+
+void* Scratch::get(size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (user_.alloc) {
+    p = user_.alloc(user_.ctx, bytes, s_);
+    if (!p) throw Error(CG_ERR_OUT_OF_MEMORY, "allocator callback failed for " + std::to_string(bytes) + " bytes");
+  } else {
+    p = pool_alloc(bytes, s_);
+  }
+  blocks_.push_back(p);
+  return p;
+}
+
+void free_block(const cg_allocator& a, void* p, hipStream_t s) {
+  if (!p) return;
+  if (a.free) a.free(a.ctx, p, s);
+  else if (!a.alloc) pool_free(p, s);
+}
+
+void Scratch::release() {
+  for (void* p : blocks_) free_block(user_, p, s_);
+  blocks_.clear();
+}
+
+// ------------------------------------------------------------------------ profiling
+
+namespace {
+
+const char* kStageNames[ST_NUM] = {"camera",    "preprocess",   "bin_count",       "scan",
+                                   "bin_emit",  "sort",         "tile_ranges",     "render",
+                                   "bwd_render", "bwd_reduce", "bwd_preprocess", "bake_rho2"};
+
+struct Pending {
+  int stage;
+  hipEvent_t a, b;
+};
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+double g_total_ms[ST_NUM];
+int64_t g_launches[ST_NUM];
+thread_local hipEvent_t t_open[ST_NUM];
+
+hipEvent_t get_event() {
+  hipEvent_t e = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_event_pool.empty()) {
+      e = g_event_pool.back();
+      g_event_pool.pop_back();
+    }
+  }
+  if (!e) CG_HIP(hipEventCreate(&e));
+  return e;
+}
+
+}  // namespace
+
+void prof_begin(int stage, hipStream_t s) {
+  if (!g_prof_on) return;
+  hipEvent_t e = get_event();
+  CG_HIP(hipEventRecord(e, s));
+  t_open[stage] = e;
+}
+
+void prof_end(int stage, hipStream_t s) {
+  if (!g_prof_on || !t_open[stage]) return;
+  hipEvent_t e = get_event();
+  CG_HIP(hipEventRecord(e, s));
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_pending.push_back(Pending{stage, t_open[stage], e});
+  t_open[stage] = nullptr;
+}
+
+}  // namespace cg
+
+extern "C" {
+
+int cg_profile_num_stages(void) { return cg::ST_NUM; }
+
+const char* cg_profile_stage_name(int stage) {
+  return (stage >= 0 && stage < cg::ST_NUM) ? cg::kStageNames[stage] : "";
+}
+
+void cg_profile_enable(int on) { cg::g_prof_on = on != 0; }
+
+cg_status cg_profile_collect(void) {
+  std::vector<cg::Pending> pend;
+  {
+    std::lock_guard<std::mutex> lk(cg::g_prof_mu);
+    pend.swap(cg::g_pending);
+  }
+  cg_status st = CG_OK;
+  for (auto& p : pend) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) {
+      st = CG_ERR_HIP;
+      cg::set_last_error("profiling event failed");
+      continue;
+    }
+    std::lock_guard<std::mutex> lk(cg::g_prof_mu);
+    cg::g_total_ms[p.stage] += ms;
+    cg::g_launches[p.stage] += 1;
+    cg::g_event_pool.push_back(p.a);
+    cg::g_event_pool.push_back(p.b);
+  }
+  return st;
+}
+
+void cg_profile_read(double* total_ms, int64_t* launches) {
+  std::lock_guard<std::mutex> lk(cg::g_prof_mu);
+  for (int i = 0; i < cg::ST_NUM; ++i) {
+    if (total_ms) total_ms[i] = cg::g_total_ms[i];
+    if (launches) launches[i] = cg::g_launches[i];
+    cg::g_total_ms[i] = 0.0;
+    cg::g_launches[i] = 0;
+  }
+}
+
+cg_status cg_release_cached_memory(void) {
+  cg::pool_release_all();
+  return CG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Device exclusive scan (uint32) and stable LSD radix sort of (uint64 key, uint32
+// value) pairs, 8 bits per pass.
+//
+// Radix pass = histogram kernel (per-block digit counts, LDS atomics) + exclusive scan
+// of the digit-major count table + scatter kernel.  The scatter is stable: each
+// wavefront owns a contiguous run of 1024 items, walks it in rounds of 64, and ranks
+// items of equal digit with 8 ballots (a wave-wide digit match); per-wave digit
+// counters in LDS carry the running offsets between rounds and are prefixed across
+// the block's four wavefronts before the writes.
+#include "cg_common.hpp"
+
+namespace cg {
+
+// ------------------------------------------------------------------------------ scan
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;  // 2048
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of one 2048-item tile per block; block totals to `partials`.
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                           int64_t n, uint32_t* __restrict__ partials) {
+  __shared__ uint32_t wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    local += v[k];
+  }
+  const uint32_t incl = wave_incl_scan(local);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int k = 0; k < w; ++k) woff += wsum[k];
+  uint32_t run = woff + incl - local;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanBlock - 1 && partials) partials[blockIdx.x] = woff + incl;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ out, int64_t n,
+                                                         const uint32_t* __restrict__ partials) {
+  const uint32_t add = partials[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) out[base + k] += add;
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t scan_temp_bytes(int64_t n) {
+  size_t total = 0;
+  int64_t m = n;
+  while (m > kScanTile) {
+    m = ceil_div(m, kScanTile);
+    total += (size_t)m * sizeof(uint32_t) * 2;
+  }
+  return total + 256;
+}
+
+static hipError_t scan_rec(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp, hipStream_t s) {
+  const int64_t blocks = ceil_div(n, kScanTile);
+  if (blocks <= 1) {
+    k_scan_tiles<<<dim3(1), dim3(kScanBlock), 0, s>>>(in, out, n, nullptr);
+    return hipGetLastError();
+  }
+  uint32_t* part = temp;
+  uint32_t* part_scan = temp + blocks;
+  k_scan_tiles<<<dim3((unsigned)blocks), dim3(kScanBlock), 0, s>>>(in, out, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_rec(part, part_scan, blocks, temp + 2 * blocks, s);
+  if (e != hipSuccess) return e;
+  k_scan_add<<<dim3((unsigned)blocks), dim3(kScanBlock), 0, s>>>(out, n, part_scan);
+  return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  return scan_rec(in, out, n, static_cast<uint32_t*>(temp), s);
+}
+
+// ------------------------------------------------------------------------------ radix sort
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortBlock = 256;
+constexpr int kSortRounds = 16;                                 // rounds of 64 items per wave
+constexpr int kSortTile = kSortBlock * kSortRounds;             // 4096 items per block
+constexpr int kWaveItems = 64 * kSortRounds;                    // 1024 items per wave
+
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                           uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t cnt[kRadix];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortRounds; ++k) {
+    const int64_t idx = base + (int64_t)k * kSortBlock + threadIdx.x;
+    if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                              const uint32_t* __restrict__ vin,
+                                                              uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                              int64_t n, int shift,
+                                                              const uint32_t* __restrict__ offsets, int nblocks) {
+  __shared__ uint32_t wcnt[4][kRadix];
+  __shared__ uint32_t gofs[kRadix];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0;
+  gofs[threadIdx.x] = offsets[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  __syncthreads();
+  const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * kWaveItems;
+  const uint64_t lt = __lanemask_lt();
+  uint64_t key[kSortRounds];
+  uint32_t val[kSortRounds];
+  uint32_t rank[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t idx = wbase + (int64_t)r * 64 + lane;
+    const bool ok = idx < n;
+    key[r] = ok ? kin[idx] : 0ull;
+    val[r] = ok ? vin[idx] : 0u;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    uint32_t base = 0;
+    if (ok) base = wcnt[wave][d];
+    if (ok && before == 0) wcnt[wave][d] = base + (uint32_t)__popcll(peers);
+    rank[r] = ok ? base + before : 0xffffffffu;
+  }
+  __syncthreads();
+  {  // exclusive prefix of the per-wave digit counts across the block's waves
+    const int d = threadIdx.x;
+    uint32_t run = 0;
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t t = wcnt[w][d];
+      wcnt[w][d] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (rank[r] == 0xffffffffu) continue;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    const uint32_t pos = gofs[d] + wcnt[wave][d] + rank[r];
+    kout[pos] = key[r];
+    vout[pos] = val[r];
+  }
+}
+
+size_t radix_temp_bytes(int64_t n) {
+  const int64_t nblocks = ceil_div(n > 0 ? n : 1, kSortTile);
+  const int64_t m = nblocks * kRadix;
+  return (size_t)m * sizeof(uint32_t) * 2 + scan_temp_bytes(m) + 256;
+}
+
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                             int end_bit, void* temp, int* result_in_alt, hipStream_t s) {
+  *result_in_alt = 0;
+  if (n <= 1) return hipSuccess;
+  const int nblocks = (int)ceil_div(n, kSortTile);
+  const int64_t m = (int64_t)nblocks * kRadix;
+  uint32_t* hist = static_cast<uint32_t*>(temp);
+  uint32_t* offs = hist + m;
+  void* stemp = offs + m;
+  uint64_t* kin = keys;
+  uint32_t* vin = vals;
+  uint64_t* kout = keys_alt;
+  uint32_t* vout = vals_alt;
+  int alt = 0;
+  for (int shift = 0; shift < end_bit; shift += kRadixBits) {
+    k_radix_hist<<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, n, shift, hist, nblocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan(hist, offs, m, stemp, s);
+    if (e != hipSuccess) return e;
+    k_radix_scatter<<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, vin, kout, vout, n, shift, offs, nblocks);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint64_t* tk = kin; kin = kout; kout = tk;
+    uint32_t* tv = vin; vin = vout; vout = tv;
+    alt ^= 1;
+  }
+  *result_in_alt = alt;
+  return hipSuccess;
+}
+
+}  // namespace cg

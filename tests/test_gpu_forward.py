@@ -1,0 +1,219 @@
+"""GPU parity of the forward path (through the C ABI) against the FP64 oracle.
+
+Images must match within 2e-4 absolute per channel (the tolerance the method's
+float32 arithmetic is held to); where the oracle reports a near-threshold decision
+(alpha_min, T_min, t_near) the GPU may match the result with that decision flipped.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_13397_amd import synth
+from parity import TOL_IMAGE, compare_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    from paper_2609_13397_amd import render as R
+    assert torch.cuda.is_available(), "no GPU"
+    return torch, R
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _opts_pair(**kw):
+    from paper_2609_13397_amd import render as R
+    return R.RenderOpts(**kw), O.Opts(**kw)
+
+
+def gpu_render(scene, cams, opts):
+    torch, R = _gpu()
+    sc = R.Scene.from_numpy(scene)
+    rgba, info, _ = R.render_forward(sc, cams, opts)
+    torch.cuda.synchronize()
+    return [v.cpu().numpy().astype(np.float64) for v in R.split_views(rgba, cams)], info
+
+
+def check_view(gpu_img, scene, cam, oopts, mode="brute", tol=TOL_IMAGE):
+    ref = O.render(scene, cam, oopts, mode=mode, with_alt=True)
+    nfail, worst, det = compare_image(gpu_img, ref, tol)
+    _say(f"   parity: fail={nfail} worst={worst:.3e} {det}")
+    assert nfail == 0, (worst, det)
+    return ref
+
+
+# --------------------------------------------------------------------------- cameras
+
+@pytest.mark.parametrize("which", ["pinhole", "kb", "equirect"])
+def test_camera_unproject_matches_oracle(which):
+    torch, R = _gpu()
+    k, _ = synth.draw_kb_coeffs(31, math.radians(95))
+    cams = {
+        "pinhole": synth.camera(synth.PINHOLE, 640, 480, fx=500.0, fy=510.0, cx=320.3, cy=241.7,
+                                R_c2w=synth.look_at((0, 0, 0), (1, 2, 0.5))),
+        "kb": synth.kb_camera(400, 400, 95.0, k, 200.0, synth.look_at((0, 0, 0), (1, -1, 0.2)), (0, 0, 0)),
+        "equirect": synth.camera(synth.EQUIRECT, 512, 256, R_c2w=synth.look_at((0, 0, 0), (0.3, 1, 0))),
+    }
+    cam = cams[which]
+    _say(f"unproject {which}")
+    rng = np.random.default_rng(2)
+    n = 20000
+    px = rng.uniform(0, cam["full_w"], n).astype(np.float32)
+    py = rng.uniform(0, cam["full_h"], n).astype(np.float32)
+    xy = torch.from_numpy(np.stack([px, py])).cuda()
+    dirs, valid = R.camera_unproject(cam, xy)
+    dirs = dirs.cpu().numpy().T.astype(np.float64)
+    valid = valid.cpu().numpy()
+    dref, vref = O.unproject(cam, px.astype(np.float64), py.astype(np.float64))
+    # validity decided in FP64 on both sides from the same float32 coordinates
+    assert np.array_equal(valid, vref)
+    err = np.max(np.abs(dirs[vref] - dref[vref]))
+    _say(f"   max dir err {err:.3e}")
+    assert err < 1e-6  # float32 rounding of a unit vector
+
+
+# --------------------------------------------------------------------------- floor bake
+
+def test_bake_rho2_matches_oracle():
+    torch, R = _gpu()
+    scene = synth.make_scene(20000, seed=21, layout="clusters", color="sh3", log_scale_mean=-4.0, log_scale_std=0.7)
+    cams = synth.orbit_views(8) + synth.fisheye_cameras()
+    _say("bake rho2")
+    sc = R.Scene.from_numpy(scene)
+    r_gpu = R.bake_rho2(sc, cams).cpu().numpy().astype(np.float64)
+    r_ref = O.bake_rho2(scene, cams)
+    assert np.array_equal(r_gpu == 0, r_ref == 0)
+    nz = r_ref > 0
+    rel = np.abs(r_gpu[nz] - r_ref[nz]) / r_ref[nz]
+    _say(f"   visible {nz.mean():.3f} max rel err {rel.max():.3e}")
+    assert rel.max() < 1e-5
+
+
+# --------------------------------------------------------------------------- forward parity
+
+TINY_VARIANTS = [
+    dict(filter_mode=1),
+    dict(filter_mode=0),
+    dict(filter_mode=2),
+    dict(filter_mode=1, bg=(0.2, 0.4, 0.6)),
+    dict(filter_mode=1, footprint_scale=3.0),
+]
+
+
+@pytest.mark.parametrize("kw", TINY_VARIANTS, ids=[str(v) for v in TINY_VARIANTS])
+def test_tiny_forward_parity(kw):
+    """256 Gaussians, 64x48 pinhole (config 1) plus a ragged 70x37 crop of a wider view."""
+    scene, cam = synth.tiny_config()
+    ragged = synth.camera(synth.PINHOLE, 90, 60, fx=45.0, fy=45.0, cx=44.0, cy=31.0,
+                          origin=(0.1, -0.1, -3.0), crop=(7, 11, 70, 37))
+    gopts, oopts = _opts_pair(**kw)
+    _say(f"tiny forward {kw}")
+    imgs, info = gpu_render(scene, [cam, ragged], gopts)
+    _say(f"   pairs {info['n_pairs']}")
+    for img, c in zip(imgs, [cam, ragged]):
+        check_view(img, scene, c, oopts)
+
+
+@pytest.mark.parametrize("composition", [0, 1])
+def test_tiny_forward_floor_parity(composition):
+    """Floor on, with rho^2 baked (by the oracle, Eq. 11) from the same camera at x2
+    resolution, so the floor partly covers the render footprint."""
+    scene, cam = synth.tiny_config()
+    scene = dict(scene)
+    scene["rho2"] = O.bake_rho2(scene, [synth.scale_camera(cam, 2.0)]).astype(np.float32)
+    gopts, oopts = _opts_pair(use_floor=True, composition=composition)
+    oopts.use_floor = 1
+    _say(f"tiny floor composition={composition}")
+    imgs, _ = gpu_render(scene, [cam], gopts)
+    check_view(imgs[0], scene, cam, oopts)
+
+
+def test_fisheye_and_equirect_small_parity():
+    """Wide cameras with sheared peripheral footprints: a 190-degree KB fisheye and an
+    equirectangular view, 2000 Gaussians around the camera, floor on."""
+    scene = synth.make_scene(2000, seed=22, layout="clusters", color="sh3", log_scale_mean=-3.0, log_scale_std=0.6)
+    scene["means"] *= 0.3
+    kb, eq = synth.fisheye_cameras()
+    kb = synth.scale_camera(kb, 1 / 16)
+    eq = synth.scale_camera(eq, 1 / 16)
+    cams = [kb, eq]
+    for c in cams:
+        c["origin"] = (0.0, -1.0, 0.3)
+    scene["rho2"] = O.bake_rho2(scene, [synth.scale_camera(c, 2.0) for c in cams]).astype(np.float32)
+    gopts, oopts = _opts_pair(use_floor=True)
+    oopts.use_floor = 1
+    _say("fisheye + equirect small")
+    imgs, info = gpu_render(scene, cams, gopts)
+    _say(f"   pairs {info['n_pairs']}")
+    for img, c in zip(imgs, cams):
+        check_view(img, scene, c, oopts)
+
+
+def test_empty_and_degenerate_inputs():
+    torch, R = _gpu()
+    _say("empty inputs")
+    scene, cam = synth.tiny_config()
+    empty = synth.subset_scene(scene, np.arange(0))
+    imgs, info = gpu_render(empty, [cam], R.RenderOpts(bg=(0.1, 0.2, 0.3)))
+    assert info["n_pairs"] == 0
+    assert np.allclose(imgs[0][..., :3], [0.1, 0.2, 0.3]) and np.all(imgs[0][..., 3] == 0)
+    # one Gaussian behind the camera: nothing is binned
+    behind = synth.subset_scene(scene, np.arange(1))
+    behind["means"] = np.array([[0.0], [0.0], [-5.0]], np.float32)
+    imgs, info = gpu_render(behind, [cam], R.RenderOpts())
+    assert info["n_pairs"] == 0 and np.all(imgs[0] == 0)
+    # zero-sized crop next to a normal view
+    c0 = synth.with_crop(cam, 0, 0, 0, 0)
+    imgs, info = gpu_render(scene, [c0, cam], R.RenderOpts())
+    assert imgs[0].shape == (0, 0, 4)
+    check_view(imgs[1], scene, cam, O.Opts())
+
+
+def test_multiview_batch_equals_single_views():
+    """A batched call renders each view exactly as a call with that view alone."""
+    torch, R = _gpu()
+    scene, cam = synth.tiny_config()
+    cams = [cam, synth.scale_camera(cam, 0.5), synth.scale_camera(cam, 2.0)]
+    _say("multiview batch")
+    batch, _ = gpu_render(scene, cams, R.RenderOpts())
+    for img, c in zip(batch, cams):
+        single, _ = gpu_render(scene, [c], R.RenderOpts())
+        assert np.array_equal(img, single[0])
+
+
+def test_determinism_and_permutation():
+    torch, R = _gpu()
+    scene, cam = synth.tiny_config()
+    _say("determinism")
+    a, _ = gpu_render(scene, [cam], R.RenderOpts())
+    b, _ = gpu_render(scene, [cam], R.RenderOpts())
+    assert np.array_equal(a[0], b[0])
+    perm = np.random.default_rng(3).permutation(scene["n"])
+    c, _ = gpu_render(synth.subset_scene(scene, perm), [cam], R.RenderOpts())
+    assert np.array_equal(a[0], c[0])
+
+
+def test_pinhole_config_eighth_resolution_parity():
+    """Config 2 at 1/8 resolution (240x135): 100k clustered Gaussians with SH colour and
+    rho^2 baked from the 8 full-resolution orbit views; two of the 8 views, floor on."""
+    scene, views = synth.pinhole_config()
+    _say("pinhole 1/8: baking rho2")
+    torch, R = _gpu()
+    sc = R.Scene.from_numpy(scene)
+    rho2 = O.bake_rho2(scene, views)
+    scene["rho2"] = rho2.astype(np.float32)
+    cams = [synth.scale_camera(views[0], 0.125), synth.scale_camera(views[3], 0.125)]
+    gopts, oopts = _opts_pair(use_floor=True)
+    oopts.use_floor = 1
+    imgs, info = gpu_render(scene, cams, gopts)
+    _say(f"   pairs {info['n_pairs']}")
+    for img, c in zip(imgs, cams):
+        check_view(img, scene, c, oopts, mode="culled")
