@@ -1,0 +1,187 @@
+"""Benchmark of the ConeGaussian hot path on one MI355X.
+
+A step is one batched forward render (cg_render_forward) of the 1M-Gaussian fisheye
+workload: 1M clustered Gaussians with degree-3 SH colour and the Eq. 11 floor baked
+from 8 pinhole orbit views, rendered into a 190-degree Kannala-Brandt fisheye
+(1600x1600) and an equirectangular view (2048x1024) -- 4.66 Mpixel per step, floor
+and anisotropic footprint filter on, marginal composition.  Inputs are resident in
+HBM before the timed region.
+
+Prints one JSON line: throughput (Mpix/s), the roofline of the dominant kernel (the
+tile render, ALU-bound: algorithmic flops = contributing pairs x flops per pair,
+divided by the kernel's average duration from HIP events on its stream), and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per contributing (pixel, Gaussian) pair: flops of the closed form
+# (FMA = 2), floor on / off, plus transcendentals, frozen before tuning.
+FLOPS_PER_PAIR = {True: 225, False: 156}
+TRANSC_PER_PAIR = {True: 8, False: 4}
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+# Algorithmic HBM bytes of one render launch: per pair a 4-byte list entry and a
+# 96-byte record; per pixel the 16-byte RGBA output.
+BYTES_PER_PAIR = 100
+BYTES_PER_PIXEL = 16
+
+RENDER_SOURCES = ["paper_2609_13397_amd/csrc/render_fwd.hip", "paper_2609_13397_amd/csrc/pair_math.hpp",
+                  "paper_2609_13397_amd/csrc/camera_dev.hpp", "paper_2609_13397_amd/csrc/cg_common.hpp"]
+
+
+def render_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in RENDER_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM traffic of the render kernel from rocprofv3 counters (profiles/), if taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "render_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("render_source_hash") != render_source_hash():
+        return None
+    return t
+
+
+def build_workload(torch, R, synth, device):
+    scene_np, cams = synth.fisheye_config()
+    scene = R.Scene.from_numpy(scene_np, device=device)
+    scene.rho2 = R.bake_rho2(scene, synth.orbit_views(), t_near=0.2)
+    torch.cuda.synchronize()
+    return scene_np, scene, cams
+
+
+def cpu_baseline(scene_np, scene_rho2, cams, opts_kw, rows=4):
+    """The FP64 oracle (culled mode) on a band of `rows` rows through the middle of each
+    view, all host threads."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2609_13397_amd import synth
+
+    sc = dict(scene_np)
+    sc["rho2"] = scene_rho2.astype(np.float32)
+    opts = O.Opts(**opts_kw)
+    threads = os.cpu_count() or 1
+    px = 0
+    t0 = time.perf_counter()
+    for c in cams:
+        w, h = c["crop"][2], c["crop"][3]
+        band = synth.with_crop(c, 0, h // 2 - rows // 2, w, rows)
+        O.render(sc, band, opts, mode="culled", n_threads=threads)
+        px += w * rows
+    dt = time.perf_counter() - t0
+    return {"value": px / dt / 1e6, "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows} middle rows of each view ({px} px), culled FP64 oracle incl. its per-call set-up",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
+              "is described in DESIGN.md and is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2609_13397_amd import render as R
+    from paper_2609_13397_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    device = torch.device("cuda:0")
+    print("bench: building workload", file=sys.stderr, flush=True)
+    scene_np, scene, cams = build_workload(torch, R, synth, device)
+    use_floor = True
+    opts = R.RenderOpts(filter_mode=R.FILTER_ANISOTROPIC, use_floor=use_floor)
+    npx = sum(R.view_pixels(cams))
+    out = torch.empty((npx, 4), dtype=torch.float32, device=device)
+
+    # pair counts (counting variant of the render kernel, outside the timed region)
+    copts = R.RenderOpts(filter_mode=R.FILTER_ANISOTROPIC, use_floor=use_floor, count_pairs=True)
+    _, info, _ = R.render_forward(scene, cams, copts, out=out)
+    torch.cuda.synchronize()
+    print(f"bench: pairs={info['n_pairs']} evaluated={info['n_evaluated']} full={info['n_full']} "
+          f"contrib={info['n_contrib']}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        R.render_forward(scene, cams, opts, out=out)
+    torch.cuda.synchronize()
+    prof = R.Profiler()
+    with prof:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            R.render_forward(scene, cams, opts, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    stages = prof.read()
+    ms_per_step = dt / args.steps * 1e3
+    value = npx * args.steps / dt / 1e6
+    print(f"bench: {ms_per_step:.3f} ms/step, {value:.1f} Mpix/s", file=sys.stderr, flush=True)
+
+    render = stages["render"]
+    render_ms = render["ms"] / max(render["launches"], 1)
+    flops = info["n_contrib"] * FLOPS_PER_PAIR[use_floor]
+    achieved = flops / (render_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                "kernel": "k_render (tile render)", "kernel_ms": render_ms,
+                "units_per_launch": info["n_contrib"], "unit_name": "contributing pair",
+                "flops_per_unit": FLOPS_PER_PAIR[use_floor], "transcendentals_per_unit": TRANSC_PER_PAIR[use_floor],
+                "evaluated_per_contributing": info["n_evaluated"] / max(info["n_contrib"], 1),
+                "full_per_contributing": info["n_full"] / max(info["n_contrib"], 1)}
+    alg_bytes = info["n_pairs"] * BYTES_PER_PAIR + npx * BYTES_PER_PIXEL
+    roofline["algorithmic_bytes"] = alg_bytes
+    roofline["achieved_GBps"] = alg_bytes / (render_ms * 1e-3) / 1e9
+    tr = load_traffic()
+    if tr is not None:
+        roofline["traffic"] = tr["bytes_per_launch"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(scene_np, scene.rho2.cpu().numpy(), cams,
+                           dict(filter_mode=1, use_floor=1), rows=args.cpu_rows)
+
+    line = {
+        "metric": "Mpix/s fwd & fwd+bwd at 1M Gaussians; serving p50/p99 ms vs per-view launch",
+        "value": value, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fisheye_1M", "gaussians": scene.n,
+                   "views": "KB fisheye 1600x1600 (190 deg) + equirect 2048x1024, one batched call",
+                   "filter": "anisotropic footprint + floor (marginal composition)", "colour": "SH degree 3",
+                   "pixels_per_step": npx, "pairs": info["n_pairs"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_ms": {k: v["ms"] / max(v["launches"], 1) for k, v in stages.items() if v["launches"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,7 +109,9 @@ enum { CG_COMPOSE_MARGINAL = 0, CG_COMPOSE_ADDITIVE = 1 };
  *                   transmittance below T_min.
  *   t_near          [0.2]   pairs with max-response depth t* <= t_near give T = 0.
  *   bg[3]           [0]     background, added as T_final * bg.
- *   footprint_scale [1]     multiplies the neighbour-ray differentials (0 = centre ray). */
+ *   footprint_scale [1]     multiplies the neighbour-ray differentials (0 = centre ray).
+ *   count_pairs     [0]     when set, cg_fwd_stats also receives the pair counts below
+ *                   (a counting variant of the render kernel; results are identical). */
 typedef struct {
   int32_t filter_mode;
   int32_t use_floor;
@@ -117,6 +119,7 @@ typedef struct {
   float alpha_min, alpha_max, T_min, t_near;
   float bg[3];
   float footprint_scale;
+  int32_t count_pairs;
 } cg_render_opts;
 
 /* Scratch allocator.  alloc returns device memory usable in stream order on `stream`
@@ -141,6 +144,11 @@ typedef struct {
   int64_t n_gaussian_views; /* n * n_views                                           */
   int32_t sort_bits;        /* radix-sort key width                                  */
   int32_t reserved;
+  /* filled only with opts.count_pairs (else -1):                                    */
+  int64_t n_evaluated;      /* (pixel, Gaussian) pairs a pixel walked through        */
+  int64_t n_full;           /* ... that passed the cheap rejection (full Eq. 9 work) */
+  int64_t n_contrib;        /* ... that were composited (alpha >= alpha_min, before
+                               termination): the method's unit of work              */
 } cg_fwd_stats;
 
 int cg_version(void);

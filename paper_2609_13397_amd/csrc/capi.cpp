@@ -275,12 +275,25 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
       CG_HIP(launch_tile_ranges(skeys, sslots, slot_gid, P, 31, ranges, sorted_gid, s));
     }
+    unsigned long long* counters = nullptr;
+    if (opts_in->count_pairs) {
+      counters = sc.get_n<unsigned long long>(4);
+      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, s));
+    }
     {
       ProfScope ps(ST_RENDER, s);
       CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sorted_gid, out_rgba, final_T,
-                               n_last, s));
+                               n_last, counters, s));
+    }
+    unsigned long long host_counters[3] = {~0ull, ~0ull, ~0ull};
+    if (counters) {
+      CG_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
+      CG_HIP(hipStreamSynchronize(s));
     }
     if (stats) {
+      stats->n_evaluated = (int64_t)host_counters[0];
+      stats->n_full = (int64_t)host_counters[1];
+      stats->n_contrib = (int64_t)host_counters[2];
       stats->n_pairs = P;
       stats->n_tiles = total_tiles;
       stats->n_pixels = total_px;

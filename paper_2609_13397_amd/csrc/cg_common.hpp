@@ -112,7 +112,7 @@ hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
 // render_fwd.hip
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
                              int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* out_rgba,
-                             float* final_T, uint32_t* n_last, hipStream_t s);
+                             float* final_T, uint32_t* n_last, unsigned long long* counters, hipStream_t s);
 
 // bake.hip
 hipError_t launch_bake_rho2(const GaussPtrs& g, const DevCamera* cams, int n_views, float t_near, float* rho2,

@@ -32,6 +32,7 @@ class RenderOpts:
     t_near: float = 0.2
     bg: tuple = (0.0, 0.0, 0.0)
     footprint_scale: float = 1.0
+    count_pairs: bool = False
 
     def to_c(self) -> _lib.CgOpts:
         o = _lib.CgOpts()
@@ -44,6 +45,7 @@ class RenderOpts:
         o.t_near = self.t_near
         o.bg[:] = list(self.bg)
         o.footprint_scale = self.footprint_scale
+        o.count_pairs = 1 if self.count_pairs else 0
         return o
 
 
@@ -171,7 +173,8 @@ def render_forward(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None, 
     _lib.check(st)
     fs = ForwardState(state, (scene, out)) if need_state else None
     info = {"n_pairs": stats.n_pairs, "n_tiles": stats.n_tiles, "n_pixels": stats.n_pixels,
-            "sort_bits": stats.sort_bits}
+            "sort_bits": stats.sort_bits, "n_evaluated": stats.n_evaluated, "n_full": stats.n_full,
+            "n_contrib": stats.n_contrib}
     return out, info, fs
 
 
