@@ -178,7 +178,7 @@ def main():
                    "pixels_per_step": npx, "pairs": info["n_pairs"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "stages_ms": {k: v["ms"] / max(v["launches"], 1) for k, v in stages.items() if v["launches"]},
+        "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in stages.items() if v["launches"]},
     }
     print(json.dumps(line), flush=True)
 

@@ -605,14 +605,16 @@ CompositeOut composite(const std::vector<int64_t>& cand, const ViewGauss& vg, co
 // ----------------------------------------------------------------------------- culling grid
 // Culled mode restricts each pixel's candidate list with a latitude-longitude grid of
 // directions around the camera centre.  A Gaussian is entered in every cell that may
-// hold a direction d with T >= alpha_min.  The bound: with Sigma_tot the Gaussian
-// covariance plus the (PSD-dominated) footprint covariance, q^T A^{-1} q equals the
-// smallest Mahalanobis distance of the ray to N(mu, Sigma_tot); it is at least
-// p^2 / (s'_max^2 + t*^2 c) where p is the perpendicular distance of mu from the ray
-// and c the pixel's (|d_x - d|^2 + |d_y - d|^2) / 3.  Also t* <= |v| + p r / 2 with
-// r = s'_max / s'_min.  T >= alpha_min then forces p below the positive root of a
-// quadratic; that gives a cone half-angle around the direction of mu.  Gaussians for
-// which no finite cone exists are entered everywhere.
+// hold a direction d with T >= alpha_min, using two facts about the filtered exponent
+// Q = q^T A^{-1} q <= L = 2 ln(sigma_eff / alpha_min):
+//  * the max-response point o + t* d is within rho of the mean, rho = s'_max sqrt(L (1 +
+//    t*^2 c / s'_min^2)) with t* <= |v| + rho (c: largest pixel footprint coefficient
+//    (|d_x - d|^2 + |d_y - d|^2) / 3 of the view), because |W^{-1} q| <= s'_max |q| and
+//    lambda_max(A) <= 1 + tr Sigma_fp^u;
+//  * Q is the ray's Mahalanobis distance to N(mu, Sigma_eff + footprint covariance), so
+//    the perpendicular distance p of mu from the ray has p^2 <= L (s'_max^2 + t*^2 c).
+// Rays meeting the ball B(mu, rho) at positive t lie in the cone asin(rho / |v|) when
+// |v| > rho; the cone half-angle is asin(min(p, rho) / |v|).
 
 struct Cone { double axis[3]; double half; bool all; };
 
@@ -624,22 +626,24 @@ Cone influence_cone(const GaussPre& G, const double o[3], double cmax, const orc
   for (int k = 0; k < 3; ++k) cn.axis[k] = dist > 0 ? v[k] / dist : 0.0;
   cn.half = kPi;
   if (G.sigma <= op.alpha_min) { cn.half = -1.0; return cn; }  // never reaches alpha_min
+  if (dist <= 0) { cn.all = true; return cn; }
   const double L = 2.0 * std::log(G.sigma / op.alpha_min);
   const double smax = std::max(G.sp[0], std::max(G.sp[1], G.sp[2]));
   const double smin = std::min(G.sp[0], std::min(G.sp[1], G.sp[2]));
   const double r = smax / smin;
+  const double c = (op.filter_mode == 0) ? 0.0 : cmax;
   // Isotropic mode spreads the in-plane trace over both whitened directions, so its
   // world-space marginal variance is bounded by s'_max^2 (1 + tau/2) <= s'_max^2 + t*^2 c r^2 / 2.
-  const double c = (op.filter_mode == 0) ? 0.0 : (op.filter_mode == 2 ? cmax * r * r / 2.0 : cmax);
-  const double A2 = 1.0 - L * c * r * r / 4.0;
-  if (A2 <= 1e-3 || dist <= 0) { cn.all = true; return cn; }
-  const double B2 = L * c * dist * r;
-  const double C2 = L * (smax * smax + c * dist * dist);
-  const double p = (B2 + std::sqrt(B2 * B2 + 4.0 * A2 * C2)) / (2.0 * A2);
-  if (p >= dist) { cn.all = true; return cn; }
-  const double half = std::asin(p / dist);
-  if (!(dist * std::cos(half) > p * r / 2.0 - op.t_near)) { cn.all = true; return cn; }
-  cn.half = half;
+  const double c_perp = (op.filter_mode == 2) ? c * r * r / 2.0 : c;
+  const double a = L * smax * smax, k = c / (smin * smin), ak = a * k;
+  if (ak >= 0.999) { cn.all = true; return cn; }
+  const double rho = (ak * dist + std::sqrt(ak * dist * ak * dist + (1.0 - ak) * a * (1.0 + k * dist * dist))) /
+                     (1.0 - ak) * (1.0 + 1e-9);
+  if (dist + rho <= op.t_near) { cn.half = -1.0; return cn; }  // every t* <= t_near
+  if (dist <= rho) { cn.all = true; return cn; }
+  const double tmax = dist + rho;
+  const double p = std::sqrt(L * (smax * smax + tmax * tmax * c_perp)) * (1.0 + 1e-9);
+  cn.half = std::asin(std::min(p, rho) / dist);
   return cn;
 }
 

@@ -26,8 +26,8 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
                                              const float4* __restrict__ cone, const TileCone* __restrict__ tiles,
                                              const TileCone* __restrict__ groups, uint32_t* __restrict__ counts,
                                              const uint32_t* __restrict__ offsets,
-                                             const uint32_t* __restrict__ depth_key, uint64_t* __restrict__ keys,
-                                             uint32_t* __restrict__ slots, uint32_t* __restrict__ slot_gid) {
+                                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                             uint32_t* __restrict__ slot_gid) {
   __shared__ uint16_t hits[4][64][kMaxGroupHits];
   const int v = blockIdx.y;
   const DevCamera& c = cams[v];
@@ -54,7 +54,6 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
   // phase 2: tile tests, one lane per tile of a hit group
   uint32_t my_count = 0;
   const uint32_t my_base = (EMIT && in) ? offsets[gv] : 0u;
-  const uint32_t my_depth = (EMIT && in) ? depth_key[gv] : 0u;
   const int tl_x = lane % kGroup, tl_y = lane / kGroup;
   for (int l = 0; l < 64; ++l) {
     const int nh_l = __builtin_amdgcn_readlane(nh, l);
@@ -62,7 +61,6 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
     const float cx = readlane_f(cn.x, l), cy = readlane_f(cn.y, l), cz = readlane_f(cn.z, l);
     const float cw = readlane_f(cn.w, l), csg = readlane_f(sg, l), ccg = readlane_f(cg, l);
     const uint32_t base = EMIT ? readlane_u(my_base, l) : 0u;
-    const uint32_t depth = EMIT ? readlane_u(my_depth, l) : 0u;
     const bool ovf = nh_l > kMaxGroupHits;
     const int n_iter = ovf ? ng : nh_l;
     uint32_t cnt = 0;
@@ -84,9 +82,14 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
       const uint64_t m = __ballot(hit);
       if (EMIT && hit) {
         const uint32_t pos = base + cnt + (uint32_t)__popcll(m & __lanemask_lt());
-        keys[pos] = ((uint64_t)(uint32_t)tile << 31) | (uint64_t)depth;
-        slots[pos] = pos;
-        slot_gid[pos] = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63) + l);
+        const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63) + l);
+        keys[pos] = (uint32_t)tile;
+        if (slot_gid) {
+          vals[pos] = pos;
+          slot_gid[pos] = gid;
+        } else {
+          vals[pos] = gid;
+        }
       }
       cnt += (uint32_t)__popcll(m);
     }
@@ -99,39 +102,80 @@ hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const
                             const TileCone* tiles, const TileCone* groups, uint32_t* counts, hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
-  k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, tiles, groups, counts, nullptr, nullptr, nullptr, nullptr,
-                                          nullptr);
+  k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, tiles, groups, counts, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const TileCone* tiles,
-                           const TileCone* groups, const uint32_t* offsets, const uint32_t* depth_key,
-                           uint64_t* keys, uint32_t* slots, uint32_t* slot_gid, hipStream_t s) {
+                           const TileCone* groups, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
+                           uint32_t* slot_gid, hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
-  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, tiles, groups, nullptr, offsets, depth_key, keys, slots,
-                                         slot_gid);
+  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, tiles, groups, nullptr, offsets, keys, vals, slot_gid);
   return hipGetLastError();
 }
 
-// Per-tile [start, end) ranges of the sorted pair list, and the Gaussian index of each
-// sorted pair.  `ranges` must be zeroed beforehand (empty tiles keep (0, 0)).
-__global__ void k_tile_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ slots,
-                              const uint32_t* __restrict__ slot_gid, int64_t n, int shift, uint2* __restrict__ ranges,
+// Compositing order of the (view, Gaussian) items: key (view << 31 | float32 depth
+// key), sorted stably so that equal keys keep the Gaussian index order.
+__global__ void k_depth_items(const uint32_t* __restrict__ depth_key, int64_t n, int64_t nv, uint64_t* __restrict__ keys,
+                              uint32_t* __restrict__ items) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nv) return;
+  const uint64_t v = (uint64_t)(k / n);
+  keys[k] = (v << 31) | (uint64_t)depth_key[k];
+  items[k] = (uint32_t)k;
+}
+
+hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,
+                              hipStream_t s) {
+  if (nv == 0) return hipSuccess;
+  k_depth_items<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(depth_key, n, nv, keys, items);
+  return hipGetLastError();
+}
+
+// counts in compositing order, and their scanned offsets back in item order
+__global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx, int64_t m,
+                             uint32_t* __restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) dst[k] = src[idx[k]];
+}
+
+__global__ void k_scatter_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx, int64_t m,
+                              uint32_t* __restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) dst[idx[k]] = src[k];
+}
+
+hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  k_gather_u32<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s>>>(src, idx, m, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  k_scatter_u32<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s>>>(src, idx, m, dst);
+  return hipGetLastError();
+}
+
+// Per-tile [start, end) ranges of the tile-sorted pair list.  `ranges` must be zeroed
+// beforehand (empty tiles keep (0, 0)).  With slot_gid, the sorted values are
+// emission slots and the Gaussian index of each sorted pair is gathered into sorted_gid.
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                              const uint32_t* __restrict__ slot_gid, int64_t n, uint2* __restrict__ ranges,
                               uint32_t* __restrict__ sorted_gid) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint32_t tile = (uint32_t)(keys[i] >> shift);
-  sorted_gid[i] = slot_gid[slots[i]];
-  if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != tile) ranges[tile].x = (uint32_t)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != tile) ranges[tile].y = (uint32_t)(i + 1);
+  const uint32_t tile = keys[i];
+  if (slot_gid) sorted_gid[i] = slot_gid[vals[i]];
+  if (i == 0 || keys[i - 1] != tile) ranges[tile].x = (uint32_t)i;
+  if (i == n - 1 || keys[i + 1] != tile) ranges[tile].y = (uint32_t)(i + 1);
 }
 
-hipError_t launch_tile_ranges(const uint64_t* keys, const uint32_t* slots, const uint32_t* slot_gid, int64_t n,
-                              int key_shift, uint2* ranges, uint32_t* sorted_gid, hipStream_t s) {
+hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const uint32_t* slot_gid, int64_t n,
+                              uint2* ranges, uint32_t* sorted_gid, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_tile_ranges<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(keys, slots, slot_gid, n, key_shift, ranges,
-                                                                         sorted_gid);
+  k_tile_ranges<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(keys, vals, slot_gid, n, ranges, sorted_gid);
   return hipGetLastError();
 }
 

@@ -230,50 +230,72 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       ProfScope ps(ST_BIN_COUNT, s);
       CG_HIP(launch_bin_count(n, n_views, dcams, cone, tiles, groups, counts, s));
     }
+    // compositing order of the (view, Gaussian) items, then pair offsets in that order
+    const int view_bits = bits_for(std::max(n_views - 1, 1));
+    uint64_t* dkeys = sc.get_n<uint64_t>(std::max<int64_t>(nv, 1));
+    uint64_t* dkeys_alt = sc.get_n<uint64_t>(std::max<int64_t>(nv, 1));
+    uint32_t* items = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
+    uint32_t* items_alt = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
+    uint32_t* counts_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
+    uint32_t* offs_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
+    void* dsort_tmp = sc.get(radix_temp_bytes(nv));
     uint32_t host_last[2] = {0, 0};
     if (nv > 0) {
+      int d_alt = 0;
+      {
+        ProfScope ps(ST_DEPTH_SORT, s);
+        CG_HIP(launch_depth_items(depth_key, n, nv, dkeys, items, s));
+        CG_HIP(launch_radix_sort(dkeys, items, dkeys_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
+      }
+      const uint32_t* sorted_items = d_alt ? items_alt : items;
       {
         ProfScope ps(ST_SCAN, s);
-        CG_HIP(launch_exclusive_scan(counts, offsets, nv, scan_tmp, s));
+        CG_HIP(launch_gather_u32(counts, sorted_items, nv, counts_sorted, s));
+        CG_HIP(launch_exclusive_scan(counts_sorted, offs_sorted, nv, scan_tmp, s));
+        CG_HIP(launch_scatter_u32(offs_sorted, sorted_items, nv, offsets, s));
       }
-      CG_HIP(hipMemcpyAsync(&host_last[0], offsets + (nv - 1), 4, hipMemcpyDeviceToHost, s));
-      CG_HIP(hipMemcpyAsync(&host_last[1], counts + (nv - 1), 4, hipMemcpyDeviceToHost, s));
+      CG_HIP(hipMemcpyAsync(&host_last[0], offs_sorted + (nv - 1), 4, hipMemcpyDeviceToHost, s));
+      CG_HIP(hipMemcpyAsync(&host_last[1], counts_sorted + (nv - 1), 4, hipMemcpyDeviceToHost, s));
     }
     CG_HIP(hipStreamSynchronize(s));
     const uint64_t P64 = (uint64_t)host_last[0] + host_last[1];
     CG_CHECK_ARG(P64 < 0xF0000000ull, "too many (tile, Gaussian) pairs for 32-bit indices");
     const int64_t P = (int64_t)P64;
 
-    uint64_t* keys = sc.get_n<uint64_t>(std::max<int64_t>(P, 1));
-    uint32_t* slots = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
-    uint64_t* keys_alt = sc.get_n<uint64_t>(std::max<int64_t>(P, 1));
-    uint32_t* slots_alt = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
-    uint32_t* slot_gid = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
-    uint32_t* sorted_gid = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    // pairs emitted in compositing order, then sorted stably by tile
+    uint32_t* keys = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint32_t* vals = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint32_t* keys_alt = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint32_t* vals_alt = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
+    uint32_t* slot_gid = st ? sc.get_n<uint32_t>(std::max<int64_t>(P, 1)) : nullptr;
+    uint32_t* sorted_gid_buf = st ? sc.get_n<uint32_t>(std::max<int64_t>(P, 1)) : nullptr;
     uint2* ranges = sc.get_n<uint2>(std::max<int64_t>(total_tiles, 1));
     void* sort_tmp = sc.get(radix_temp_bytes(P));
     float* final_T = st ? sc.get_n<float>(std::max<int64_t>(total_px, 1)) : nullptr;
     uint32_t* n_last = st ? sc.get_n<uint32_t>(std::max<int64_t>(total_px, 1)) : nullptr;
 
     const int tile_bits = bits_for(std::max<int64_t>(total_tiles - 1, 1));
-    const int end_bit = 31 + tile_bits;
     int in_alt = 0;
     if (P > 0) {
       {
         ProfScope ps(ST_BIN_EMIT, s);
-        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, tiles, groups, offsets, depth_key, keys, slots, slot_gid, s));
+        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, tiles, groups, offsets, keys, vals, slot_gid, s));
       }
       {
         ProfScope ps(ST_SORT, s);
-        CG_HIP(launch_radix_sort(keys, slots, keys_alt, slots_alt, P, end_bit, sort_tmp, &in_alt, s));
+        CG_HIP(launch_radix_sort32(keys, vals, keys_alt, vals_alt, P, tile_bits, sort_tmp, &in_alt, s));
       }
     }
-    uint64_t* skeys = in_alt ? keys_alt : keys;
-    uint32_t* sslots = in_alt ? slots_alt : slots;
+    uint32_t* skeys = in_alt ? keys_alt : keys;
+    uint32_t* svals = in_alt ? vals_alt : vals;
+    // inference: the sorted values are the Gaussian indices; training: emission slots
+    uint32_t* sorted_gid = st ? sorted_gid_buf : svals;
+    uint32_t* sslots = st ? svals : nullptr;
+    const int end_bit = tile_bits;
     {
       ProfScope ps(ST_RANGES, s);
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
-      CG_HIP(launch_tile_ranges(skeys, sslots, slot_gid, P, 31, ranges, sorted_gid, s));
+      CG_HIP(launch_tile_ranges(skeys, svals, slot_gid, P, ranges, st ? sorted_gid : nullptr, s));
     }
     unsigned long long* counters = nullptr;
     if (opts_in->count_pairs) {

@@ -43,19 +43,23 @@ struct TileCone {
   float sb, cb, cmax, pad;
 };
 
-// Per (view, Gaussian) record read by the render kernels (96 bytes, 16-byte aligned).
+// Per (view, Gaussian) record read by the render kernels (112 bytes, 16-byte aligned).
+// The first 16 bytes are the cull cone: a ray d can only reach alpha_min if
+// |d - u| <= lim, with u the unit direction from the camera centre to the mean (the
+// influence cone of the binning as a chord length; lim < 0: never, lim >= 2: always).
 struct alignas(16) Record {
-  float W[9];      // whitening diag(1/s') R^T, row-major
-  float mu[3];     // mean
-  float sigma;     // effective opacity sigma_eff (Eq. 10)
-  float rgb[3];    // view-dependent colour
-  float sp2[3];    // s'^2 (floored squared scales)
-  float rho2;      // floor variance (0 when the floor is off)
-  float Lg;        // 2 ln(sigma_eff / alpha_min): cull bound of the pre-rejection
-  float kg;        // 1 / min(s'^2)
+  float ux, uy, uz, lim;   // cull cone: direction to the mean, chord limit
+  float W[9];              // whitening diag(1/s') R^T, row-major
+  float mu[3];             // mean
+  float sigma;             // effective opacity sigma_eff (Eq. 10)
+  float rgb[3];            // view-dependent colour
+  float sp2[3];            // s'^2 (floored squared scales)
+  float rho2;              // floor variance (0 when the floor is off)
+  float Lg;                // 2 ln(sigma_eff / alpha_min): bound of the pre-rejection
+  float kg;                // 1 / min(s'^2)
   float pad[2];
 };
-static_assert(sizeof(Record) == 96, "Record layout");
+static_assert(sizeof(Record) == 112, "Record layout");
 
 struct Opts {
   int filter_mode, use_floor, composition;
@@ -95,10 +99,14 @@ hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_vi
 hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone,
                             const TileCone* tiles, const TileCone* groups, uint32_t* counts, hipStream_t s);
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const TileCone* tiles,
-                           const TileCone* groups, const uint32_t* offsets, const uint32_t* depth_key,
-                           uint64_t* keys, uint32_t* slots, uint32_t* slot_gid, hipStream_t s);
-hipError_t launch_tile_ranges(const uint64_t* keys, const uint32_t* slots, const uint32_t* slot_gid, int64_t n,
-                              int key_shift, uint2* ranges, uint32_t* sorted_gid, hipStream_t s);
+                           const TileCone* groups, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
+                           uint32_t* slot_gid, hipStream_t s);
+hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,
+                              hipStream_t s);
+hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
+hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const uint32_t* slot_gid, int64_t n,
+                              uint2* ranges, uint32_t* sorted_gid, hipStream_t s);
 
 // sort.hip
 size_t scan_temp_bytes(int64_t n);
@@ -108,6 +116,8 @@ size_t radix_temp_bytes(int64_t n);
 // (keys, vals) and 1 if it is in (keys_alt, vals_alt).
 hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
                              int end_bit, void* temp, int* result_in_alt, hipStream_t s);
+hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                               int end_bit, void* temp, int* result_in_alt, hipStream_t s);
 
 // render_fwd.hip
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
@@ -120,7 +130,7 @@ hipError_t launch_bake_rho2(const GaussPtrs& g, const DevCamera* cams, int n_vie
 
 // ---------------------------------------------------------------- profiling (pool.cpp)
 enum Stage {
-  ST_CAMERA = 0, ST_PREPROCESS, ST_BIN_COUNT, ST_SCAN, ST_BIN_EMIT, ST_SORT, ST_RANGES, ST_RENDER,
+  ST_CAMERA = 0, ST_PREPROCESS, ST_BIN_COUNT, ST_DEPTH_SORT, ST_SCAN, ST_BIN_EMIT, ST_SORT, ST_RANGES, ST_RENDER,
   ST_BWD_RENDER, ST_BWD_REDUCE, ST_BWD_PREPROCESS, ST_BAKE, ST_NUM
 };
 void prof_begin(int stage, hipStream_t s);

@@ -133,11 +133,16 @@ __device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, floa
 // Filtered response T of one pair.  FILTER 0: centre ray; 1: anisotropic (Eq. 9);
 // 2: isotropic in-plane covariance of the same trace.  MARGINAL: floor composition by
 // Eq. 12 (records with rho2 = 0 take the plain path).  Returns false when the pair
-// cannot reach alpha_min (T is then not set): t* <= t_near, or the pre-rejection
+// cannot reach alpha_min (T is then not set): the ray is outside the Gaussian's
+// influence cone, t* <= t_near, or the pre-rejection
 // D^2 > L (1 + tr Sigma_fp^u) with tr Sigma_fp^u <= t*^2 c_pix / s'_min^2, which
 // bounds q^T A^{-1} q from below (Sigma_render^u is dominated by Sigma_fp^u).
 template <int FILTER, bool MARGINAL>
 __device__ __forceinline__ bool pair_response(const Record& R, const PairPixel& p, const Opts& o, float& T) {
+  {  // influence cone of the Gaussian, tested at this pixel's centre ray
+    const float cx = p.a0 - R.ux, cy = p.a1 - R.uy, cz = p.a2 - R.uz;
+    if (cx * cx + cy * cy + cz * cz > R.lim * R.lim || R.lim < 0.f) return false;
+  }
   PairGeom g;
   if (!pair_geom(R, p, o.t_near, g)) return false;
   if (FILTER == 0) {

@@ -115,13 +115,18 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
 
   depth_key[out] = __float_as_uint(depth_key_f32(mu[0], mu[1], mu[2], c.of[0], c.of[1], c.of[2]));
 
-  // Influence cone.  If T >= alpha_min then (i) the perpendicular distance p of the
-  // mean from the ray satisfies p^2 <= L (s'_max^2 + t*^2 c) with L = 2 ln(sigma_eff /
-  // alpha_min) and c the pixel footprint coefficient (the filtered exponent is the
-  // ray's Mahalanobis distance to N(mu, Sigma_eff + footprint), whose marginal across
-  // the ray is bounded by s'_max^2 + t*^2 c), and (ii) t* <= |v| + p r / 2 with
-  // r = s'_max / s'_min.  Together they bound p by the root of a quadratic; the cone
-  // half-angle is asin(p / |v|).  Computed in FP64 with relative margins.
+  // Influence cone.  If T >= alpha_min then q^T A^{-1} q <= L = 2 ln(sigma_eff /
+  // alpha_min), and
+  //  (i) the max-response point x* = o + t* d lies within rho of the mean: |x* - mu| =
+  //      |W^{-1} q| <= s'_max |q| <= s'_max sqrt(L lambda_max(A)), with lambda_max(A) <=
+  //      1 + t*^2 c / s'_min^2 (c: the pixel footprint coefficient) and t* <= |v| + rho,
+  //      which closes to a quadratic in rho; rays from o that meet the ball B(mu, rho)
+  //      at positive t form the cone asin(rho / |v|) when |v| > rho;
+  // (ii) the perpendicular distance p of the mean from the ray obeys p^2 <= L (s'_max^2 +
+  //      t*^2 c): the filtered exponent is the ray's Mahalanobis distance to
+  //      N(mu, Sigma_eff + footprint), whose marginal across the ray has variance at
+  //      most s'_max^2 + t*^2 c.
+  // The half-angle is asin(min(p, rho) / |v|).  FP64 with relative margins.
   float gamma = -1.f;
   if (dist > 0.0 && sig_eff > o.alpha_min) {
     const double L = 2.0 * log((double)sig_eff / (double)o.alpha_min);
@@ -129,28 +134,35 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
     const double smax = sqrt((double)fmaxf(sp2[0], fmaxf(sp2[1], sp2[2])));
     const double smin = sqrt((double)sp2min);
     const double rr = smax / smin;
-    double cw = (double)view_cmax[v] * 1.01;
-    if (o.filter_mode == CG_FILTER_CENTER_RAY) cw = 0.0;
-    else if (o.filter_mode == CG_FILTER_ISOTROPIC) cw *= rr * rr * 0.5;
-    const double A2 = 1.0 - L * cw * rr * rr * 0.25;
-    if (A2 <= 1e-3) {
+    const double cw = o.filter_mode == CG_FILTER_CENTER_RAY ? 0.0 : (double)view_cmax[v] * 1.01;
+    // isotropic mode spreads the in-plane trace over both whitened directions
+    const double cw_perp = o.filter_mode == CG_FILTER_ISOTROPIC ? cw * rr * rr * 0.5 : cw;
+    const double a = L * smax * smax, k = cw / (smin * smin), ak = a * k;
+    if (ak >= 0.999) {
       gamma = kPiF;
     } else {
-      const double B2 = L * cw * dist * rr;
-      const double C2 = L * (smax * smax + cw * dist * dist);
-      const double p = (B2 + sqrt(B2 * B2 + 4.0 * A2 * C2)) / (2.0 * A2) * 1.001 + 1e-9;
-      if (dist + p * rr * 0.5 <= (double)o.t_near * 0.999) {
+      const double rho =
+          (ak * dist + sqrt(ak * dist * ak * dist + (1.0 - ak) * a * (1.0 + k * dist * dist))) / (1.0 - ak) * 1.001;
+      if (dist + rho <= (double)o.t_near * 0.999) {
         gamma = -1.f;  // every t* is at most t_near
-      } else if (p >= dist) {
+      } else if (dist <= rho) {
         gamma = kPiF;
       } else {
-        const double gm = asin(p / dist) * 1.0001 + 1e-6;
-        gamma = (dist * cos(gm) > p * rr * 0.5 - (double)o.t_near && gm < kPi) ? (float)gm : kPiF;
+        const double tmax = dist + rho;
+        const double p = sqrt(L * (smax * smax + tmax * tmax * cw_perp)) * 1.001;
+        const double gm = asin(fmin(p, rho) / dist) * 1.0001 + 1e-6;
+        gamma = gm < kPi ? (float)gm : kPiF;
       }
     }
   } else {
     r.Lg = 0.f;
   }
+  r.ux = vx;
+  r.uy = vy;
+  r.uz = vz;
+  if (gamma < 0.f) r.lim = -1.f;
+  else if (gamma >= kPiF) r.lim = 3.f;
+  else r.lim = 2.f * sinf(0.5f * gamma) + 1e-5f;
   rec[out] = r;
   cone[out] = make_float4(vx, vy, vz, gamma);
 }

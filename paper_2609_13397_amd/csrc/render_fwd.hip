@@ -1,14 +1,53 @@
-// Tile render: one 256-thread workgroup per 16x16 tile, one pixel per thread.  The
-// tile's depth-sorted list of Gaussians is walked in batches of 256 records staged
-// in LDS; every pixel evaluates the filtered closed-form response of Eq. 9 (with the
-// marginal floor composition of Eq. 12) and composites front to back (Eq. 4).  The
-// workgroup stops fetching batches once every pixel has terminated.
+// Tile render: one 256-thread workgroup per 16x16 tile, one pixel per thread, one 8x8
+// quadrant per wavefront.  The tile's depth-sorted list of Gaussians is walked in
+// batches of 256 records staged in LDS; each wavefront keeps the records whose
+// influence cone can reach its quadrant, and every pixel evaluates the filtered
+// closed-form response of Eq. 9 (with the marginal floor composition of Eq. 12) and
+// composites front to back (Eq. 4).  The workgroup stops fetching batches once every
+// pixel has terminated.
 #include "pair_math.hpp"
 
 namespace cg {
 
-// COUNT: also count, per pixel, the pairs walked through, those that needed the full
-// footprint arithmetic and those composited, and add them to counters[0..2].
+// Wave-level view of a tile: wave w renders the 8x8 quadrant (w % 2, w / 2) of the
+// 16x16 tile.  Its cone (axis = normalised mean of the quadrant's centre rays, chord
+// radius = largest chord from the axis to one of them) lets the wave drop, 64 records
+// at a time, every record whose influence cone cannot reach any of its pixels:
+// |a - u| > lim + radius implies |d - u| > lim for every ray d of the quadrant.
+struct WaveCone {
+  float ax, ay, az, rad;
+  bool live;
+};
+
+__device__ __forceinline__ WaveCone wave_cone(const PixelRay& r) {
+  float sx = r.valid ? r.df[0] : 0.f, sy = r.valid ? r.df[1] : 0.f, sz = r.valid ? r.df[2] : 0.f;
+  float cnt = r.valid ? 1.f : 0.f;
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+    sz += __shfl_xor(sz, o);
+    cnt += __shfl_xor(cnt, o);
+  }
+  WaveCone w;
+  w.live = cnt > 0.f;
+  const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
+  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+  w.ax = sx * inv;
+  w.ay = sy * inv;
+  w.az = sz * inv;
+  float ch = 0.f;
+  if (r.valid) {
+    const float dx = w.ax - r.df[0], dy = w.ay - r.df[1], dz = w.az - r.df[2];
+    ch = sqrtf(dx * dx + dy * dy + dz * dz);
+  }
+  for (int o = 32; o > 0; o >>= 1) ch = fmaxf(ch, __shfl_xor(ch, o));
+  w.rad = ch * 1.0001f + 2e-6f;
+  if (nrm < 0.5f * cnt) w.rad = 3.f;  // rays spread too widely for a mean axis
+  return w;
+}
+
+// COUNT: also count, per pixel, the pairs that reached the per-pixel tests, those that
+// needed the full footprint arithmetic and those composited, into counters[0..2].
 template <int FILTER, bool MARGINAL, bool COUNT>
 __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                 int per_xcd, Opts o, const Record* __restrict__ rec, int64_t n_gauss,
@@ -28,13 +67,15 @@ __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ ca
   const DevCamera& c = cams[v];
   const int lt = t - c.tile_offset;
   const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
-  const int i = tx * kTile + (threadIdx.x & (kTile - 1));
-  const int j = ty * kTile + (threadIdx.x / kTile);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int j = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
   const bool inside = i < c.crop_w && j < c.crop_h;
   PixelRay r;
   r.valid = false;
   if (inside) r = pixel_ray(c, i, j, o.fs);
   const PairPixel px = make_pair_pixel(r, c);
+  const WaveCone wc = wave_cone(r);
 
   const uint2 rg = ranges[t];
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -47,29 +88,47 @@ __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ ca
     if (idx < rg.y) srec[threadIdx.x] = vrec[sorted_gid[idx]];
     __syncthreads();
     const int cnt = (int)min(256u, rg.y - base);
-    if (!done) {
-      int k = 0;
-      for (; k < cnt; ++k) {
-        float T;
-        if (COUNT) ++c_eval;
-        if (!pair_response<FILTER, MARGINAL>(srec[k], px, o, T)) continue;
-        if (COUNT) ++c_full;
-        const float alpha = fminf(T, o.alpha_max);
-        if (alpha < o.alpha_min) continue;
-        const float test = Ttr * (1.f - alpha);
-        if (test < o.T_min) {
-          done = true;
-          break;
+    if (wc.live && __ballot(!done) != 0) {
+      for (int sub = 0; sub < cnt; sub += 64) {
+        bool rel = false;
+        if (sub + lane < cnt) {
+          const Record& R = srec[sub + lane];
+          const float dx = wc.ax - R.ux, dy = wc.ay - R.uy, dz = wc.az - R.uz;
+          const float lim = R.lim + wc.rad;
+          rel = R.lim >= 0.f && dx * dx + dy * dy + dz * dz <= lim * lim;
         }
-        if (COUNT) ++c_contrib;
-        const float w = Ttr * alpha;
-        C0 = fmaf(w, srec[k].rgb[0], C0);
-        C1 = fmaf(w, srec[k].rgb[1], C1);
-        C2 = fmaf(w, srec[k].rgb[2], C2);
-        Ttr = test;
+        uint64_t m = __ballot(rel);
+        while (m) {
+          const int k = sub + (int)__builtin_ctzll(m);
+          m &= m - 1;
+          if (!done) {
+            float T;
+            if (COUNT) ++c_eval;
+            if (pair_response<FILTER, MARGINAL>(srec[k], px, o, T)) {
+              if (COUNT) ++c_full;
+              const float alpha = fminf(T, o.alpha_max);
+              if (alpha >= o.alpha_min) {
+                const float test = Ttr * (1.f - alpha);
+                if (test < o.T_min) {
+                  done = true;
+                  last = base + (uint32_t)k;
+                } else {
+                  if (COUNT) ++c_contrib;
+                  const float w = Ttr * alpha;
+                  C0 = fmaf(w, srec[k].rgb[0], C0);
+                  C1 = fmaf(w, srec[k].rgb[1], C1);
+                  C2 = fmaf(w, srec[k].rgb[2], C2);
+                  Ttr = test;
+                }
+              }
+            }
+          }
+          if (__ballot(!done) == 0) break;
+        }
+        if (__ballot(!done) == 0) break;
       }
-      last = base + (uint32_t)k;
     }
+    if (!done) last = base + (uint32_t)cnt;
     __syncthreads();
   }
   if (inside) {
@@ -81,7 +140,7 @@ __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ ca
     out.w = 1.f - Ttr;
     reinterpret_cast<float4*>(out_rgba)[p] = out;
     if (final_T) final_T[p] = Ttr;
-    if (n_last) n_last[p] = last;
+    if (n_last) n_last[p] = r.valid ? last : rg.x;
   }
   if (COUNT) {
     if (threadIdx.x < 3) scount[threadIdx.x] = 0;

@@ -128,9 +128,9 @@ void Scratch::release() {
 
 namespace {
 
-const char* kStageNames[ST_NUM] = {"camera",    "preprocess",   "bin_count",       "scan",
-                                   "bin_emit",  "sort",         "tile_ranges",     "render",
-                                   "bwd_render", "bwd_reduce", "bwd_preprocess", "bake_rho2"};
+const char* kStageNames[ST_NUM] = {"camera",     "preprocess", "bin_count",      "depth_sort", "scan",
+                                   "bin_emit",   "sort",       "tile_ranges",    "render",     "bwd_render",
+                                   "bwd_reduce", "bwd_preprocess", "bake_rho2"};
 
 struct Pending {
   int stage;

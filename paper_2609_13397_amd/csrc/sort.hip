@@ -105,7 +105,8 @@ constexpr int kSortRounds = 16;                                 // rounds of 64 
 constexpr int kSortTile = kSortBlock * kSortRounds;             // 4096 items per block
 constexpr int kWaveItems = 64 * kSortRounds;                    // 1024 items per wave
 
-__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+template <class K>
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t n, int shift,
                                                            uint32_t* __restrict__ hist, int nblocks) {
   __shared__ uint32_t cnt[kRadix];
   cnt[threadIdx.x] = 0;
@@ -119,9 +120,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint64_t* __res
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint64_t* __restrict__ kin,
+template <class K>
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ kin,
                                                               const uint32_t* __restrict__ vin,
-                                                              uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                               int64_t n, int shift,
                                                               const uint32_t* __restrict__ offsets, int nblocks) {
   __shared__ uint32_t wcnt[4][kRadix];
@@ -132,14 +134,14 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint64_t* __
   __syncthreads();
   const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * kWaveItems;
   const uint64_t lt = __lanemask_lt();
-  uint64_t key[kSortRounds];
+  K key[kSortRounds];
   uint32_t val[kSortRounds];
   uint32_t rank[kSortRounds];
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t idx = wbase + (int64_t)r * 64 + lane;
     const bool ok = idx < n;
-    key[r] = ok ? kin[idx] : 0ull;
+    key[r] = ok ? kin[idx] : K(0);
     val[r] = ok ? vin[idx] : 0u;
     const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
     uint64_t peers = __ballot(ok);
@@ -182,8 +184,9 @@ size_t radix_temp_bytes(int64_t n) {
   return (size_t)m * sizeof(uint32_t) * 2 + scan_temp_bytes(m) + 256;
 }
 
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                             int end_bit, void* temp, int* result_in_alt, hipStream_t s) {
+template <class K>
+static hipError_t radix_sort_t(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, int64_t n, int end_bit,
+                               void* temp, int* result_in_alt, hipStream_t s) {
   *result_in_alt = 0;
   if (n <= 1) return hipSuccess;
   const int nblocks = (int)ceil_div(n, kSortTile);
@@ -191,26 +194,36 @@ hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
   uint32_t* hist = static_cast<uint32_t*>(temp);
   uint32_t* offs = hist + m;
   void* stemp = offs + m;
-  uint64_t* kin = keys;
+  K* kin = keys;
   uint32_t* vin = vals;
-  uint64_t* kout = keys_alt;
+  K* kout = keys_alt;
   uint32_t* vout = vals_alt;
   int alt = 0;
   for (int shift = 0; shift < end_bit; shift += kRadixBits) {
-    k_radix_hist<<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, n, shift, hist, nblocks);
+    k_radix_hist<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, n, shift, hist, nblocks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_exclusive_scan(hist, offs, m, stemp, s);
     if (e != hipSuccess) return e;
-    k_radix_scatter<<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, vin, kout, vout, n, shift, offs, nblocks);
+    k_radix_scatter<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, vin, kout, vout, n, shift, offs, nblocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    uint64_t* tk = kin; kin = kout; kout = tk;
+    K* tk = kin; kin = kout; kout = tk;
     uint32_t* tv = vin; vin = vout; vout = tv;
     alt ^= 1;
   }
   *result_in_alt = alt;
   return hipSuccess;
+}
+
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                             int end_bit, void* temp, int* result_in_alt, hipStream_t s) {
+  return radix_sort_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, end_bit, temp, result_in_alt, s);
+}
+
+hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                               int end_bit, void* temp, int* result_in_alt, hipStream_t s) {
+  return radix_sort_t<uint32_t>(keys, vals, keys_alt, vals_alt, n, end_bit, temp, result_in_alt, s);
 }
 
 }  // namespace cg

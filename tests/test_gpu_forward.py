@@ -217,3 +217,22 @@ def test_pinhole_config_eighth_resolution_parity():
     _say(f"   pairs {info['n_pairs']}")
     for img, c in zip(imgs, cams):
         check_view(img, scene, c, oopts, mode="culled")
+
+
+def test_contributing_pair_count_matches_oracle():
+    """The counting render variant counts composited pairs exactly as the oracle does
+    (pixels with a near-threshold decision may differ by their own pair counts)."""
+    torch, R = _gpu()
+    scene, cam = synth.tiny_config()
+    _say("pair counts")
+    sc = R.Scene.from_numpy(scene)
+    rgba, info, _ = R.render_forward(sc, [cam], R.RenderOpts(count_pairs=True))
+    plain, _, _ = R.render_forward(sc, [cam], R.RenderOpts())
+    torch.cuda.synchronize()
+    assert torch.equal(rgba, plain)  # the counting variant renders identically
+    ref = O.render(scene, cam, O.Opts(), with_alt=True)
+    amb = ref["n_dec"] > 0
+    slack = int(ref["n_contrib"][amb].sum()) + int(amb.sum())
+    _say(f"   gpu {info['n_contrib']} oracle {int(ref['n_contrib'].sum())} slack {slack}")
+    assert abs(info["n_contrib"] - int(ref["n_contrib"].sum())) <= slack
+    assert info["n_evaluated"] >= info["n_full"] >= info["n_contrib"] > 0
