@@ -177,6 +177,11 @@ cg_status cg_render_backward(cg_fwd_state* st, const float* grad_rgba, float* d_
 
 void cg_fwd_state_release(cg_fwd_state* st);
 
+/* Diagnostic of the last cg_render_backward on `st`: the number of pixels whose
+ * replayed front-to-back walk did not end at the transmittance the forward stored
+ * (0 when the replay is exact); -1 before any backward call. */
+int64_t cg_bwd_replay_mismatches(const cg_fwd_state* st);
+
 /* Inverse mapping Pi^{-1} (Sec. 3) of n continuous full-image pixel coordinates.
  *   pix_xy [2][n] device; dirs [3][n] unit world directions (0 where invalid);
  *   valid [n] 1/0. */

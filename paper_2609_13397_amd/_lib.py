@@ -70,6 +70,7 @@ SIGNATURES = {
     "cg_render_forward": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cg_render_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cg_fwd_state_release": (None, [_vp]),
+    "cg_bwd_replay_mismatches": (C.c_int64, [_vp]),
     "cg_camera_unproject": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp]),
     "cg_bake_rho2": (C.c_int, [_vp, _vp, C.c_int32, C.c_float, _vp, _vp]),
     "cg_profile_num_stages": (C.c_int, []),

@@ -15,6 +15,9 @@ LIB = os.path.join(HERE, "libconegauss.so")
 ARCH = os.environ.get("CG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
+          # contract a*b+c only within one source expression, so that the forward render and
+          # the backward replay (same expressions, different kernels) round identically
+          "-ffp-contract=on",
           "-Wall", "-Wno-unused-function",
           # no packed-FP32 instructions in device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

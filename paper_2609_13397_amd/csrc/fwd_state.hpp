@@ -24,6 +24,7 @@ struct cg_fwd_state {
   cg_allocator alloc{nullptr, nullptr, nullptr};
   hipStream_t stream = nullptr;
   std::vector<void*> blocks;          // scratch owned by the state
+  int64_t replay_mismatches = -1;     // set by the backward pass
 };
 
 namespace cg {

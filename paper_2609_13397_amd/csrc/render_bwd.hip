@@ -1,11 +1,433 @@
-// Backward pass (placeholder until the kernels land).
+// Backward pass.
+//
+// 1. Tile backward (k_render_bwd): the same tiles, wave quadrants and batches as the
+//    forward.  Each pixel replays the forward front to back, so transmittance is
+//    recomputed, never divided.  For a composited pair k with colour c_k, alpha_k and
+//    transmittance T_k in front of it,
+//      dL/dalpha_k = sum_ch G_ch (c_k T_k - (S_k + T_fin bg) / (1 - alpha_k)) + G_a T_fin / (1 - alpha_k),
+//      dL/dc_k     = G alpha_k T_k,
+//    where S_k = C_fin - C_{<=k} is the colour composited behind k (C_fin from the
+//    forward output).  dL/dT_k = dL/dalpha_k below the alpha_max clamp.  The record
+//    gradient of each pair (pair_grad) is summed over the quadrant's pixels with wave
+//    shuffles and over the four quadrants through LDS, and written, without atomics,
+//    to the pair's emission slot.
+// 2. Per (view, Gaussian) sum of its pairs' partial gradients (contiguous slots).
+// 3. Preprocess backward to the raw parameters, summing views in a fixed order.
+#include <algorithm>
+
 #include "fwd_state.hpp"
+#include "pair_math.hpp"
+
+namespace cg {
+
+constexpr int kGradLen = 20;  // dW[9] dmu[3] dsigma dsp2[3] drgb[3] pad
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+struct WaveConeB {
+  float ax, ay, az, rad;
+  bool live;
+};
+
+__device__ __forceinline__ WaveConeB wave_cone_b(const PixelRay& r) {
+  float sx = r.valid ? r.df[0] : 0.f, sy = r.valid ? r.df[1] : 0.f, sz = r.valid ? r.df[2] : 0.f;
+  float cnt = r.valid ? 1.f : 0.f;
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+    sz += __shfl_xor(sz, o);
+    cnt += __shfl_xor(cnt, o);
+  }
+  WaveConeB w;
+  w.live = cnt > 0.f;
+  const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
+  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+  w.ax = sx * inv;
+  w.ay = sy * inv;
+  w.az = sz * inv;
+  float ch = 0.f;
+  if (r.valid) {
+    const float dx = w.ax - r.df[0], dy = w.ay - r.df[1], dz = w.az - r.df[2];
+    ch = sqrtf(dx * dx + dy * dy + dz * dz);
+  }
+  for (int o = 32; o > 0; o >>= 1) ch = fmaxf(ch, __shfl_xor(ch, o));
+  w.rad = ch * 1.0001f + 2e-6f;
+  if (nrm < 0.5f * cnt) w.rad = 3.f;
+  return w;
+}
+
+template <int FILTER, bool MARGINAL>
+__global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
+                                                    int per_xcd, Opts o, const Record* __restrict__ rec,
+                                                    int64_t n_gauss, const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ sorted_gid,
+                                                    const uint32_t* __restrict__ sorted_slots,
+                                                    const float* __restrict__ out_rgba,
+                                                    const float* __restrict__ final_T,
+                                                    const float* __restrict__ grad_rgba, float* __restrict__ partial,
+                                                    unsigned int* __restrict__ mismatch) {
+  __shared__ Record srec[64];
+  __shared__ float gacc[4][64][kGradLen + 1];
+  const int b = blockIdx.x;
+  const int t = (b & 7) * per_xcd + (b >> 3);
+  if (t >= total_tiles) return;
+  const int v = view_of_tile(cams, n_views, t);
+  const DevCamera& c = cams[v];
+  const int lt = t - c.tile_offset;
+  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int j = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = i < c.crop_w && j < c.crop_h;
+  PixelRay r;
+  r.valid = false;
+  if (inside) r = pixel_ray(c, i, j, o.fs);
+  const PairPixel px = make_pair_pixel(r, c);
+  const WaveConeB wc = wave_cone_b(r);
+
+  // upstream gradient and forward result of this pixel
+  float G0 = 0.f, G1 = 0.f, G2 = 0.f, Ga = 0.f, Tfin = 1.f, Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f;
+  int64_t p = 0;
+  if (inside) {
+    p = c.px_offset + (int64_t)j * c.crop_w + i;
+    const float4 gr = reinterpret_cast<const float4*>(grad_rgba)[p];
+    const float4 fo = reinterpret_cast<const float4*>(out_rgba)[p];
+    G0 = gr.x; G1 = gr.y; G2 = gr.z; Ga = gr.w;
+    Tfin = final_T[p];
+    Cf0 = fo.x - Tfin * o.bg[0];
+    Cf1 = fo.y - Tfin * o.bg[1];
+    Cf2 = fo.z - Tfin * o.bg[2];
+  }
+  const float back0 = Tfin * o.bg[0], back1 = Tfin * o.bg[1], back2 = Tfin * o.bg[2];
+
+  const uint2 rg = ranges[t];
+  float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !r.valid;
+  const Record* vrec = rec + (int64_t)v * n_gauss;
+  uint32_t stop_at = rg.y;
+  for (uint32_t base = rg.x; base < rg.y; base += 64) {
+    if (__syncthreads_count(!done) == 0) {
+      stop_at = base;
+      break;
+    }
+    const int cnt = (int)min(64u, rg.y - base);
+    if (threadIdx.x < 64 && (int)threadIdx.x < cnt) srec[threadIdx.x] = vrec[sorted_gid[base + threadIdx.x]];
+    for (int k = lane; k < 64 * (kGradLen + 1); k += 64) (&gacc[wave][0][0])[k] = 0.f;
+    __syncthreads();
+    if (wc.live && __ballot(!done) != 0) {
+      bool rel = false;
+      if (lane < cnt) {
+        const Record& R = srec[lane];
+        const float dx = wc.ax - R.ux, dy = wc.ay - R.uy, dz = wc.az - R.uz;
+        const float lim = R.lim + wc.rad;
+        rel = R.lim >= 0.f && dx * dx + dy * dy + dz * dz <= lim * lim;
+      }
+      uint64_t m = __ballot(rel);
+      while (m) {
+        const int k = (int)__builtin_ctzll(m);
+        m &= m - 1;
+        float gv[kGradLen];
+#pragma unroll
+        for (int q = 0; q < kGradLen; ++q) gv[q] = 0.f;
+        bool contrib = false;
+        if (!done) {
+          const Record& R = srec[k];
+          float T;
+          if (pair_response<FILTER, MARGINAL>(R, px, o, T)) {
+            const float alpha = fminf(T, o.alpha_max);
+            if (alpha >= o.alpha_min) {
+              const float test = Ttr * (1.f - alpha);
+              if (test < o.T_min) {
+                done = true;
+              } else {
+                contrib = true;
+                const float w = Ttr * alpha;
+                C0 = fmaf(w, R.rgb[0], C0);
+                C1 = fmaf(w, R.rgb[1], C1);
+                C2 = fmaf(w, R.rgb[2], C2);
+                const float inv1 = 1.f / (1.f - alpha);
+                // colour behind this pair (excluding the background term)
+                const float S0 = Cf0 - C0, S1 = Cf1 - C1, S2 = Cf2 - C2;
+                float dalpha = Ga * Tfin * inv1;
+                dalpha += G0 * (R.rgb[0] * Ttr - (S0 + back0) * inv1);
+                dalpha += G1 * (R.rgb[1] * Ttr - (S1 + back1) * inv1);
+                dalpha += G2 * (R.rgb[2] * Ttr - (S2 + back2) * inv1);
+                gv[16] = G0 * w;
+                gv[17] = G1 * w;
+                gv[18] = G2 * w;
+                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL>(R, px, o, dalpha, T, gv);
+                Ttr = test;
+              }
+            }
+          }
+        }
+        if (__ballot(contrib) != 0) {
+#pragma unroll
+          for (int q = 0; q < kGradLen - 1; ++q) {
+            const float s = wave_sum(gv[q]);
+            if (lane == 0) gacc[wave][k][q] = s;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // sum the four quadrants and write each pair's partial gradient to its slot
+    for (int e = threadIdx.x; e < cnt * kGradLen; e += 256) {
+      const int k = e / kGradLen, q = e % kGradLen;
+      const float s = gacc[0][k][q] + gacc[1][k][q] + gacc[2][k][q] + gacc[3][k][q];
+      partial[(int64_t)sorted_slots[base + k] * kGradLen + q] = s;
+    }
+  }
+  // pairs after the point where every pixel of the tile had terminated get no gradient
+  for (int64_t e = threadIdx.x; e < (int64_t)(rg.y - stop_at) * kGradLen; e += 256)
+    partial[(int64_t)sorted_slots[stop_at + e / kGradLen] * kGradLen + e % kGradLen] = 0.f;
+  // pixels that ran to the end of their list must have reached the stored transmittance
+  if (r.valid && !done && Ttr != Tfin) atomicAdd(mismatch, 1u);
+}
+
+// Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt).
+__global__ void k_reduce_items(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets, int64_t nv,
+                               const float* __restrict__ partial, float* __restrict__ item_grad) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nv) return;
+  float acc[kGradLen];
+#pragma unroll
+  for (int q = 0; q < kGradLen; ++q) acc[q] = 0.f;
+  const uint32_t cnt = counts[it], off = offsets[it];
+  for (uint32_t s = 0; s < cnt; ++s) {
+    const float4* row = reinterpret_cast<const float4*>(partial + (int64_t)(off + s) * kGradLen);
+#pragma unroll
+    for (int q4 = 0; q4 < kGradLen / 4; ++q4) {
+      const float4 x = row[q4];
+      acc[4 * q4 + 0] += x.x;
+      acc[4 * q4 + 1] += x.y;
+      acc[4 * q4 + 2] += x.z;
+      acc[4 * q4 + 3] += x.w;
+    }
+  }
+  float4* out = reinterpret_cast<float4*>(item_grad + it * kGradLen);
+#pragma unroll
+  for (int q4 = 0; q4 < kGradLen / 4; ++q4)
+    out[q4] = make_float4(acc[4 * q4], acc[4 * q4 + 1], acc[4 * q4 + 2], acc[4 * q4 + 3]);
+}
+
+// Gradient of the degree-3 real SH basis (the polynomials of sh_basis3 in
+// preprocess.hip) with respect to the unnormalised direction components.
+__device__ __forceinline__ void sh_basis3_grad(float x, float y, float z, float Y[16], float dYx[16], float dYy[16],
+                                               float dYz[16]) {
+  constexpr float c0 = 0.28209479177387814f, c1 = 0.4886025119029199f, c2a = 1.0925484305920792f,
+                  c2b = 0.31539156525252005f, c2c = 0.5462742152960396f, c3a = 0.5900435899266435f,
+                  c3b = 2.890611442640554f, c3c = 0.4570457994644658f, c3d = 0.3731763325901154f,
+                  c3e = 1.445305721320277f;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = c0;                        dYx[0] = 0.f;                 dYy[0] = 0.f;                  dYz[0] = 0.f;
+  Y[1] = -c1 * y;                   dYx[1] = 0.f;                 dYy[1] = -c1;                  dYz[1] = 0.f;
+  Y[2] = c1 * z;                    dYx[2] = 0.f;                 dYy[2] = 0.f;                  dYz[2] = c1;
+  Y[3] = -c1 * x;                   dYx[3] = -c1;                 dYy[3] = 0.f;                  dYz[3] = 0.f;
+  Y[4] = c2a * x * y;               dYx[4] = c2a * y;             dYy[4] = c2a * x;              dYz[4] = 0.f;
+  Y[5] = -c2a * y * z;              dYx[5] = 0.f;                 dYy[5] = -c2a * z;             dYz[5] = -c2a * y;
+  Y[6] = c2b * (3.f * zz - 1.f);    dYx[6] = 0.f;                 dYy[6] = 0.f;                  dYz[6] = 6.f * c2b * z;
+  Y[7] = -c2a * x * z;              dYx[7] = -c2a * z;            dYy[7] = 0.f;                  dYz[7] = -c2a * x;
+  Y[8] = c2c * (xx - yy);           dYx[8] = 2.f * c2c * x;       dYy[8] = -2.f * c2c * y;       dYz[8] = 0.f;
+  Y[9] = -c3a * y * (3.f * xx - yy);  dYx[9] = -6.f * c3a * x * y;  dYy[9] = -c3a * (3.f * xx - 3.f * yy); dYz[9] = 0.f;
+  Y[10] = c3b * x * y * z;          dYx[10] = c3b * y * z;        dYy[10] = c3b * x * z;         dYz[10] = c3b * x * y;
+  Y[11] = -c3c * y * (5.f * zz - 1.f);  dYx[11] = 0.f;  dYy[11] = -c3c * (5.f * zz - 1.f);  dYz[11] = -10.f * c3c * y * z;
+  Y[12] = c3d * z * (5.f * zz - 3.f);   dYx[12] = 0.f;  dYy[12] = 0.f;  dYz[12] = c3d * (15.f * zz - 3.f);
+  Y[13] = -c3c * x * (5.f * zz - 1.f);  dYx[13] = -c3c * (5.f * zz - 1.f);  dYy[13] = 0.f;  dYz[13] = -10.f * c3c * x * z;
+  Y[14] = c3e * z * (xx - yy);      dYx[14] = 2.f * c3e * x * z;  dYy[14] = -2.f * c3e * y * z;  dYz[14] = c3e * (xx - yy);
+  Y[15] = -c3a * x * (xx - 3.f * yy);  dYx[15] = -c3a * (3.f * xx - 3.f * yy);  dYy[15] = 6.f * c3a * x * y;  dYz[15] = 0.f;
+}
+
+// Preprocess backward: per Gaussian, the per-view record gradients back to the raw
+// parameters (activations of Sec. 3, the floor of Eq. 10, the colour).  Views are
+// summed in index order; outputs are overwritten.
+__global__ void k_preprocess_bwd(GaussPtrs g, const DevCamera* __restrict__ cams, int n_views, Opts o,
+                                 const float* __restrict__ item_grad, float* __restrict__ d_means,
+                                 float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+                                 float* __restrict__ d_logits, float* __restrict__ d_color) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = g.n;
+  if (i >= n) return;
+  const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+  const float q[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
+  const float qnorm = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float qn = 1.f / qnorm;
+  const float w = q[0] * qn, x = q[1] * qn, y = q[2] * qn, z = q[3] * qn;
+  const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                      2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                      2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+  const float sigma = 1.f / (1.f + expf(-g.logits[i]));
+  const float rho2 = (o.use_floor && g.rho2) ? g.rho2[i] : 0.f;
+  float s[3], sp[3], sp2[3];
+  float ratio = 1.f;
+  for (int k = 0; k < 3; ++k) {
+    s[k] = expf(g.log_scales[k * n + i]);
+    if (rho2 > 0.f) {
+      sp2[k] = s[k] * s[k] + rho2;
+      sp[k] = sqrtf(sp2[k]);
+      ratio *= s[k] / sp[k];
+    } else {
+      sp[k] = s[k];
+      sp2[k] = s[k] * s[k];
+    }
+  }
+  float dmu[3] = {0.f, 0.f, 0.f}, dR[9], dsp2[3] = {0.f, 0.f, 0.f}, dsig_eff = 0.f;
+  for (int k = 0; k < 9; ++k) dR[k] = 0.f;
+  const int ncol = g.color_mode == 0 ? 3 : 48;
+  float dcol[48];
+  for (int k = 0; k < 48; ++k) dcol[k] = 0.f;
+  for (int v = 0; v < n_views; ++v) {
+    const float* gr = item_grad + ((int64_t)v * n + i) * kGradLen;
+    // W[a][b] = R[b][a] / s'_a
+    for (int a = 0; a < 3; ++a) {
+      float acc = 0.f;
+      for (int b2 = 0; b2 < 3; ++b2) {
+        dR[3 * b2 + a] += gr[3 * a + b2] / sp[a];
+        acc += gr[3 * a + b2] * R[3 * b2 + a];
+      }
+      // d s'_a = -acc / s'_a^2  ->  d s'^2_a = d s'_a / (2 s'_a)
+      dsp2[a] += -acc / (sp[a] * sp[a]) / (2.f * sp[a]);
+    }
+    dmu[0] += gr[9];
+    dmu[1] += gr[10];
+    dmu[2] += gr[11];
+    dsig_eff += gr[12];
+    dsp2[0] += gr[13];
+    dsp2[1] += gr[14];
+    dsp2[2] += gr[15];
+    const float drgb[3] = {gr[16], gr[17], gr[18]};
+    if (g.color_mode == 0) {
+      for (int ch = 0; ch < 3; ++ch) dcol[ch] += drgb[ch];
+    } else {
+      const DevCamera& c = cams[v];
+      const double vd[3] = {(double)mu[0] - c.o[0], (double)mu[1] - c.o[1], (double)mu[2] - c.o[2]};
+      const double dist = sqrt(vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]);
+      const float ux = (float)(vd[0] / dist), uy = (float)(vd[1] / dist), uz = (float)(vd[2] / dist);
+      float Y[16], dYx[16], dYy[16], dYz[16];
+      sh_basis3_grad(ux, uy, uz, Y, dYx, dYy, dYz);
+      float du[3] = {0.f, 0.f, 0.f};
+      for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.f;
+        for (int k = 0; k < 16; ++k) acc += g.color[(3 * k + ch) * n + i] * Y[k];
+        if (acc + 0.5f <= 0.f) continue;  // clamped channel
+        for (int k = 0; k < 16; ++k) {
+          const float cf = g.color[(3 * k + ch) * n + i];
+          dcol[3 * k + ch] += drgb[ch] * Y[k];
+          du[0] += drgb[ch] * cf * dYx[k];
+          du[1] += drgb[ch] * cf * dYy[k];
+          du[2] += drgb[ch] * cf * dYz[k];
+        }
+      }
+      // u = v / |v|
+      const float ud = du[0] * ux + du[1] * uy + du[2] * uz;
+      const float idist = (float)(1.0 / dist);
+      dmu[0] += (du[0] - ud * ux) * idist;
+      dmu[1] += (du[1] - ud * uy) * idist;
+      dmu[2] += (du[2] - ud * uz) * idist;
+    }
+  }
+  // sigma_eff = sigma * prod s / s'
+  const float dsig = dsig_eff * ratio;
+  const float dratio = dsig_eff * sigma;
+  for (int k = 0; k < 3; ++k) {
+    // s'^2 = s^2 + rho2; ratio depends on s_k through s_k / sqrt(s_k^2 + rho2)
+    float ds = dsp2[k] * 2.f * s[k];
+    if (rho2 > 0.f) ds += dratio * ratio * (1.f / s[k] - s[k] / sp2[k]);
+    d_log_scales[k * n + i] = ds * s[k];
+  }
+  d_logits[i] = dsig * sigma * (1.f - sigma);
+  for (int k = 0; k < 3; ++k) d_means[k * n + i] = dmu[k];
+  // R(q_hat) -> q_hat -> q
+  const float dw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  const float dx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                          2.f * x * dR[8]);
+  const float dy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                          2.f * y * dR[8]);
+  const float dz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] +
+                          x * dR[6] + y * dR[7]);
+  const float dot = dw * w + dx * x + dy * y + dz * z;
+  d_quats[i] = (dw - dot * w) * qn;
+  d_quats[n + i] = (dx - dot * x) * qn;
+  d_quats[2 * n + i] = (dy - dot * y) * qn;
+  d_quats[3 * n + i] = (dz - dot * z) * qn;
+  for (int k = 0; k < ncol; ++k) d_color[(int64_t)k * n + i] = dcol[k];
+}
+
+template <int FILTER, bool MARGINAL>
+static void launch_bwd_t(const cg_fwd_state* st, const float* grad_rgba, float* partial, unsigned int* mismatch,
+                         hipStream_t s) {
+  const int per_xcd = (int)((st->total_tiles + 7) / 8);
+  k_render_bwd<FILTER, MARGINAL><<<dim3(per_xcd * 8), dim3(256), 0, s>>>(
+      st->dcams, st->n_views, (int)st->total_tiles, per_xcd, st->opts, st->rec, st->g.n, st->ranges, st->sorted_gid,
+      st->sorted_slots, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
+}
+
+void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, float* d_log_scales, float* d_quats,
+                  float* d_opacity, float* d_color, hipStream_t s) {
+  CG_CHECK_ARG(st, "null forward state");
+  CG_CHECK_ARG(st->sorted_slots || st->P == 0, "state was not created for a backward pass");
+  const int64_t n = st->g.n;
+  if (n == 0) return;
+  CG_CHECK_ARG(d_means && d_log_scales && d_quats && d_opacity && d_color, "null gradient output");
+  CG_CHECK_ARG(grad_rgba || st->total_px == 0, "null grad_rgba");
+  const int64_t nv = n * st->n_views;
+  Scratch sc(&st->alloc, s);
+  float* partial = sc.get_n<float>((size_t)std::max<int64_t>(st->P, 1) * kGradLen);
+  float* item_grad = sc.get_n<float>((size_t)nv * kGradLen);
+  unsigned int* mismatch = sc.get_n<unsigned int>(4);
+  CG_HIP(launch_fill_u32(mismatch, 0u, 1, s));
+  if (st->P > 0) {
+    ProfScope ps(ST_BWD_RENDER, s);
+    const Opts& o = st->opts;
+    const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
+    switch (o.filter_mode) {
+      case CG_FILTER_CENTER_RAY: launch_bwd_t<0, false>(st, grad_rgba, partial, mismatch, s); break;
+      case CG_FILTER_ISOTROPIC:
+        if (marginal) launch_bwd_t<2, true>(st, grad_rgba, partial, mismatch, s);
+        else launch_bwd_t<2, false>(st, grad_rgba, partial, mismatch, s);
+        break;
+      default:
+        if (marginal) launch_bwd_t<1, true>(st, grad_rgba, partial, mismatch, s);
+        else launch_bwd_t<1, false>(st, grad_rgba, partial, mismatch, s);
+    }
+    CG_HIP(hipGetLastError());
+  }
+  {
+    ProfScope ps(ST_BWD_REDUCE, s);
+    k_reduce_items<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(st->counts, st->offsets, nv, partial,
+                                                                          item_grad);
+    CG_HIP(hipGetLastError());
+  }
+  {
+    ProfScope ps(ST_BWD_PREPROCESS, s);
+    k_preprocess_bwd<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
+        st->g, st->dcams, st->n_views, st->opts, item_grad, d_means, d_log_scales, d_quats, d_opacity, d_color);
+    CG_HIP(hipGetLastError());
+  }
+  unsigned int host_mismatch = 0;
+  CG_HIP(hipMemcpyAsync(&host_mismatch, mismatch, 4, hipMemcpyDeviceToHost, s));
+  CG_HIP(hipStreamSynchronize(s));
+  st->replay_mismatches = host_mismatch;
+}
+
+}  // namespace cg
 
 extern "C" cg_status cg_render_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means,
                                         float* d_log_scales, float* d_quats, float* d_opacity_logits, float* d_color,
                                         hipStream_t stream) {
-  (void)st; (void)grad_rgba; (void)d_means; (void)d_log_scales; (void)d_quats; (void)d_opacity_logits;
-  (void)d_color; (void)stream;
-  cg::set_last_error("backward not built yet");
-  return CG_ERR_UNSUPPORTED;
+  try {
+    cg::run_backward(st, grad_rgba, d_means, d_log_scales, d_quats, d_opacity_logits, d_color, stream);
+    return CG_OK;
+  } catch (const cg::Error& e) {
+    cg::set_last_error(e.what());
+    return e.status;
+  } catch (const std::exception& e) {
+    cg::set_last_error(e.what());
+    return CG_ERR_STATE;
+  }
 }
+
+extern "C" int64_t cg_bwd_replay_mismatches(const cg_fwd_state* st) { return st ? st->replay_mismatches : -1; }

@@ -201,6 +201,11 @@ def render_backward(state: ForwardState, grad_rgba: torch.Tensor, scene: Scene) 
     return grads
 
 
+def replay_mismatches(state: ForwardState) -> int:
+    """Pixels whose backward replay did not reproduce the forward transmittance."""
+    return int(_lib.lib().cg_bwd_replay_mismatches(state.handle))
+
+
 def camera_unproject(cam: dict, pix_xy: torch.Tensor):
     """Pi^{-1} of continuous full-image coordinates pix_xy [2, n] (float32 cuda).
     Returns (dirs [3, n], valid [n] bool)."""
