@@ -68,7 +68,47 @@ def build_workload(torch, R, synth, device):
     return scene_np, scene, cams
 
 
-def cpu_baseline(scene_np, scene_rho2, cams, opts_kw, rows=4):
+def train_step_bench(torch, R, synth, device, steps, warmup):
+    """fwd + L1 + bwd on the training-step workload: 1M Gaussians, 2 orbit pinholes + 2
+    centre fisheyes at 1280x720, L1 loss against the render of a perturbed copy of the
+    scene (seeded), gradients for means / log-scales / rotations / opacity / SH."""
+    scene_np, target_np, cams = synth.training_config()
+    scene = R.Scene.from_numpy(scene_np, device=device)
+    scene.rho2 = R.bake_rho2(scene, synth.orbit_views(), t_near=0.2)
+    target = R.Scene.from_numpy(target_np, device=device)
+    target.rho2 = scene.rho2
+    opts = R.RenderOpts(filter_mode=R.FILTER_ANISOTROPIC, use_floor=True)
+    with torch.no_grad():
+        tgt, _, _ = R.render_forward(target, cams, opts)
+        tgt = tgt.clone()
+    params = [getattr(scene, k).clone().requires_grad_(True) for k in R.PARAM_NAMES]
+    npx = sum(R.view_pixels(cams))
+
+    def step():
+        rgba = R.ConeGaussRender.apply(*params, scene.rho2, cams, opts, scene.color_mode)
+        loss = (rgba - tgt).abs().mean()
+        loss.backward()
+        return loss
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    prof = R.Profiler()
+    with prof:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    stages = prof.read()
+    return {"value": npx * steps / dt / 1e6, "unit": "Mpix/s", "ms_per_step": dt / steps * 1e3, "steps": steps,
+            "workload": "train_1M: 1M Gaussians, 2 pinhole + 2 KB fisheye 1280x720, L1 vs seeded target",
+            "pixels_per_step": npx,
+            "stages_ms_per_step": {k: v["ms"] / steps for k, v in stages.items() if v["launches"]}}
+
+
+def cpu_baseline(scene_np, scene_rho2, cams, opts_kw, rows=16):
     """The FP64 oracle (culled mode) on a band of `rows` rows through the middle of each
     view, all host threads."""
     import numpy as np
@@ -99,7 +139,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=4)
+    ap.add_argument("--cpu-rows", type=int, default=16)
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
@@ -113,6 +156,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     device = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=device).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: copy calibration done (3 x 256 MiB device copies)", file=sys.stderr, flush=True)
     print("bench: building workload", file=sys.stderr, flush=True)
     scene_np, scene, cams = build_workload(torch, R, synth, device)
     use_floor = True
@@ -161,6 +211,13 @@ def main():
     if tr is not None:
         roofline["traffic"] = tr["bytes_per_launch"]
 
+    fwd_bwd = None
+    if not args.no_train:
+        print("bench: training step (fwd + L1 + bwd)", file=sys.stderr, flush=True)
+        fwd_bwd = train_step_bench(torch, R, synth, device, max(3, args.steps // 4), max(1, args.warmup // 2))
+        print(f"bench: fwd+bwd {fwd_bwd['ms_per_step']:.3f} ms/step, {fwd_bwd['value']:.1f} Mpix/s",
+              file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -178,6 +235,7 @@ def main():
                    "pixels_per_step": npx, "pairs": info["n_pairs"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fwd_bwd": fwd_bwd,
         "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in stages.items() if v["launches"]},
     }
     print(json.dumps(line), flush=True)
