@@ -108,6 +108,71 @@ def train_step_bench(torch, R, synth, device, steps, warmup):
             "stages_ms_per_step": {k: v["ms"] / steps for k, v in stages.items() if v["launches"]}}
 
 
+def serving_bench(torch, R, synth, device, n_requests=200, levels=(0.25, 0.5, 0.75, 0.9)):
+    """Three device-resident scenes (500k, 1.5M, 3M Gaussians); Poisson view requests
+    with camera model uniform over {pinhole, KB fisheye, equirect} and scale uniform over
+    1/8 .. x8 (x2..x8 as crops of the base size).  The per-view-launch baseline (one
+    worker, one view per call) is driven by a burst to find its saturation rate; both
+    it and the continuous-batching server (3 workers, up to 8 fused views) are then
+    replayed at 25/50/75/90 % of that rate: p50/p99 latency (completion minus
+    submission) and Mpix/s."""
+    from paper_2609_13397_amd import serving
+
+    scenes = []
+    for n, seed in ((500_000, 51), (1_500_000, 52), (3_000_000, 53)):
+        sc = R.Scene.from_numpy(synth.make_scene(n, seed=seed, layout="clusters", color="sh3",
+                                                 log_scale_mean=-4.0, log_scale_std=0.7), device=device)
+        sc.rho2 = R.bake_rho2(sc, synth.orbit_views(), 0.2)
+        scenes.append(sc)
+    torch.cuda.synchronize()
+    trace = synth.serving_trace(n_requests, qps=1.0, seed=54)
+    total_px = sum(r.pixels for r in trace)
+    buf = torch.empty((total_px, 4), dtype=torch.float32, device=device)
+    ptrs, off = [], 0
+    for r in trace:
+        ptrs.append(buf.data_ptr() + off * 16)
+        off += r.pixels
+    opts = R.RenderOpts(use_floor=True).to_c()
+
+    def make(batched):
+        cfg = serving.default_config(n_workers=3, max_batch_views=8) if batched else \
+            serving.default_config(n_workers=1, max_batch_views=1)
+        srv = serving.RenderServer(cfg)
+        sids = [srv.add_scene(sc.to_c(), opts, keep=sc) for sc in scenes]
+        return srv, sids
+
+    # warm the caching pools of both configurations
+    for batched in (False, True):
+        srv, sids = make(batched)
+        serving.replay(srv, sids, trace[:20], ptrs[:20], R.camera_struct, burst=True)
+        srv.close()
+    srv, sids = make(False)
+    sat = serving.replay(srv, sids, trace, ptrs, R.camera_struct, burst=True)
+    srv.close()
+    sat_rps = len(trace) / sat.wall_s
+    out = {"requests_per_level": n_requests, "baseline_saturation_rps": sat_rps,
+           "baseline_saturation_mpix_per_s": sat.summary()["mpix_per_s"], "levels": []}
+    for lv in levels:
+        qps = lv * sat_rps
+        row = {"load": lv, "qps": qps}
+        for name, batched in (("per_view_launch", False), ("batched", True)):
+            srv, sids = make(batched)
+            res = serving.replay(srv, sids, trace, ptrs, R.camera_struct, time_scale=1.0 / qps)
+            srv.close()
+            row[name] = res.summary()
+        out["levels"].append(row)
+        print(f"bench: serving load {lv:.2f} qps {qps:.1f}: baseline p50 {row['per_view_launch']['p50_ms']:.2f} "
+              f"p99 {row['per_view_launch']['p99_ms']:.2f} | batched p50 {row['batched']['p50_ms']:.2f} "
+              f"p99 {row['batched']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    # saturation of the batched server (burst)
+    srv, sids = make(True)
+    bsat = serving.replay(srv, sids, trace, ptrs, R.camera_struct, burst=True)
+    srv.close()
+    out["batched_saturation_rps"] = len(trace) / bsat.wall_s
+    out["batched_saturation_mpix_per_s"] = bsat.summary()["mpix_per_s"]
+    return out
+
+
 def cpu_baseline(scene_np, scene_rho2, cams, opts_kw, rows=16):
     """The FP64 oracle (culled mode) on a band of `rows` rows through the middle of each
     view, all host threads."""
@@ -141,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16)
     ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -218,6 +285,11 @@ def main():
         print(f"bench: fwd+bwd {fwd_bwd['ms_per_step']:.3f} ms/step, {fwd_bwd['value']:.1f} Mpix/s",
               file=sys.stderr, flush=True)
 
+    serving_res = None
+    if not args.no_serving:
+        print("bench: serving", file=sys.stderr, flush=True)
+        serving_res = serving_bench(torch, R, synth, device, n_requests=args.serving_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -236,6 +308,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd,
+        "serving": serving_res,
         "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in stages.items() if v["launches"]},
     }
     print(json.dumps(line), flush=True)

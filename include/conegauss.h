@@ -197,6 +197,67 @@ cg_status cg_camera_unproject(const cg_camera* cam /* host */, int64_t n, const 
 cg_status cg_bake_rho2(const cg_gaussians* g /* host struct, device arrays */, const cg_camera* cams /* host */,
                        int32_t n_views, float t_near, float* rho2_out, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------- serving
+ * A render server with continuous batching (extension of the paper's renderer to a
+ * serving loop).  Scenes are registered once and stay device-resident (the server
+ * keeps the device pointers; the caller keeps the arrays alive).  Requests (scene,
+ * camera, caller-owned device output [crop_h][crop_w][4]) queue in arrival order.
+ * Each of n_workers threads owns a HIP stream; a free worker takes the oldest
+ * request when its estimated scratch memory fits hbm_budget_bytes next to the
+ * requests already running (or when nothing runs), and fuses further queued
+ * requests for the same scene into the same multi-view render call, up to
+ * max_batch_views views and max_batch_pixels pixels, while they fit the budget.
+ * A fused call renders each view bit for bit as a call with that view alone.
+ * With n_workers = 1 and max_batch_views = 1 the server is the plain one-view-per-
+ * launch renderer.  fake_executor = 1 replaces rendering by a sleep of
+ * fake_ns_per_call + fake_ns_per_pixel * pixels (scheduler tests without a GPU). */
+typedef struct cg_server cg_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;     /* [24 GiB] scratch that admitted requests may hold together */
+  int32_t max_batch_views;     /* [8]      views fused into one render call                 */
+  int32_t n_workers;           /* [3]      concurrent render calls, one HIP stream each     */
+  int64_t max_batch_pixels;    /* [16 Mi]  pixel cap of one fused call                      */
+  int32_t fake_executor;       /* [0]                                                       */
+  int32_t device;              /* [0]      HIP device of the worker streams                 */
+  double fake_ns_per_pixel;    /* [1]                                                       */
+  double fake_ns_per_call;     /* [50000]                                                   */
+} cg_server_config;
+
+/* One finished (or cancelled: status CG_ERR_STATE) request.  Times are seconds on the
+ * clock of cg_server_now(): submission, admission, start and end of its render call. */
+typedef struct {
+  int64_t request_id;
+  int32_t status;
+  int32_t scene;
+  int32_t batch_views;
+  int32_t reserved;
+  double t_submit, t_admit, t_start, t_done;
+  int64_t n_pairs;             /* pairs of the fused call that rendered it */
+} cg_server_completion;
+
+typedef struct {
+  int64_t queued, in_flight, completed, batches, views, max_batch_views;
+  int64_t reserved_bytes, peak_reserved_bytes;
+} cg_server_stats;
+
+void cg_server_default_config(cg_server_config* cfg /* host */);
+cg_status cg_server_create(const cg_server_config* cfg, cg_server** out);
+/* g: host struct of device arrays (kept by pointer); opts: render options of the scene. */
+cg_status cg_server_add_scene(cg_server* s, const cg_gaussians* g, const cg_render_opts* opts, int32_t* scene_id);
+/* Validates the camera on the host and queues the request; returns at once. */
+cg_status cg_server_submit(cg_server* s, int32_t scene, const cg_camera* cam, float* out_rgba, int64_t* request_id);
+/* Removes a request that has not been admitted yet; *cancelled = 1 if it was found. */
+cg_status cg_server_cancel(cg_server* s, int64_t request_id, int32_t* cancelled);
+/* Moves up to `capacity` completions into out (waiting up to wait_ms for the first). */
+cg_status cg_server_poll(cg_server* s, cg_server_completion* out, int32_t capacity, int32_t* n_out, int32_t wait_ms);
+/* Blocks until the queue is empty and no render call is running. */
+cg_status cg_server_drain(cg_server* s);
+cg_status cg_server_get_stats(cg_server* s, cg_server_stats* out);
+/* Drops queued requests, waits for running calls, stops the workers. */
+void cg_server_destroy(cg_server* s);
+double cg_server_now(void);
+
 /* Per-stage GPU timing.  When enabled, every kernel launch of the library is
  * bracketed with HIP events on its stream.  cg_profile_collect synchronises on the
  * recorded events and adds their durations to per-stage totals; cg_profile_read

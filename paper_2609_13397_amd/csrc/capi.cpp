@@ -18,6 +18,10 @@ double kb_poly(const cg_camera& c, double th) {
   return th * (1.0 + t2 * (c.k[0] + t2 * (c.k[1] + t2 * (c.k[2] + t2 * c.k[3]))));
 }
 
+}  // namespace
+
+namespace cg {
+
 void check_camera(const cg_camera& c, int idx) {
   const std::string w = "camera " + std::to_string(idx) + ": ";
   CG_CHECK_ARG(c.model == CG_PINHOLE || c.model == CG_FISHEYE_KB || c.model == CG_EQUIRECT, w + "unknown model");
@@ -52,6 +56,10 @@ void check_camera(const cg_camera& c, int idx) {
   CG_CHECK_ARG(std::fabs(det) > 1e-3, w + "rotation is singular");
 }
 
+}  // namespace cg
+
+namespace {
+
 void inv3(const double* A, double* I) {
   const double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
                    A[2] * (A[3] * A[7] - A[4] * A[6]);
@@ -65,6 +73,10 @@ void inv3(const double* A, double* I) {
   I[7] = (A[1] * A[6] - A[0] * A[7]) / d;
   I[8] = (A[0] * A[4] - A[1] * A[3]) / d;
 }
+
+}  // namespace
+
+namespace cg {
 
 DevCamera make_dev_camera(const cg_camera& c) {
   DevCamera d;
@@ -141,27 +153,14 @@ GaussPtrs make_gauss(const cg_gaussians& g) {
   return p;
 }
 
+}  // namespace cg
+
+namespace {
+
 int bits_for(int64_t v) {
   int b = 0;
   while (b < 63 && (int64_t(1) << b) <= v) ++b;
   return b;
-}
-
-template <class F>
-cg_status guarded(F&& f) {
-  try {
-    f();
-    return CG_OK;
-  } catch (const Error& e) {
-    set_last_error(e.what());
-    return e.status;
-  } catch (const std::bad_alloc&) {
-    set_last_error("host out of memory");
-    return CG_ERR_OUT_OF_MEMORY;
-  } catch (const std::exception& e) {
-    set_last_error(e.what());
-    return CG_ERR_STATE;
-  }
 }
 
 }  // namespace
@@ -171,8 +170,8 @@ cg_status guarded(F&& f) {
 namespace cg {
 
 void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, const cg_render_opts* opts_in,
-                 const cg_allocator* alloc, float* out_rgba, cg_fwd_state** state_out, cg_fwd_stats* stats,
-                 hipStream_t s) {
+                 const cg_allocator* alloc, float* out_rgba, float* const* view_out, cg_fwd_state** state_out,
+                 cg_fwd_stats* stats, hipStream_t s) {
   CG_CHECK_ARG(g_in && cams && opts_in, "null argument");
   CG_CHECK_ARG(n_views >= 1 && n_views <= 4096, "n_views must be in [1, 4096]");
   const GaussPtrs g = make_gauss(*g_in);
@@ -185,13 +184,15 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     hc[v].tile_offset = (int32_t)total_tiles;
     hc[v].group_offset = (int32_t)total_groups;
     hc[v].px_offset = total_px;
+    hc[v].out = view_out ? view_out[v] : (out_rgba ? out_rgba + 4 * total_px : nullptr);
+    CG_CHECK_ARG(hc[v].out || (int64_t)cams[v].crop_w * cams[v].crop_h == 0, "null output for a non-empty view");
     CG_CHECK_ARG((int64_t)hc[v].groups_x * hc[v].groups_y <= 65535, "view too large (more than 65535 tile groups)");
     total_tiles += (int64_t)hc[v].tiles_x * hc[v].tiles_y;
     total_groups += (int64_t)hc[v].groups_x * hc[v].groups_y;
     total_px += (int64_t)cams[v].crop_w * cams[v].crop_h;
   }
   CG_CHECK_ARG(total_tiles < (int64_t(1) << 31) / 8 - 8, "too many tiles");
-  CG_CHECK_ARG(total_px == 0 || out_rgba, "null out_rgba");
+
   const int64_t n = g.n;
   const int64_t nv = n * n_views;
   CG_CHECK_ARG(nv < (int64_t(1) << 31), "n * n_views must be below 2^31");
@@ -378,7 +379,7 @@ cg_status cg_render_forward(const cg_gaussians* g, const cg_camera* cams, int32_
                             const cg_render_opts* opts, const cg_allocator* alloc, float* out_rgba,
                             cg_fwd_state** state_out, cg_fwd_stats* stats_out, hipStream_t stream) {
   if (state_out) *state_out = nullptr;
-  return guarded([&] { run_forward(g, cams, n_views, opts, alloc, out_rgba, state_out, stats_out, stream); });
+  return guarded([&] { run_forward(g, cams, n_views, opts, alloc, out_rgba, nullptr, state_out, stats_out, stream); });
 }
 
 void cg_fwd_state_release(cg_fwd_state* st) {

@@ -25,7 +25,8 @@ struct DevCamera {
   int32_t tile_offset;   // first global tile index of this view
   int32_t group_offset;  // first global group index of this view
   int32_t pad0;
-  int64_t px_offset;     // first output pixel of this view
+  int64_t px_offset;     // first pixel of this view in the per-pixel arrays
+  float* out;            // this view's RGBA output, [crop_h][crop_w][4]
   double fx, fy, cx, cy, inv_fx, inv_fy, inv_w, inv_h;
   double k[4];
   double R[9];           // row-major camera-to-world

@@ -28,7 +28,29 @@ struct cg_fwd_state {
 };
 
 namespace cg {
+// view_out: per-view output pointers (NULL: views laid out contiguously in out_rgba).
 void run_forward(const cg_gaussians* g, const cg_camera* cams, int n_views, const cg_render_opts* opts,
-                 const cg_allocator* alloc, float* out_rgba, cg_fwd_state** state_out, cg_fwd_stats* stats,
-                 hipStream_t s);
+                 const cg_allocator* alloc, float* out_rgba, float* const* view_out, cg_fwd_state** state_out,
+                 cg_fwd_stats* stats, hipStream_t s);
+// Host-side validation and set-up shared by the entry points (capi.cpp).
+void check_camera(const cg_camera& c, int idx);
+DevCamera make_dev_camera(const cg_camera& c);
+GaussPtrs make_gauss(const cg_gaussians& g);
+Opts make_opts(const cg_render_opts& o);
+template <class F>
+cg_status guarded(F&& f) {
+  try {
+    f();
+    return CG_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host out of memory");
+    return CG_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return CG_ERR_STATE;
+  }
+}
 }

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
   if (inside) {
     p = c.px_offset + (int64_t)j * c.crop_w + i;
     const float4 gr = reinterpret_cast<const float4*>(grad_rgba)[p];
-    const float4 fo = reinterpret_cast<const float4*>(out_rgba)[p];
+    const float4 fo = reinterpret_cast<const float4*>(c.out)[(int64_t)j * c.crop_w + i];
     G0 = gr.x; G1 = gr.y; G2 = gr.z; Ga = gr.w;
     Tfin = final_T[p];
     Cf0 = fo.x - Tfin * o.bg[0];

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ ca
     out.y = C1 + Ttr * o.bg[1];
     out.z = C2 + Ttr * o.bg[2];
     out.w = 1.f - Ttr;
-    reinterpret_cast<float4*>(out_rgba)[p] = out;
+    reinterpret_cast<float4*>(c.out)[(int64_t)j * c.crop_w + i] = out;
     if (final_T) final_T[p] = Ttr;
     if (n_last) n_last[p] = r.valid ? last : rg.x;
   }

@@ -28,7 +28,8 @@ def test_library_exports_every_declared_symbol():
     L = _lib.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert set(declared_functions()) == set(_lib.SIGNATURES)
+    from paper_2609_13397_amd import serving
+    assert set(declared_functions()) == set(_lib.SIGNATURES) | set(serving.SERVER_SIGNATURES)
     assert L.cg_version() == 1
 
 
