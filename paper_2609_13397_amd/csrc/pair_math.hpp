@@ -20,25 +20,31 @@
 
 namespace cg {
 
+// Per-pixel ray data used by every pair (64 bytes, so a wave's pixels fit in LDS).
 struct PairPixel {
   double d0, d1, d2;     // centre ray (FP64)
-  double o0, o1, o2;     // camera centre (FP64)
   float a0, a1, a2;      // centre ray (float32)
   float x0, x1, x2;      // d_x - d
   float y0, y1, y2;      // d_y - d
   float cpix;            // (|d_x - d|^2 + |d_y - d|^2) / 3
 };
 
-__device__ __forceinline__ PairPixel make_pair_pixel(const PixelRay& r, const DevCamera& c) {
+// Camera centre in FP64 (uniform over a tile).
+struct Origin {
+  double x, y, z;
+};
+
+__device__ __forceinline__ PairPixel make_pair_pixel(const PixelRay& r) {
   PairPixel p;
   p.d0 = r.d[0]; p.d1 = r.d[1]; p.d2 = r.d[2];
-  p.o0 = c.o[0]; p.o1 = c.o[1]; p.o2 = c.o[2];
   p.a0 = r.df[0]; p.a1 = r.df[1]; p.a2 = r.df[2];
   p.x0 = r.dx[0]; p.x1 = r.dx[1]; p.x2 = r.dx[2];
   p.y0 = r.dy[0]; p.y1 = r.dy[1]; p.y2 = r.dy[2];
   p.cpix = r.cpix;
   return p;
 }
+
+__device__ __forceinline__ Origin make_origin(const DevCamera& c) { return Origin{c.o[0], c.o[1], c.o[2]}; }
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -51,8 +57,9 @@ struct PairGeom {
 };
 
 // Geometry part: a, t*, q, D^2.  Returns false when t* <= t_near (T = 0).
-__device__ __forceinline__ bool pair_geom(const Record& R, const PairPixel& p, float t_near, PairGeom& g) {
-  const double vx = (double)R.mu[0] - p.o0, vy = (double)R.mu[1] - p.o1, vz = (double)R.mu[2] - p.o2;
+__device__ __forceinline__ bool pair_geom(const Record& R, const PairPixel& p, const Origin& O, float t_near,
+                                          PairGeom& g) {
+  const double vx = (double)R.mu[0] - O.x, vy = (double)R.mu[1] - O.y, vz = (double)R.mu[2] - O.z;
   const double te = vx * p.d0 + vy * p.d1 + vz * p.d2;
   const float wx = (float)(vx - te * p.d0), wy = (float)(vy - te * p.d1), wz = (float)(vz - te * p.d2);
   const float* W = R.W;
@@ -130,42 +137,38 @@ __device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, floa
   return true;
 }
 
-// Filtered response T of one pair.  FILTER 0: centre ray; 1: anisotropic (Eq. 9);
-// 2: isotropic in-plane covariance of the same trace.  MARGINAL: floor composition by
-// Eq. 12 (records with rho2 = 0 take the plain path).  Returns false when the pair
-// cannot reach alpha_min (T is then not set): the ray is outside the Gaussian's
-// influence cone, t* <= t_near, or the pre-rejection
-// D^2 > L (1 + tr Sigma_fp^u) with tr Sigma_fp^u <= t*^2 c_pix / s'_min^2, which
-// bounds q^T A^{-1} q from below (Sigma_render^u is dominated by Sigma_fp^u).
+// The cheap tests of one pair, in order: the ray against the Gaussian's influence
+// cone (chord test), t* > t_near, and the pre-rejection D^2 <= L (1 + tr Sigma_fp^u)
+// with tr Sigma_fp^u <= t*^2 c_pix / s'_min^2, which bounds q^T A^{-1} q from below
+// (Sigma_render^u is dominated by Sigma_fp^u).  False means the pair cannot reach
+// alpha_min.  On true, g holds the geometry of Eq. 2.
+template <int FILTER>
+__device__ __forceinline__ bool pair_cheap(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
+                                           PairGeom& g) {
+  const float cx = p.a0 - R.ux, cy = p.a1 - R.uy, cz = p.a2 - R.uz;
+  if (cx * cx + cy * cy + cz * cz > R.lim * R.lim || R.lim < 0.f) return false;
+  if (!pair_geom(R, p, O, o.t_near, g)) return false;
+  if (FILTER == 0) return g.D2 <= R.Lg;
+  return g.D2 <= R.Lg * fmaf(g.tstar * g.tstar * p.cpix, R.kg, 1.f) * 1.0001f + 1e-6f;
+}
+
+// Filtered response T of a pair that passed pair_cheap.  FILTER 0: centre ray (Eq. 3,
+// C = 1); 1: anisotropic (Eq. 9); 2: isotropic in-plane covariance of the same trace.
+// MARGINAL: floor composition by Eq. 12 (records with rho2 = 0 take the plain path).
 template <int FILTER, bool MARGINAL>
-__device__ __forceinline__ bool pair_response(const Record& R, const PairPixel& p, const Opts& o, float& T) {
-  {  // influence cone of the Gaussian, tested at this pixel's centre ray
-    const float cx = p.a0 - R.ux, cy = p.a1 - R.uy, cz = p.a2 - R.uz;
-    if (cx * cx + cy * cy + cz * cz > R.lim * R.lim || R.lim < 0.f) return false;
-  }
-  PairGeom g;
-  if (!pair_geom(R, p, o.t_near, g)) return false;
-  if (FILTER == 0) {
-    if (g.D2 > R.Lg) return false;
-    T = R.sigma * __expf(-0.5f * g.D2);
-    return true;
-  }
-  if (g.D2 > R.Lg * fmaf(g.tstar * g.tstar * p.cpix, R.kg, 1.f) * 1.0001f + 1e-6f) return false;
+__device__ __forceinline__ float pair_full(const Record& R, const PairPixel& p, const PairGeom& g) {
+  if (FILTER == 0) return R.sigma * __expf(-0.5f * g.D2);
   PairFoot f;
   pair_foot(R, p, g, f);
   float G11 = 1.f, G12 = 0.f, G22 = 1.f;
   bool filt = true;
   if (MARGINAL && R.rho2 > 0.f) filt = floor_G(R, f, G11, G12, G22);
-  if (!filt) {
-    T = R.sigma * __expf(-0.5f * g.D2);
-    return true;
-  }
+  if (!filt) return R.sigma * __expf(-0.5f * g.D2);
   if (FILTER == 2) {
     const float tau = (MARGINAL && R.rho2 > 0.f) ? (G11 * f.K11 + 2.f * G12 * f.K12 + G22 * f.K22) : (f.K11 + f.K22);
     const float s = 1.f + 0.5f * tau;
     const float is = fast_rcp(s);
-    T = R.sigma * is * __expf(-0.5f * g.D2 * is);
-    return true;
+    return R.sigma * is * __expf(-0.5f * g.D2 * is);
   }
   float det, quad;
   if (MARGINAL && R.rho2 > 0.f) {
@@ -181,7 +184,16 @@ __device__ __forceinline__ bool pair_response(const Record& R, const PairPixel& 
     det = P11 * P22 - P12 * P12;
     quad = (P22 * f.h1 * f.h1 - 2.f * P12 * f.h1 * f.h2 + P11 * f.h2 * f.h2) * fast_rcp(det);
   }
-  T = R.sigma * rsqrtf(det) * __expf(-0.5f * (g.D2 - quad));
+  return R.sigma * rsqrtf(det) * __expf(-0.5f * (g.D2 - quad));
+}
+
+// Both parts; false when the pair cannot reach alpha_min (T is then not set).
+template <int FILTER, bool MARGINAL>
+__device__ __forceinline__ bool pair_response(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
+                                              float& T) {
+  PairGeom g;
+  if (!pair_cheap<FILTER>(R, p, O, o, g)) return false;
+  T = pair_full<FILTER, MARGINAL>(R, p, g);
   return true;
 }
 
@@ -198,13 +210,13 @@ namespace cg {
 // with one, G = g+ u u^T (u the leading eigenvector); at the clamp kink the clamped
 // branch's (zero) derivative is used.
 template <int FILTER, bool MARGINAL>
-__device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, const Opts& o, float dT, float T,
-                                          float* __restrict__ g) {
+__device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
+                                          float dT, float T, float* __restrict__ g) {
   PairGeom gm;
-  pair_geom(R, p, o.t_near, gm);
+  pair_geom(R, p, O, o.t_near, gm);
   const float* W = R.W;
   // forward recompute of the remaining intermediates
-  const double vx = (double)R.mu[0] - p.o0, vy = (double)R.mu[1] - p.o1, vz = (double)R.mu[2] - p.o2;
+  const double vx = (double)R.mu[0] - O.x, vy = (double)R.mu[1] - O.y, vz = (double)R.mu[2] - O.z;
   const double te = vx * p.d0 + vy * p.d1 + vz * p.d2;
   const float wx = (float)(vx - te * p.d0), wy = (float)(vy - te * p.d1), wz = (float)(vz - te * p.d2);
   const float yx = -(W[0] * wx + W[1] * wy + W[2] * wz);

@@ -85,7 +85,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
   PixelRay r;
   r.valid = false;
   if (inside) r = pixel_ray(c, i, j, o.fs);
-  const PairPixel px = make_pair_pixel(r, c);
+  const PairPixel px = make_pair_pixel(r);
+  const Origin org = make_origin(c);
   const WaveConeB wc = wave_cone_b(r);
 
   // upstream gradient and forward result of this pixel
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
         if (!done) {
           const Record& R = srec[k];
           float T;
-          if (pair_response<FILTER, MARGINAL>(R, px, o, T)) {
+          if (pair_response<FILTER, MARGINAL>(R, px, org, o, T)) {
             const float alpha = fminf(T, o.alpha_max);
             if (alpha >= o.alpha_min) {
               const float test = Ttr * (1.f - alpha);
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
                 gv[16] = G0 * w;
                 gv[17] = G1 * w;
                 gv[18] = G2 * w;
-                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL>(R, px, o, dalpha, T, gv);
+                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL>(R, px, org, o, dalpha, T, gv);
                 Ttr = test;
               }
             }

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ ca
   PixelRay r;
   r.valid = false;
   if (inside) r = pixel_ray(c, i, j, o.fs);
-  const PairPixel px = make_pair_pixel(r, c);
+  const PairPixel px = make_pair_pixel(r);
+  const Origin org = make_origin(c);
   const WaveCone wc = wave_cone(r);
 
   const uint2 rg = ranges[t];
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ ca
           if (!done) {
             float T;
             if (COUNT) ++c_eval;
-            if (pair_response<FILTER, MARGINAL>(srec[k], px, o, T)) {
+            if (pair_response<FILTER, MARGINAL>(srec[k], px, org, o, T)) {
               if (COUNT) ++c_full;
               const float alpha = fminf(T, o.alpha_max);
               if (alpha >= o.alpha_min) {
