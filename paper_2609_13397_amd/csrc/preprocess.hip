@@ -2,33 +2,9 @@
 // whitening W = diag(1/s') R^T (Eq. 1 with Sigma_eff), view-dependent colour, the
 // float32 compositing key and the angular influence cone used by the binning.
 #include "camera_dev.hpp"
+#include "sh.hpp"
 
 namespace cg {
-
-// Real spherical harmonics of degree <= 3 at a unit direction (x, y, z): orthonormal
-// on the sphere, Condon-Shortley phase, (l, m) order with m = -l..l.  Each constant is
-// the normalisation sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) (times sqrt 2 for m != 0)
-// multiplied by the integer factor of the associated Legendre function written as a
-// polynomial in x, y, z.
-__device__ __forceinline__ void sh_basis3(float x, float y, float z, float Y[16]) {
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[0] = 0.28209479177387814f;                        // 1 / (2 sqrt(pi))
-  Y[1] = -0.4886025119029199f * y;                    // sqrt(3 / (4 pi))
-  Y[2] = 0.4886025119029199f * z;
-  Y[3] = -0.4886025119029199f * x;
-  Y[4] = 1.0925484305920792f * x * y;                 // (1/2) sqrt(15 / pi)
-  Y[5] = -1.0925484305920792f * y * z;
-  Y[6] = 0.31539156525252005f * (3.f * zz - 1.f);     // (1/4) sqrt(5 / pi)
-  Y[7] = -1.0925484305920792f * x * z;
-  Y[8] = 0.5462742152960396f * (xx - yy);             // (1/4) sqrt(15 / pi)
-  Y[9] = -0.5900435899266435f * y * (3.f * xx - yy);  // (1/4) sqrt(35 / (2 pi))
-  Y[10] = 2.890611442640554f * x * y * z;             // (1/2) sqrt(105 / pi)
-  Y[11] = -0.4570457994644658f * y * (5.f * zz - 1.f);  // (1/4) sqrt(21 / (2 pi))
-  Y[12] = 0.3731763325901154f * z * (5.f * zz - 3.f);   // (1/4) sqrt(7 / pi)
-  Y[13] = -0.4570457994644658f * x * (5.f * zz - 1.f);
-  Y[14] = 1.445305721320277f * z * (xx - yy);           // (1/4) sqrt(105 / pi)
-  Y[15] = -0.5900435899266435f * x * (xx - 3.f * yy);
-}
 
 // |mu - o|^2 in float32 with the operation order ((vx*vx + vy*vy) + vz*vz) and no
 // fused multiply-add: the compositing key, identical on every platform that rounds

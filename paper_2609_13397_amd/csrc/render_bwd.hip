@@ -8,24 +8,22 @@
 //      dL/dc_k     = G alpha_k T_k,
 //    where S_k = C_fin - C_{<=k} is the colour composited behind k (C_fin from the
 //    forward output).  dL/dT_k = dL/dalpha_k below the alpha_max clamp.  The record
-//    gradient of each pair (pair_grad) is summed over the quadrant's pixels with wave
-//    shuffles and over the four quadrants through LDS, and written, without atomics,
-//    to the pair's emission slot.
+//    gradient of each pair (pair_grad) is summed over the quadrant's pixels by a
+//    transposed wave reduction on the VALU lane movers (wave_ops.hpp) and over the
+//    four quadrants through LDS, and written, without atomics, to the pair's
+//    emission slot.
 // 2. Per (view, Gaussian) sum of its pairs' partial gradients (contiguous slots).
 // 3. Preprocess backward to the raw parameters, summing views in a fixed order.
 #include <algorithm>
 
 #include "fwd_state.hpp"
 #include "pair_math.hpp"
+#include "sh.hpp"
+#include "wave_ops.hpp"
 
 namespace cg {
 
-constexpr int kGradLen = 20;  // dW[9] dmu[3] dsigma dsp2[3] drgb[3] pad
-
-__device__ __forceinline__ float wave_sum(float v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+constexpr int kGradLen = 20;  // dW[9] dmu[3] dsigma dsp2[3] drgb[3] pad (zero)
 
 struct WaveConeB {
   float ax, ay, az, rad;
@@ -35,12 +33,10 @@ struct WaveConeB {
 __device__ __forceinline__ WaveConeB wave_cone_b(const PixelRay& r) {
   float sx = r.valid ? r.df[0] : 0.f, sy = r.valid ? r.df[1] : 0.f, sz = r.valid ? r.df[2] : 0.f;
   float cnt = r.valid ? 1.f : 0.f;
-  for (int o = 32; o > 0; o >>= 1) {
-    sx += __shfl_xor(sx, o);
-    sy += __shfl_xor(sy, o);
-    sz += __shfl_xor(sz, o);
-    cnt += __shfl_xor(cnt, o);
-  }
+  sx = wave_total(sx);
+  sy = wave_total(sy);
+  sz = wave_total(sz);
+  cnt = wave_total(cnt);
   WaveConeB w;
   w.live = cnt > 0.f;
   const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
@@ -53,7 +49,7 @@ __device__ __forceinline__ WaveConeB wave_cone_b(const PixelRay& r) {
     const float dx = w.ax - r.df[0], dy = w.ay - r.df[1], dz = w.az - r.df[2];
     ch = sqrtf(dx * dx + dy * dy + dz * dz);
   }
-  for (int o = 32; o > 0; o >>= 1) ch = fmaxf(ch, __shfl_xor(ch, o));
+  ch = wave_max(ch);
   w.rad = ch * 1.0001f + 2e-6f;
   if (nrm < 0.5f * cnt) w.rad = 3.f;
   return w;
@@ -88,6 +84,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
   const PairPixel px = make_pair_pixel(r);
   const Origin org = make_origin(c);
   const WaveConeB wc = wave_cone_b(r);
+  const int red_idx = wave_sum20_index(lane);  // which gradient component this lane's wave sum holds
 
   // upstream gradient and forward result of this pixel
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, Ga = 0.f, Tfin = 1.f, Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f;
@@ -166,11 +163,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
           }
         }
         if (__ballot(contrib) != 0) {
-#pragma unroll
-          for (int q = 0; q < kGradLen - 1; ++q) {
-            const float s = wave_sum(gv[q]);
-            if (lane == 0) gacc[wave][k][q] = s;
-          }
+          const float s = wave_sum20(gv, lane);
+          if (red_idx >= 0) gacc[wave][k][red_idx] = s;
         }
       }
     }
@@ -189,63 +183,34 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
   if (r.valid && !done && Ttr != Tfin) atomicAdd(mismatch, 1u);
 }
 
-// Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt).
-__global__ void k_reduce_items(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets, int64_t nv,
-                               const float* __restrict__ partial, float* __restrict__ item_grad) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= nv) return;
-  float acc[kGradLen];
-#pragma unroll
-  for (int q = 0; q < kGradLen; ++q) acc[q] = 0.f;
-  const uint32_t cnt = counts[it], off = offsets[it];
-  for (uint32_t s = 0; s < cnt; ++s) {
-    const float4* row = reinterpret_cast<const float4*>(partial + (int64_t)(off + s) * kGradLen);
-#pragma unroll
-    for (int q4 = 0; q4 < kGradLen / 4; ++q4) {
-      const float4 x = row[q4];
-      acc[4 * q4 + 0] += x.x;
-      acc[4 * q4 + 1] += x.y;
-      acc[4 * q4 + 2] += x.z;
-      acc[4 * q4 + 3] += x.w;
-    }
-  }
-  float4* out = reinterpret_cast<float4*>(item_grad + it * kGradLen);
-#pragma unroll
-  for (int q4 = 0; q4 < kGradLen / 4; ++q4)
-    out[q4] = make_float4(acc[4 * q4], acc[4 * q4 + 1], acc[4 * q4 + 2], acc[4 * q4 + 3]);
-}
+// Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt),
+// added in slot order.  20 lanes per item, one gradient component each, 3 items per
+// wave: a wave waits on the largest of 3 slot counts instead of 64, and each slot's
+// row is read as one contiguous 80-byte segment.
+constexpr int kReduceItemsPerWave = 64 / kGradLen;
 
-// Gradient of the degree-3 real SH basis (the polynomials of sh_basis3 in
-// preprocess.hip) with respect to the unnormalised direction components.
-__device__ __forceinline__ void sh_basis3_grad(float x, float y, float z, float Y[16], float dYx[16], float dYy[16],
-                                               float dYz[16]) {
-  constexpr float c0 = 0.28209479177387814f, c1 = 0.4886025119029199f, c2a = 1.0925484305920792f,
-                  c2b = 0.31539156525252005f, c2c = 0.5462742152960396f, c3a = 0.5900435899266435f,
-                  c3b = 2.890611442640554f, c3c = 0.4570457994644658f, c3d = 0.3731763325901154f,
-                  c3e = 1.445305721320277f;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[0] = c0;                        dYx[0] = 0.f;                 dYy[0] = 0.f;                  dYz[0] = 0.f;
-  Y[1] = -c1 * y;                   dYx[1] = 0.f;                 dYy[1] = -c1;                  dYz[1] = 0.f;
-  Y[2] = c1 * z;                    dYx[2] = 0.f;                 dYy[2] = 0.f;                  dYz[2] = c1;
-  Y[3] = -c1 * x;                   dYx[3] = -c1;                 dYy[3] = 0.f;                  dYz[3] = 0.f;
-  Y[4] = c2a * x * y;               dYx[4] = c2a * y;             dYy[4] = c2a * x;              dYz[4] = 0.f;
-  Y[5] = -c2a * y * z;              dYx[5] = 0.f;                 dYy[5] = -c2a * z;             dYz[5] = -c2a * y;
-  Y[6] = c2b * (3.f * zz - 1.f);    dYx[6] = 0.f;                 dYy[6] = 0.f;                  dYz[6] = 6.f * c2b * z;
-  Y[7] = -c2a * x * z;              dYx[7] = -c2a * z;            dYy[7] = 0.f;                  dYz[7] = -c2a * x;
-  Y[8] = c2c * (xx - yy);           dYx[8] = 2.f * c2c * x;       dYy[8] = -2.f * c2c * y;       dYz[8] = 0.f;
-  Y[9] = -c3a * y * (3.f * xx - yy);  dYx[9] = -6.f * c3a * x * y;  dYy[9] = -c3a * (3.f * xx - 3.f * yy); dYz[9] = 0.f;
-  Y[10] = c3b * x * y * z;          dYx[10] = c3b * y * z;        dYy[10] = c3b * x * z;         dYz[10] = c3b * x * y;
-  Y[11] = -c3c * y * (5.f * zz - 1.f);  dYx[11] = 0.f;  dYy[11] = -c3c * (5.f * zz - 1.f);  dYz[11] = -10.f * c3c * y * z;
-  Y[12] = c3d * z * (5.f * zz - 3.f);   dYx[12] = 0.f;  dYy[12] = 0.f;  dYz[12] = c3d * (15.f * zz - 3.f);
-  Y[13] = -c3c * x * (5.f * zz - 1.f);  dYx[13] = -c3c * (5.f * zz - 1.f);  dYy[13] = 0.f;  dYz[13] = -10.f * c3c * x * z;
-  Y[14] = c3e * z * (xx - yy);      dYx[14] = 2.f * c3e * x * z;  dYy[14] = -2.f * c3e * y * z;  dYz[14] = c3e * (xx - yy);
-  Y[15] = -c3a * x * (xx - 3.f * yy);  dYx[15] = -c3a * (3.f * xx - 3.f * yy);  dYy[15] = 6.f * c3a * x * y;  dYz[15] = 0.f;
+__global__ __launch_bounds__(256) void k_reduce_items(const uint32_t* __restrict__ counts,
+                                                      const uint32_t* __restrict__ offsets, int64_t nv,
+                                                      const float* __restrict__ partial,
+                                                      float* __restrict__ item_grad) {
+  const int lane = threadIdx.x & 63;
+  const int sub = lane / kGradLen, q = lane - sub * kGradLen;
+  if (sub >= kReduceItemsPerWave) return;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t it = wave * kReduceItemsPerWave + sub;
+  if (it >= nv) return;
+  const uint32_t cnt = counts[it];
+  const float* src = partial + (int64_t)offsets[it] * kGradLen + q;
+  float acc = 0.f;
+#pragma unroll 4
+  for (uint32_t k = 0; k < cnt; ++k) acc += src[(int64_t)k * kGradLen];
+  item_grad[it * kGradLen + q] = acc;
 }
 
 // Preprocess backward: per Gaussian, the per-view record gradients back to the raw
 // parameters (activations of Sec. 3, the floor of Eq. 10, the colour).  Views are
 // summed in index order; outputs are overwritten.
-__global__ void k_preprocess_bwd(GaussPtrs g, const DevCamera* __restrict__ cams, int n_views, Opts o,
+__global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCamera* __restrict__ cams, int n_views, Opts o,
                                  const float* __restrict__ item_grad, float* __restrict__ d_means,
                                  float* __restrict__ d_log_scales, float* __restrict__ d_quats,
                                  float* __restrict__ d_logits, float* __restrict__ d_color) {
@@ -277,14 +242,14 @@ __global__ void k_preprocess_bwd(GaussPtrs g, const DevCamera* __restrict__ cams
   }
   float dmu[3] = {0.f, 0.f, 0.f}, dR[9], dsp2[3] = {0.f, 0.f, 0.f}, dsig_eff = 0.f;
   for (int k = 0; k < 9; ++k) dR[k] = 0.f;
-  const int ncol = g.color_mode == 0 ? 3 : 48;
-  float dcol[48];
-  for (int k = 0; k < 48; ++k) dcol[k] = 0.f;
+#pragma unroll 1
   for (int v = 0; v < n_views; ++v) {
     const float* gr = item_grad + ((int64_t)v * n + i) * kGradLen;
     // W[a][b] = R[b][a] / s'_a
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       float acc = 0.f;
+#pragma unroll
       for (int b2 = 0; b2 < 3; ++b2) {
         dR[3 * b2 + a] += gr[3 * a + b2] / sp[a];
         acc += gr[3 * a + b2] * R[3 * b2 + a];
@@ -299,35 +264,55 @@ __global__ void k_preprocess_bwd(GaussPtrs g, const DevCamera* __restrict__ cams
     dsp2[0] += gr[13];
     dsp2[1] += gr[14];
     dsp2[2] += gr[15];
-    const float drgb[3] = {gr[16], gr[17], gr[18]};
-    if (g.color_mode == 0) {
-      for (int ch = 0; ch < 3; ++ch) dcol[ch] += drgb[ch];
-    } else {
-      const DevCamera& c = cams[v];
-      const double vd[3] = {(double)mu[0] - c.o[0], (double)mu[1] - c.o[1], (double)mu[2] - c.o[2]};
-      const double dist = sqrt(vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]);
-      const float ux = (float)(vd[0] / dist), uy = (float)(vd[1] / dist), uz = (float)(vd[2] / dist);
-      float Y[16], dYx[16], dYy[16], dYz[16];
-      sh_basis3_grad(ux, uy, uz, Y, dYx, dYy, dYz);
-      float du[3] = {0.f, 0.f, 0.f};
-      for (int ch = 0; ch < 3; ++ch) {
-        float acc = 0.f;
-        for (int k = 0; k < 16; ++k) acc += g.color[(3 * k + ch) * n + i] * Y[k];
-        if (acc + 0.5f <= 0.f) continue;  // clamped channel
-        for (int k = 0; k < 16; ++k) {
-          const float cf = g.color[(3 * k + ch) * n + i];
-          dcol[3 * k + ch] += drgb[ch] * Y[k];
-          du[0] += drgb[ch] * cf * dYx[k];
-          du[1] += drgb[ch] * cf * dYy[k];
-          du[2] += drgb[ch] * cf * dYz[k];
-        }
+  }
+  // colour, one channel at a time so that a thread holds 16 coefficients, 16 basis
+  // values and 16 accumulators (views again in index order)
+  if (g.color_mode == 0) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.f;
+#pragma unroll 1
+      for (int v = 0; v < n_views; ++v) acc += item_grad[((int64_t)v * n + i) * kGradLen + 16 + ch];
+      d_color[(int64_t)ch * n + i] = acc;
+    }
+  } else {
+#pragma unroll 1
+    for (int ch = 0; ch < 3; ++ch) {
+      float cf[16], dcol[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        cf[k] = g.color[(int64_t)(3 * k + ch) * n + i];
+        dcol[k] = 0.f;
       }
-      // u = v / |v|
-      const float ud = du[0] * ux + du[1] * uy + du[2] * uz;
-      const float idist = (float)(1.0 / dist);
-      dmu[0] += (du[0] - ud * ux) * idist;
-      dmu[1] += (du[1] - ud * uy) * idist;
-      dmu[2] += (du[2] - ud * uz) * idist;
+#pragma unroll 1
+      for (int v = 0; v < n_views; ++v) {
+        const float drgb = item_grad[((int64_t)v * n + i) * kGradLen + 16 + ch];
+        const DevCamera& c = cams[v];
+        const double vd[3] = {(double)mu[0] - c.o[0], (double)mu[1] - c.o[1], (double)mu[2] - c.o[2]};
+        const double dist = sqrt(vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]);
+        const float ux = (float)(vd[0] / dist), uy = (float)(vd[1] / dist), uz = (float)(vd[2] / dist);
+        float Y[16];
+        sh_basis3(ux, uy, uz, Y);
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += cf[k] * Y[k];
+        const float dc = acc + 0.5f <= 0.f ? 0.f : drgb;  // a clamped channel passes nothing back
+#pragma unroll
+        for (int k = 0; k < 16; ++k) dcol[k] += dc * Y[k];
+        // through the direction u = v / |v|: du = dc sum_k cf_k grad Y_k
+        float du[3];
+        sh_basis3_vjp(ux, uy, uz, cf, du);
+        du[0] *= dc;
+        du[1] *= dc;
+        du[2] *= dc;
+        const float ud = du[0] * ux + du[1] * uy + du[2] * uz;
+        const float idist = (float)(1.0 / dist);
+        dmu[0] += (du[0] - ud * ux) * idist;
+        dmu[1] += (du[1] - ud * uy) * idist;
+        dmu[2] += (du[2] - ud * uz) * idist;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) d_color[(int64_t)(3 * k + ch) * n + i] = dcol[k];
     }
   }
   // sigma_eff = sigma * prod s / s'
@@ -354,7 +339,6 @@ __global__ void k_preprocess_bwd(GaussPtrs g, const DevCamera* __restrict__ cams
   d_quats[n + i] = (dx - dot * x) * qn;
   d_quats[2 * n + i] = (dy - dot * y) * qn;
   d_quats[3 * n + i] = (dz - dot * z) * qn;
-  for (int k = 0; k < ncol; ++k) d_color[(int64_t)k * n + i] = dcol[k];
 }
 
 template <int FILTER, bool MARGINAL>
@@ -398,8 +382,9 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
   }
   {
     ProfScope ps(ST_BWD_REDUCE, s);
-    k_reduce_items<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(st->counts, st->offsets, nv, partial,
-                                                                          item_grad);
+    const int64_t waves = (nv + kReduceItemsPerWave - 1) / kReduceItemsPerWave;
+    k_reduce_items<<<dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s>>>(st->counts, st->offsets, nv, partial,
+                                                                         item_grad);
     CG_HIP(hipGetLastError());
   }
   {
