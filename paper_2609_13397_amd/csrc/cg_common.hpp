@@ -44,12 +44,14 @@ struct TileCone {
   float sb, cb, cmax, pad;
 };
 
-// Per (view, Gaussian) record read by the render kernels (112 bytes, 16-byte aligned).
-// The first 16 bytes are the cull cone: a ray d can only reach alpha_min if
-// |d - u| <= lim, with u the unit direction from the camera centre to the mean (the
-// influence cone of the binning as a chord length; lim < 0: never, lim >= 2: always).
+// Per (view, Gaussian) render record (128 bytes).  Cull cone: a ray direction d can
+// reach the Gaussian only if |d - u| <= lim, u = v / |v| (the influence cone of the
+// binning as a chord length; lim < 0: never, lim >= 2: always).  Tangent-cone test:
+// with n = v x d, D^2(d) = n^T Sigma' n / (P^2 |W d|^2) (P = s'_1 s'_2 s'_3), and
+// S = Sigma' / (Lambda P^2) turns the pre-rejection bound D^2 <= Lambda into
+// n^T S n <= |W d|^2 (S = 0 accepts every ray).
 struct alignas(16) Record {
-  float ux, uy, uz, lim;   // cull cone: direction to the mean, chord limit
+  float vx, vy, vz, lim;   // v = mu - o rounded from FP64; chord limit of the cull cone
   float W[9];              // whitening diag(1/s') R^T, row-major
   float mu[3];             // mean
   float sigma;             // effective opacity sigma_eff (Eq. 10)
@@ -58,9 +60,9 @@ struct alignas(16) Record {
   float rho2;              // floor variance (0 when the floor is off)
   float Lg;                // 2 ln(sigma_eff / alpha_min): bound of the pre-rejection
   float kg;                // 1 / min(s'^2)
-  float pad[2];
+  float S[6];              // S00, 2 S01, 2 S02, S11, 2 S12, S22
 };
-static_assert(sizeof(Record) == 112, "Record layout");
+static_assert(sizeof(Record) == 128, "Record layout");
 
 struct Opts {
   int filter_mode, use_floor, composition;

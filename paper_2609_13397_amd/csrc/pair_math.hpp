@@ -56,17 +56,22 @@ struct PairGeom {
   float D2, tstar;
 };
 
-// Geometry part: a, t*, q, D^2.  Returns false when t* <= t_near (T = 0).
-__device__ __forceinline__ bool pair_geom(const Record& R, const PairPixel& p, const Origin& O, float t_near,
-                                          PairGeom& g) {
-  const double vx = (double)R.mu[0] - O.x, vy = (double)R.mu[1] - O.y, vz = (double)R.mu[2] - O.z;
-  const double te = vx * p.d0 + vy * p.d1 + vz * p.d2;
-  const float wx = (float)(vx - te * p.d0), wy = (float)(vy - te * p.d1), wz = (float)(vz - te * p.d2);
+// a = W d and 1 / |a|^2.
+__device__ __forceinline__ float pair_dir(const Record& R, const PairPixel& p, PairGeom& g) {
   const float* W = R.W;
   g.ax = W[0] * p.a0 + W[1] * p.a1 + W[2] * p.a2;
   g.ay = W[3] * p.a0 + W[4] * p.a1 + W[5] * p.a2;
   g.az = W[6] * p.a0 + W[7] * p.a1 + W[8] * p.a2;
-  g.rn = fast_rcp(g.ax * g.ax + g.ay * g.ay + g.az * g.az);
+  return g.ax * g.ax + g.ay * g.ay + g.az * g.az;
+}
+
+// Geometry after pair_dir: t*, q, D^2.  Returns false when t* <= t_near (T = 0).
+__device__ __forceinline__ bool pair_geom_rest(const Record& R, const PairPixel& p, const Origin& O, float t_near,
+                                               PairGeom& g) {
+  const double vx = (double)R.mu[0] - O.x, vy = (double)R.mu[1] - O.y, vz = (double)R.mu[2] - O.z;
+  const double te = vx * p.d0 + vy * p.d1 + vz * p.d2;
+  const float wx = (float)(vx - te * p.d0), wy = (float)(vy - te * p.d1), wz = (float)(vz - te * p.d2);
+  const float* W = R.W;
   // y = o_u + t_e a = -W w
   const float yx = -(W[0] * wx + W[1] * wy + W[2] * wz);
   const float yy = -(W[3] * wx + W[4] * wy + W[5] * wz);
@@ -78,6 +83,13 @@ __device__ __forceinline__ bool pair_geom(const Record& R, const PairPixel& p, c
   g.qz = yz - f * g.az;
   g.D2 = g.qx * g.qx + g.qy * g.qy + g.qz * g.qz;
   return g.tstar > t_near;
+}
+
+// Geometry part: a, t*, q, D^2.  Returns false when t* <= t_near (T = 0).
+__device__ __forceinline__ bool pair_geom(const Record& R, const PairPixel& p, const Origin& O, float t_near,
+                                          PairGeom& g) {
+  g.rn = fast_rcp(pair_dir(R, p, g));
+  return pair_geom_rest(R, p, O, t_near, g);
 }
 
 // Footprint part in the 2x2 form.
@@ -137,17 +149,24 @@ __device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, floa
   return true;
 }
 
-// The cheap tests of one pair, in order: the ray against the Gaussian's influence
-// cone (chord test), t* > t_near, and the pre-rejection D^2 <= L (1 + tr Sigma_fp^u)
-// with tr Sigma_fp^u <= t*^2 c_pix / s'_min^2, which bounds q^T A^{-1} q from below
-// (Sigma_render^u is dominated by Sigma_fp^u).  False means the pair cannot reach
-// alpha_min.  On true, g holds the geometry of Eq. 2.
+// The cheap tests of one pair, in order: the tangent-cone test n^T S n <= |W d|^2
+// (n = v x d; it passes every ray that can meet the pre-rejection bound below),
+// t* > t_near, and the pre-rejection D^2 <= L (1 + tr Sigma_fp^u) with tr Sigma_fp^u
+// <= t*^2 c_pix / s'_min^2, which bounds q^T A^{-1} q from below (Sigma_render^u is
+// dominated by Sigma_fp^u).  False means the pair cannot reach alpha_min.  On true, g
+// holds the geometry of Eq. 2.
 template <int FILTER>
 __device__ __forceinline__ bool pair_cheap(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
                                            PairGeom& g) {
-  const float cx = p.a0 - R.ux, cy = p.a1 - R.uy, cz = p.a2 - R.uz;
-  if (cx * cx + cy * cy + cz * cz > R.lim * R.lim || R.lim < 0.f) return false;
-  if (!pair_geom(R, p, O, o.t_near, g)) return false;
+  const float nx = R.vy * p.a2 - R.vz * p.a1;
+  const float ny = R.vz * p.a0 - R.vx * p.a2;
+  const float nz = R.vx * p.a1 - R.vy * p.a0;
+  const float aa = pair_dir(R, p, g);
+  const float* S = R.S;
+  const float nsn = nx * (S[0] * nx + S[1] * ny + S[2] * nz) + ny * (S[3] * ny + S[4] * nz) + S[5] * nz * nz;
+  if (nsn > aa) return false;
+  g.rn = fast_rcp(aa);
+  if (!pair_geom_rest(R, p, O, o.t_near, g)) return false;
   if (FILTER == 0) return g.D2 <= R.Lg;
   return g.D2 <= R.Lg * fmaf(g.tstar * g.tstar * p.cpix, R.kg, 1.f) * 1.0001f + 1e-6f;
 }

@@ -69,19 +69,17 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
   r.rho2 = rho2;
   const float sp2min = fminf(sp2[0], fminf(sp2[1], sp2[2]));
   r.kg = 1.f / sp2min;
-  r.pad[0] = 0.f;
-  r.pad[1] = 0.f;
 
   // direction and distance from the camera centre in FP64
   const double vd[3] = {(double)mu[0] - c.o[0], (double)mu[1] - c.o[1], (double)mu[2] - c.o[2]};
   const double dist = sqrt(vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]);
-  const float vx = (float)(vd[0] / dist), vy = (float)(vd[1] / dist), vz = (float)(vd[2] / dist);
+  const float ux = (float)(vd[0] / dist), uy = (float)(vd[1] / dist), uz = (float)(vd[2] / dist);
 
   if (g.color_mode == 0) {
     for (int ch = 0; ch < 3; ++ch) r.rgb[ch] = g.color[ch * n + i];
   } else {
     float Y[16];
-    sh_basis3(vx, vy, vz, Y);
+    sh_basis3(ux, uy, uz, Y);
     for (int ch = 0; ch < 3; ++ch) {
       float acc = 0.f;
       for (int k = 0; k < 16; ++k) acc += g.color[(3 * k + ch) * n + i] * Y[k];
@@ -133,14 +131,52 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
   } else {
     r.Lg = 0.f;
   }
-  r.ux = vx;
-  r.uy = vy;
-  r.uz = vz;
+  // Tangent-cone test.  The render's pre-rejection accepts a pair only if D^2 <=
+  // Lambda(t*) = L (1 + t*^2 c k)(1 + 1e-4) + 1e-6 (c <= the view's largest pixel
+  // footprint coefficient, k = 1 / s'_min^2), and t* <= |v| + s'_max D (the
+  // max-response point lies within s'_max D of the mean), which closes into a
+  // quadratic bound D <= D_max.  D_max is widened by the rounding of the float32
+  // test: n = v x d from float32 v and d is off by a few ulp of |v|, which moves the
+  // tested D by at most that times s'_max / (s'_min s'_mid).  S = 0 (accept all) when
+  // the bound does not close or S would not fit float32.
+  double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (gamma >= 0.f && dist > 0.0) {
+    const double L = (double)r.Lg, kk = (double)r.kg;
+    const double cw = o.filter_mode == CG_FILTER_CENTER_RAY ? 0.0 : (double)view_cmax[v] * 1.01;
+    const double A0 = 1.0001 * L + 1e-6, B0 = 1.0001 * L * cw * kk;
+    double s2[3] = {(double)sp2[0], (double)sp2[1], (double)sp2[2]};
+    double lo = fmin(s2[0], fmin(s2[1], s2[2])), hi = fmax(s2[0], fmax(s2[1], s2[2]));
+    const double mid = s2[0] + s2[1] + s2[2] - lo - hi;
+    const double smax = sqrt(hi), bs2 = B0 * hi;
+    if (bs2 < 0.99) {
+      const double bvs = B0 * dist * smax;
+      double Dm = (bvs + sqrt(bvs * bvs + (1.0 - bs2) * (A0 + B0 * dist * dist))) / (1.0 - bs2);
+      Dm = Dm * 1.0002 + 1e-6 * dist * smax / sqrt(lo * mid) + 1e-5;
+      const double scale = 1.0 / (Dm * Dm * s2[0] * s2[1] * s2[2]);
+      // Sigma' = R diag(s'^2) R^T
+      double Sg[6];
+      const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+      bool ok = true;
+      for (int e = 0; e < 6; ++e) {
+        const int a = ij[e][0], b = ij[e][1];
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += (double)R[3 * a + k] * s2[k] * (double)R[3 * b + k];
+        Sg[e] = acc * scale * (a == b ? 1.0 : 2.0);
+        ok = ok && fabs(Sg[e]) < 1e30;
+      }
+      if (ok)
+        for (int e = 0; e < 6; ++e) S[e] = Sg[e];
+    }
+  }
+  for (int e = 0; e < 6; ++e) r.S[e] = (float)S[e];
+  r.vx = (float)vd[0];
+  r.vy = (float)vd[1];
+  r.vz = (float)vd[2];
   if (gamma < 0.f) r.lim = -1.f;
   else if (gamma >= kPiF) r.lim = 3.f;
   else r.lim = 2.f * sinf(0.5f * gamma) + 1e-5f;
   rec[out] = r;
-  cone[out] = make_float4(vx, vy, vz, gamma);
+  cone[out] = make_float4(ux, uy, uz, gamma);
 }
 
 hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,

@@ -55,8 +55,10 @@ __device__ __forceinline__ WaveConeB wave_cone_b(const PixelRay& r) {
   return w;
 }
 
+// Four waves per SIMD: the register budget (128 VGPRs) that pair_grad fits in without
+// spilling.
 template <int FILTER, bool MARGINAL>
-__global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                     int per_xcd, Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ sorted_gid,
@@ -119,7 +121,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const DevCamera* __restrict_
       bool rel = false;
       if (lane < cnt) {
         const Record& R = srec[lane];
-        const float dx = wc.ax - R.ux, dy = wc.ay - R.uy, dz = wc.az - R.uz;
+        const float vv = R.vx * R.vx + R.vy * R.vy + R.vz * R.vz;
+        const float iv = vv > 0.f ? rsqrtf(vv) : 0.f;  // v = 0 only for records seen in every direction
+        const float dx = wc.ax - R.vx * iv, dy = wc.ay - R.vy * iv, dz = wc.az - R.vz * iv;
         const float lim = R.lim + wc.rad;
         rel = R.lim >= 0.f && dx * dx + dy * dy + dz * dz <= lim * lim;
       }

@@ -1,13 +1,21 @@
 // Tile render: one 256-thread workgroup per 16x16 tile, one pixel per thread, one 8x8
 // quadrant per wavefront.  The tile's depth-sorted list of Gaussians is walked in
-// batches of 256 records staged in LDS; each wavefront keeps the records whose
+// batches of kFwdBatch records staged in LDS; each wavefront keeps the records whose
 // influence cone can reach its quadrant, and every pixel evaluates the filtered
 // closed-form response of Eq. 9 (with the marginal floor composition of Eq. 12) and
 // composites front to back (Eq. 4).  The workgroup stops fetching batches once every
 // pixel has terminated.
 #include "pair_math.hpp"
+#include "wave_ops.hpp"
 
 namespace cg {
+
+// Records staged per batch (128 B each, loaded by the first kFwdBatch threads).  With
+// 16 KiB of LDS per workgroup and at most 64 VGPRs (amdgpu_waves_per_eu(8) on the
+// kernel), eight waves per SIMD stay resident: the loop is VALU-bound with long LDS
+// and FP64 latencies, which more resident waves hide.
+constexpr int kFwdBatch = 128;
+static_assert(kFwdBatch % 64 == 0 && kFwdBatch <= 256, "one record per thread, whole waves");
 
 // Wave-level view of a tile: wave w renders the 8x8 quadrant (w % 2, w / 2) of the
 // 16x16 tile.  Its cone (axis = normalised mean of the quadrant's centre rays, chord
@@ -22,12 +30,10 @@ struct WaveCone {
 __device__ __forceinline__ WaveCone wave_cone(const PixelRay& r) {
   float sx = r.valid ? r.df[0] : 0.f, sy = r.valid ? r.df[1] : 0.f, sz = r.valid ? r.df[2] : 0.f;
   float cnt = r.valid ? 1.f : 0.f;
-  for (int o = 32; o > 0; o >>= 1) {
-    sx += __shfl_xor(sx, o);
-    sy += __shfl_xor(sy, o);
-    sz += __shfl_xor(sz, o);
-    cnt += __shfl_xor(cnt, o);
-  }
+  sx = wave_total(sx);
+  sy = wave_total(sy);
+  sz = wave_total(sz);
+  cnt = wave_total(cnt);
   WaveCone w;
   w.live = cnt > 0.f;
   const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
@@ -40,7 +46,7 @@ __device__ __forceinline__ WaveCone wave_cone(const PixelRay& r) {
     const float dx = w.ax - r.df[0], dy = w.ay - r.df[1], dz = w.az - r.df[2];
     ch = sqrtf(dx * dx + dy * dy + dz * dz);
   }
-  for (int o = 32; o > 0; o >>= 1) ch = fmaxf(ch, __shfl_xor(ch, o));
+  ch = wave_max(ch);
   w.rad = ch * 1.0001f + 2e-6f;
   if (nrm < 0.5f * cnt) w.rad = 3.f;  // rays spread too widely for a mean axis
   return w;
@@ -49,13 +55,13 @@ __device__ __forceinline__ WaveCone wave_cone(const PixelRay& r) {
 // COUNT: also count, per pixel, the pairs that reached the per-pixel tests, those that
 // needed the full footprint arithmetic and those composited, into counters[0..2].
 template <int FILTER, bool MARGINAL, bool COUNT>
-__global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                 int per_xcd, Opts o, const Record* __restrict__ rec, int64_t n_gauss,
                                                 const uint2* __restrict__ ranges,
                                                 const uint32_t* __restrict__ sorted_gid, float* __restrict__ out_rgba,
                                                 float* __restrict__ final_T, uint32_t* __restrict__ n_last,
                                                 unsigned long long* __restrict__ counters) {
-  __shared__ Record srec[256];
+  __shared__ Record srec[kFwdBatch];
   __shared__ unsigned int scount[3];
   uint32_t c_eval = 0, c_full = 0, c_contrib = 0;
   // Workgroup b is dispatched to XCD b % 8: hand each XCD a contiguous band of tiles,
@@ -83,18 +89,20 @@ __global__ __launch_bounds__(256) void k_render(const DevCamera* __restrict__ ca
   bool done = !r.valid;
   uint32_t last = rg.x;
   const Record* vrec = rec + (int64_t)v * n_gauss;
-  for (uint32_t base = rg.x; base < rg.y; base += 256) {
+  for (uint32_t base = rg.x; base < rg.y; base += kFwdBatch) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t idx = base + threadIdx.x;
-    if (idx < rg.y) srec[threadIdx.x] = vrec[sorted_gid[idx]];
+    if ((int)threadIdx.x < kFwdBatch && idx < rg.y) srec[threadIdx.x] = vrec[sorted_gid[idx]];
     __syncthreads();
-    const int cnt = (int)min(256u, rg.y - base);
+    const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - base);
     if (wc.live && __ballot(!done) != 0) {
       for (int sub = 0; sub < cnt; sub += 64) {
         bool rel = false;
         if (sub + lane < cnt) {
           const Record& R = srec[sub + lane];
-          const float dx = wc.ax - R.ux, dy = wc.ay - R.uy, dz = wc.az - R.uz;
+          const float vv = R.vx * R.vx + R.vy * R.vy + R.vz * R.vz;
+          const float iv = vv > 0.f ? rsqrtf(vv) : 0.f;  // v = 0 only for records seen in every direction
+          const float dx = wc.ax - R.vx * iv, dy = wc.ay - R.vy * iv, dz = wc.az - R.vz * iv;
           const float lim = R.lim + wc.rad;
           rel = R.lim >= 0.f && dx * dx + dy * dy + dz * dz <= lim * lim;
         }

@@ -68,7 +68,7 @@ struct cg_server {
     const int64_t px = (int64_t)cam.crop_w * cam.crop_h;
     const int64_t tiles = (int64_t)((cam.crop_w + 15) / 16) * ((cam.crop_h + 15) / 16);
     const double pairs = sc.pairs_per_px * (double)px + 64.0 * (double)tiles;
-    return (size_t)(sc.g.n * 176 + pairs * 24.0 + (double)tiles * 48.0 + (double)px * 8.0 + (1 << 20));
+    return (size_t)(sc.g.n * 192 + pairs * 24.0 + (double)tiles * 48.0 + (double)px * 8.0 + (1 << 20));
   }
 
   bool can_admit_head() const {

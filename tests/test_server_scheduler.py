@@ -97,7 +97,7 @@ def test_hbm_budget_back_pressure():
     """With a budget that fits about two requests, admitted scratch never exceeds it and
     requests wait in the queue instead of failing."""
     g, o, keep = _fake_scene(n=100000)
-    one = 100000 * 176 + (1 << 20)  # the per-Gaussian part of a request's estimate
+    one = 100000 * 192 + (1 << 20)  # the per-Gaussian part of a request's estimate
     s = _server(n_workers=4, max_batch_views=1, hbm_budget_bytes=int(2.5 * one) + (1 << 21))
     sid = s.add_scene(g, o, keep)
     for _ in range(20):
