@@ -120,12 +120,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (wc.live && __ballot(!done) != 0) {
       bool rel = false;
       if (lane < cnt) {
-        const Record& R = srec[lane];
-        const float vv = R.vx * R.vx + R.vy * R.vy + R.vz * R.vz;
-        const float iv = vv > 0.f ? rsqrtf(vv) : 0.f;  // v = 0 only for records seen in every direction
-        const float dx = wc.ax - R.vx * iv, dy = wc.ay - R.vy * iv, dz = wc.az - R.vz * iv;
-        const float lim = R.lim + wc.rad;
-        rel = R.lim >= 0.f && dx * dx + dy * dy + dz * dz <= lim * lim;
+        rel = record_reaches_cone(srec[lane], wc.ax, wc.ay, wc.az, wc.rad);
       }
       uint64_t m = __ballot(rel);
       while (m) {

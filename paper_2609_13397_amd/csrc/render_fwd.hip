@@ -99,12 +99,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       for (int sub = 0; sub < cnt; sub += 64) {
         bool rel = false;
         if (sub + lane < cnt) {
-          const Record& R = srec[sub + lane];
-          const float vv = R.vx * R.vx + R.vy * R.vy + R.vz * R.vz;
-          const float iv = vv > 0.f ? rsqrtf(vv) : 0.f;  // v = 0 only for records seen in every direction
-          const float dx = wc.ax - R.vx * iv, dy = wc.ay - R.vy * iv, dz = wc.az - R.vz * iv;
-          const float lim = R.lim + wc.rad;
-          rel = R.lim >= 0.f && dx * dx + dy * dy + dz * dz <= lim * lim;
+          rel = record_reaches_cone(srec[sub + lane], wc.ax, wc.ay, wc.az, wc.rad);
         }
         uint64_t m = __ballot(rel);
         while (m) {
