@@ -30,13 +30,17 @@ FLOPS_PER_PAIR = {True: 225, False: 156}
 TRANSC_PER_PAIR = {True: 8, False: 4}
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
-# Algorithmic HBM bytes of one render launch: per pair a 4-byte list entry and a
-# 96-byte record; per pixel the 16-byte RGBA output.
-BYTES_PER_PAIR = 100
+# Algorithmic HBM bytes of one render launch: per pair a 4-byte list entry and its
+# 128-byte record; per pixel the 16-byte RGBA output.
+BYTES_PER_PAIR = 132
 BYTES_PER_PIXEL = 16
 
+# sources whose change invalidates the measured HBM traffic of the render kernel (the
+# kernel itself, the pair arithmetic and culling it inlines, and the records it reads)
 RENDER_SOURCES = ["paper_2609_13397_amd/csrc/render_fwd.hip", "paper_2609_13397_amd/csrc/pair_math.hpp",
-                  "paper_2609_13397_amd/csrc/camera_dev.hpp", "paper_2609_13397_amd/csrc/cg_common.hpp"]
+                  "paper_2609_13397_amd/csrc/record_bounds.hpp", "paper_2609_13397_amd/csrc/camera_dev.hpp",
+                  "paper_2609_13397_amd/csrc/cg_common.hpp", "paper_2609_13397_amd/csrc/preprocess.hip"]
+TRAFFIC_KERNEL = "cg::k_render<1, true, false>"  # the anisotropic + marginal-floor variant the bench times
 
 
 def render_source_hash() -> str:
@@ -198,19 +202,88 @@ def cpu_baseline(scene_np, scene_rho2, cams, opts_kw, rows=16):
             "seconds": dt}
 
 
+def _counter_rows(path: str, counter: str):
+    import csv
+    with open(path) as f:
+        return [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+
+
+def summarize_traffic(fetch_csv: str, write_csv: str, commands) -> dict:
+    """profiles/render_traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, both with --copy-calibration): per-dispatch KiB of the render kernel,
+    each scaled by what the counter reads for the 256 MiB calibration copies."""
+    fetch = _counter_rows(fetch_csv, "FETCH_SIZE")
+    write = _counter_rows(write_csv, "WRITE_SIZE")
+
+    def pick(rows, name):
+        return [float(r["Counter_Value"]) for r in rows if name in r["Kernel_Name"]]
+
+    def copies(rows):
+        vals = sorted(((float(r["Counter_Value"]), r) for r in rows if "copyBuffer" in r["Kernel_Name"]),
+                      key=lambda x: -x[0])
+        return [v for v, _ in vals[:3]]
+
+    copy_kib = 256 * 1024
+    fc, wc = copies(fetch), copies(write)
+    ff = copy_kib / (sum(fc) / len(fc))
+    wf = copy_kib / (sum(wc) / len(wc))
+    fr, wr = pick(fetch, TRAFFIC_KERNEL), pick(write, TRAFFIC_KERNEL)
+    if not fr or not wr:
+        raise SystemExit(f"no {TRAFFIC_KERNEL} dispatches in the counter files")
+    per_launch = (sum(fr) / len(fr) * ff + sum(wr) / len(wr) * wf) * 1024
+    out = {"render_source_hash": render_source_hash(), "kernel": TRAFFIC_KERNEL, "workload": "fisheye_1M",
+           "fetch_kib_per_dispatch": fr, "write_kib_per_dispatch": wr,
+           "copy_calibration": {"bytes_kib": copy_kib, "fetch_kib": sum(fc) / len(fc), "write_kib": sum(wc) / len(wc),
+                                "fetch_factor": ff, "write_factor": wf},
+           "bytes_per_launch": per_launch, "commands": list(commands)}
+    with open(os.path.join(ROOT, "profiles", "render_traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def summarize_trace(stats_csv: str, out_md: str, title: str, commands, notes: str = ""):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    lines = [f"# {title}", "", "Command (run from the repository root on the GPU box):", "", "```", *commands, "```", ""]
+    if notes:
+        lines += [notes, ""]
+    lines += ["| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:20]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=16)
+    ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+    # offline summaries of rocprofv3 output into profiles/ (no GPU needed)
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT_MD"))
+    ap.add_argument("--title", default="")
+    ap.add_argument("--notes", default="")
+    ap.add_argument("--command", action="append", default=[], help="profiling command recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        t = summarize_traffic(*args.summarize_traffic, args.command)
+        print(json.dumps({k: t[k] for k in ("kernel", "bytes_per_launch", "copy_calibration")}))
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, args.title, args.command, args.notes)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
               "is described in DESIGN.md and is not built.", file=sys.stderr)

@@ -17,6 +17,7 @@
 #pragma once
 
 #include "camera_dev.hpp"
+#include "record_bounds.hpp"
 
 namespace cg {
 
@@ -169,31 +170,6 @@ __device__ __forceinline__ bool pair_cheap(const Record& R, const PairPixel& p, 
   if (!pair_geom_rest(R, p, O, o.t_near, g)) return false;
   if (FILTER == 0) return g.D2 <= R.Lg;
   return g.D2 <= R.Lg * fmaf(g.tstar * g.tstar * p.cpix, R.kg, 1.f) * 1.0001f + 1e-6f;
-}
-
-// Whether record R can pass pair_cheap for some ray d of a wave's cone |d - a| <= rad
-// (a unit).  Two conservative tests: the chord test of the influence cone, and the
-// tangent-cone test bounded over the cone: |(v x d)|_S >= |(v x a)|_S - sqrt(tr S) |v|
-// rad (lambda_max(S) <= tr S) and |W d| <= |W a| + rad / s'_min, so a wave for which
-// the lower bound of |n|_S exceeds the upper bound of |W d| has no pixel that passes.
-__device__ __forceinline__ bool record_reaches_cone(const Record& R, float ax, float ay, float az, float rad) {
-  if (R.lim < 0.f) return false;
-  const float vv = R.vx * R.vx + R.vy * R.vy + R.vz * R.vz;
-  const float iv = vv > 0.f ? rsqrtf(vv) : 0.f;  // v = 0 only for records seen in every direction
-  const float dx = ax - R.vx * iv, dy = ay - R.vy * iv, dz = az - R.vz * iv;
-  const float lim = R.lim + rad;
-  if (dx * dx + dy * dy + dz * dz > lim * lim) return false;
-  if (rad >= 2.f) return true;
-  const float nx = R.vy * az - R.vz * ay, ny = R.vz * ax - R.vx * az, nz = R.vx * ay - R.vy * ax;
-  const float* S = R.S;
-  const float nsn = nx * (S[0] * nx + S[1] * ny + S[2] * nz) + ny * (S[3] * ny + S[4] * nz) + S[5] * nz * nz;
-  const float* W = R.W;
-  const float wx = W[0] * ax + W[1] * ay + W[2] * az;
-  const float wy = W[3] * ax + W[4] * ay + W[5] * az;
-  const float wz = W[6] * ax + W[7] * ay + W[8] * az;
-  const float lo = sqrtf(fmaxf(nsn, 0.f)) * 0.9999f - sqrtf(S[0] + S[3] + S[5]) * (vv * iv) * rad;
-  const float hi = sqrtf(wx * wx + wy * wy + wz * wz) * 1.0001f + sqrtf(R.kg) * rad * 1.0001f;
-  return lo <= hi;
 }
 
 // Filtered response T of a pair that passed pair_cheap.  FILTER 0: centre ray (Eq. 3,
