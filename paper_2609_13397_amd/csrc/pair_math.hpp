@@ -55,6 +55,9 @@ struct PairGeom {
   float rn;           // 1 / |a|^2
   float qx, qy, qz;   // q
   float D2, tstar;
+  float wx, wy, wz;   // w = (I - d d^T)(mu - o), rounded from FP64
+  float yx, yy, yz;   // y = -W w = o_u + t_e a
+  float ya;           // y . a
 };
 
 // a = W d and 1 / |a|^2.
@@ -77,7 +80,10 @@ __device__ __forceinline__ bool pair_geom_rest(const Record& R, const PairPixel&
   const float yx = -(W[0] * wx + W[1] * wy + W[2] * wz);
   const float yy = -(W[3] * wx + W[4] * wy + W[5] * wz);
   const float yz = -(W[6] * wx + W[7] * wy + W[8] * wz);
-  const float f = (yx * g.ax + yy * g.ay + yz * g.az) * g.rn;
+  g.wx = wx; g.wy = wy; g.wz = wz;
+  g.yx = yx; g.yy = yy; g.yz = yz;
+  g.ya = yx * g.ax + yy * g.ay + yz * g.az;
+  const float f = g.ya * g.rn;
   g.tstar = (float)te - f;
   g.qx = yx - f * g.ax;
   g.qy = yy - f * g.ay;
@@ -122,31 +128,41 @@ __device__ __forceinline__ void pair_foot(const Record& R, const PairPixel& p, c
   f.h2 = (f.ey0 * g.qx + f.ey1 * g.qy + f.ey2 * g.qz) * isq3;
 }
 
+// Floor state of one pair: Phi = E^T S'^2 E / 3, its eigen-decomposition quantities and
+// G = g(Phi) (kept for the backward).
+struct PairFloor {
+  float G11, G12, G22;
+  float P11, P12, P22;
+  float dd, rr, lp, lm, gp;
+};
+
 // G = g(Phi) for the marginal composition; returns false when G = 0 (the floor
 // covers the footprint in every direction).
-__device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, float& G11, float& G12, float& G22) {
+__device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, PairFloor& fl) {
   constexpr float third = 1.f / 3.f;
-  const float P11 = (R.sp2[0] * f.ex0 * f.ex0 + R.sp2[1] * f.ex1 * f.ex1 + R.sp2[2] * f.ex2 * f.ex2) * third;
-  const float P12 = (R.sp2[0] * f.ex0 * f.ey0 + R.sp2[1] * f.ex1 * f.ey1 + R.sp2[2] * f.ex2 * f.ey2) * third;
-  const float P22 = (R.sp2[0] * f.ey0 * f.ey0 + R.sp2[1] * f.ey1 * f.ey1 + R.sp2[2] * f.ey2 * f.ey2) * third;
-  const float m = 0.5f * (P11 + P22), dd = 0.5f * (P11 - P22);
-  const float rr = sqrtf(dd * dd + P12 * P12);
-  const float lp = m + rr, lm = m - rr;
+  fl.P11 = (R.sp2[0] * f.ex0 * f.ex0 + R.sp2[1] * f.ex1 * f.ex1 + R.sp2[2] * f.ex2 * f.ex2) * third;
+  fl.P12 = (R.sp2[0] * f.ex0 * f.ey0 + R.sp2[1] * f.ex1 * f.ey1 + R.sp2[2] * f.ex2 * f.ey2) * third;
+  fl.P22 = (R.sp2[0] * f.ey0 * f.ey0 + R.sp2[1] * f.ey1 * f.ey1 + R.sp2[2] * f.ey2 * f.ey2) * third;
+  const float m = 0.5f * (fl.P11 + fl.P22);
+  fl.dd = 0.5f * (fl.P11 - fl.P22);
+  fl.rr = sqrtf(fl.dd * fl.dd + fl.P12 * fl.P12);
+  fl.lp = m + fl.rr;
+  fl.lm = m - fl.rr;
   const float rho2 = R.rho2;
-  if (lp <= rho2) return false;
-  const float gp = 1.f - rho2 / lp;
+  if (fl.lp <= rho2) return false;
+  fl.gp = 1.f - rho2 / fl.lp;
   float gm, beta;
-  if (lm > rho2) {
-    gm = 1.f - rho2 / lm;
-    beta = rho2 / (lp * lm);
+  if (fl.lm > rho2) {
+    gm = 1.f - rho2 / fl.lm;
+    beta = rho2 / (fl.lp * fl.lm);
   } else {
     gm = 0.f;
-    beta = gp / (2.f * rr);
+    beta = fl.gp / (2.f * fl.rr);
   }
-  const float gbar = 0.5f * (gp + gm);
-  G11 = gbar + beta * dd;
-  G22 = gbar - beta * dd;
-  G12 = beta * P12;
+  const float gbar = 0.5f * (fl.gp + gm);
+  fl.G11 = gbar + beta * fl.dd;
+  fl.G22 = gbar - beta * fl.dd;
+  fl.G12 = beta * fl.P12;
   return true;
 }
 
@@ -175,15 +191,20 @@ __device__ __forceinline__ bool pair_cheap(const Record& R, const PairPixel& p, 
 // Filtered response T of a pair that passed pair_cheap.  FILTER 0: centre ray (Eq. 3,
 // C = 1); 1: anisotropic (Eq. 9); 2: isotropic in-plane covariance of the same trace.
 // MARGINAL: floor composition by Eq. 12 (records with rho2 = 0 take the plain path).
+// The footprint and floor state are left in f and fl for the backward.
 template <int FILTER, bool MARGINAL>
-__device__ __forceinline__ float pair_full(const Record& R, const PairPixel& p, const PairGeom& g) {
+__device__ __forceinline__ float pair_full_keep(const Record& R, const PairPixel& p, const PairGeom& g, PairFoot& f,
+                                                PairFloor& fl, bool& filt) {
+  filt = true;
   if (FILTER == 0) return R.sigma * __expf(-0.5f * g.D2);
-  PairFoot f;
   pair_foot(R, p, g, f);
-  float G11 = 1.f, G12 = 0.f, G22 = 1.f;
-  bool filt = true;
-  if (MARGINAL && R.rho2 > 0.f) filt = floor_G(R, f, G11, G12, G22);
+  fl.G11 = 1.f;
+  fl.G12 = 0.f;
+  fl.G22 = 1.f;
+  fl.P11 = fl.P12 = fl.P22 = fl.dd = fl.rr = fl.lp = fl.lm = fl.gp = 0.f;
+  if (MARGINAL && R.rho2 > 0.f) filt = floor_G(R, f, fl);
   if (!filt) return R.sigma * __expf(-0.5f * g.D2);
+  const float G11 = fl.G11, G12 = fl.G12, G22 = fl.G22;
   if (FILTER == 2) {
     const float tau = (MARGINAL && R.rho2 > 0.f) ? (G11 * f.K11 + 2.f * G12 * f.K12 + G22 * f.K22) : (f.K11 + f.K22);
     const float s = 1.f + 0.5f * tau;
@@ -207,6 +228,14 @@ __device__ __forceinline__ float pair_full(const Record& R, const PairPixel& p, 
   return R.sigma * rsqrtf(det) * __expf(-0.5f * (g.D2 - quad));
 }
 
+template <int FILTER, bool MARGINAL>
+__device__ __forceinline__ float pair_full(const Record& R, const PairPixel& p, const PairGeom& g) {
+  PairFoot f;
+  PairFloor fl;
+  bool filt;
+  return pair_full_keep<FILTER, MARGINAL>(R, p, g, f, fl, filt);
+}
+
 // Both parts; false when the pair cannot reach alpha_min (T is then not set).
 template <int FILTER, bool MARGINAL>
 __device__ __forceinline__ bool pair_response(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
@@ -223,26 +252,20 @@ namespace cg {
 
 // ---------------------------------------------------------------------------- backward
 // Gradient of one pair's response T with respect to its record: dL/dT = dT is given;
-// the result g[19] = (dW[9], dmu[3], dsigma, dsp2[3], pad...) is ADDED to.  The forward
-// intermediates are recomputed with the same code as pair_response, then every step is
-// differentiated in reverse order.  G = g(Phi) (the marginal composition) is
-// differentiated in closed form: with both eigenvalues above rho^2, G = I - rho^2 Phi^{-1};
-// with one, G = g+ u u^T (u the leading eigenvector); at the clamp kink the clamped
-// branch's (zero) derivative is used.
+// the result g[19] = (dW[9], dmu[3], dsigma, dsp2[3], pad...) is ADDED to.  gm, ft, fl
+// and filt are the forward intermediates left by pair_cheap and pair_full_keep for this
+// pair; every step is differentiated in reverse order.  G = g(Phi) (the marginal
+// composition) is differentiated in closed form: with both eigenvalues above rho^2,
+// G = I - rho^2 Phi^{-1}; with one, G = g+ u u^T (u the leading eigenvector); at the
+// clamp kink the clamped branch's (zero) derivative is used.
 template <int FILTER, bool MARGINAL>
-__device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
-                                          float dT, float T, float* __restrict__ g) {
-  PairGeom gm;
-  pair_geom(R, p, O, o.t_near, gm);
+__device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, const PairGeom& gm, const PairFoot& ft,
+                                          const PairFloor& fl, bool filt, float dT, float T,
+                                          float* __restrict__ g) {
   const float* W = R.W;
-  // forward recompute of the remaining intermediates
-  const double vx = (double)R.mu[0] - O.x, vy = (double)R.mu[1] - O.y, vz = (double)R.mu[2] - O.z;
-  const double te = vx * p.d0 + vy * p.d1 + vz * p.d2;
-  const float wx = (float)(vx - te * p.d0), wy = (float)(vy - te * p.d1), wz = (float)(vz - te * p.d2);
-  const float yx = -(W[0] * wx + W[1] * wy + W[2] * wz);
-  const float yy = -(W[3] * wx + W[4] * wy + W[5] * wz);
-  const float yz = -(W[6] * wx + W[7] * wy + W[8] * wz);
-  const float ya = yx * gm.ax + yy * gm.ay + yz * gm.az;
+  const float wx = gm.wx, wy = gm.wy, wz = gm.wz;
+  const float yx = gm.yx, yy = gm.yy, yz = gm.yz;
+  const float ya = gm.ya;
   const float f = ya * gm.rn;
 
   // adjoints
@@ -260,33 +283,20 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
   if (FILTER == 0) {
     dD2 = -0.5f * dlogT;
   } else {
-    PairFoot ft;
-    pair_foot(R, p, gm, ft);
-    float G11 = 1.f, G12 = 0.f, G22 = 1.f;
-    bool filt = true;
-    // floor quantities for the closed-form derivative of g(Phi)
-    float P11 = 0.f, P12 = 0.f, P22 = 0.f, lp = 0.f, rr = 0.f, gp = 0.f, c2 = 0.f, s2 = 0.f, detP = 0.f;
+    const float G11 = fl.G11, G12 = fl.G12, G22 = fl.G22;
+    const float P11 = fl.P11, P12 = fl.P12, P22 = fl.P22, lp = fl.lp, rr = fl.rr, gp = fl.gp;
+    float c2 = 0.f, s2 = 0.f, detP = 0.f;
     int gcase = 0;  // 0: no floor; 1: G = I - rho^2 Phi^-1; 2: G = g+ u u^T; 3: G = 0
     const bool floor_on = MARGINAL && R.rho2 > 0.f;
     if (floor_on) {
-      constexpr float third = 1.f / 3.f;
-      P11 = (R.sp2[0] * ft.ex0 * ft.ex0 + R.sp2[1] * ft.ex1 * ft.ex1 + R.sp2[2] * ft.ex2 * ft.ex2) * third;
-      P12 = (R.sp2[0] * ft.ex0 * ft.ey0 + R.sp2[1] * ft.ex1 * ft.ey1 + R.sp2[2] * ft.ex2 * ft.ey2) * third;
-      P22 = (R.sp2[0] * ft.ey0 * ft.ey0 + R.sp2[1] * ft.ey1 * ft.ey1 + R.sp2[2] * ft.ey2 * ft.ey2) * third;
-      filt = floor_G(R, ft, G11, G12, G22);
-      const float m = 0.5f * (P11 + P22), dd = 0.5f * (P11 - P22);
-      rr = sqrtf(dd * dd + P12 * P12);
-      lp = m + rr;
-      const float lm = m - rr;
       if (!filt) {
         gcase = 3;
-      } else if (lm > R.rho2) {
+      } else if (fl.lm > R.rho2) {
         gcase = 1;
         detP = P11 * P22 - P12 * P12;
       } else {
         gcase = 2;
-        gp = 1.f - R.rho2 / lp;
-        c2 = dd / rr;
+        c2 = fl.dd / rr;
         s2 = P12 / rr;
       }
     }

@@ -132,8 +132,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         bool contrib = false;
         if (!done) {
           const Record& R = srec[k];
-          float T;
-          if (pair_response<FILTER, MARGINAL>(R, px, org, o, T)) {
+          // the forward's tests and response (pair_response), keeping the intermediates
+          // that the reverse pass needs
+          PairGeom gm;
+          PairFoot ft;
+          PairFloor fl;
+          bool filt = true;
+          if (pair_cheap<FILTER>(R, px, org, o, gm)) {
+            const float T = pair_full_keep<FILTER, MARGINAL>(R, px, gm, ft, fl, filt);
             const float alpha = fminf(T, o.alpha_max);
             if (alpha >= o.alpha_min) {
               const float test = Ttr * (1.f - alpha);
@@ -155,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 gv[16] = G0 * w;
                 gv[17] = G1 * w;
                 gv[18] = G2 * w;
-                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL>(R, px, org, o, dalpha, T, gv);
+                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL>(R, px, gm, ft, fl, filt, dalpha, T, gv);
                 Ttr = test;
               }
             }
