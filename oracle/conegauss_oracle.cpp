@@ -65,6 +65,7 @@ struct orc_opts {
   float alpha_min, alpha_max, T_min, t_near;
   float bg[3];
   float footprint_scale; // multiplies the neighbour-ray differentials
+  int32_t order_mode;    // 0 per-Gaussian key |mu - o|; 1 per-ray max-response depth t*
 };
 
 }  // extern "C"
@@ -602,6 +603,49 @@ CompositeOut composite(const std::vector<int64_t>& cand, const ViewGauss& vg, co
   return out;
 }
 
+// Per-ray compositing order (the front-to-back order of Eq. 4 by each pair's own
+// max-response depth t* along this pixel's ray, Sec. 3): the candidates stably sorted
+// by t*, so equal depths keep the per-Gaussian key order.  Two pairs that can both
+// composite and whose t* lie within a small relative band are a decision: an FP32
+// renderer may order them either way; swap_at[j] is the earlier one's position.
+constexpr double kBandOrder = 1e-5;
+
+struct RayOrder {
+  std::vector<int64_t> list;
+  int n_dec;
+  int64_t swap_a[kMaxDecisions], swap_b[kMaxDecisions];
+};
+
+template <class PairFn>
+RayOrder ray_order(const std::vector<int64_t>& cand, const orc_opts& op, PairFn pair) {
+  struct Item { double t; int64_t k; bool live; };
+  std::vector<Item> items;
+  items.reserve(cand.size());
+  for (int64_t k : cand) {
+    const PairResult pr = pair(k);
+    const bool live = pr.tstar > op.t_near * (1.0 - kBandNear) &&
+                      std::min(pr.T_raw, (double)op.alpha_max) >= op.alpha_min * (1.0 - kBandAlpha);
+    items.push_back(Item{pr.tstar, k, live});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.t < b.t; });
+  RayOrder ro;
+  ro.n_dec = 0;
+  ro.list.reserve(items.size());
+  int64_t prev = -1;
+  for (size_t q = 0; q < items.size(); ++q) {
+    ro.list.push_back(items[q].k);
+    if (!items[q].live) continue;
+    if (prev >= 0 && ro.n_dec < kMaxDecisions &&
+        std::fabs(items[q].t - items[prev].t) <= kBandOrder * std::max(1.0, std::fabs(items[q].t))) {
+      ro.swap_a[ro.n_dec] = prev;
+      ro.swap_b[ro.n_dec] = (int64_t)q;
+      ro.n_dec++;
+    }
+    prev = (int64_t)q;
+  }
+  return ro;
+}
+
 // ----------------------------------------------------------------------------- culling grid
 // Culled mode restricts each pixel's candidate list with a latitude-longitude grid of
 // directions around the camera centre.  A Gaussian is entered in every cell that may
@@ -876,19 +920,28 @@ int orc_render(const orc_gaussians* g, const orc_camera* cam, const orc_opts* op
       auto pair = [&](int64_t k) { return pair_response(vg.pre[k], o, r.d, r.dx, r.dy, *op); };
       std::vector<int64_t> culled;
       if (mode == 1) grid.candidates(r.d, culled);
-      const std::vector<int64_t>& cand = (mode == 1) ? culled : vg.order;
+      const std::vector<int64_t>& keyed = (mode == 1) ? culled : vg.order;
+      // order_mode 1: this ray's own t* order, with its near-ties as the first decisions
+      RayOrder ro;
+      ro.n_dec = 0;
+      if (op->order_mode == 1) ro = ray_order(keyed, *op, pair);
+      const std::vector<int64_t>& cand = (op->order_mode == 1) ? ro.list : keyed;
       const CompositeOut co = composite(cand, vg, *op, pair, -1);
+      const int n_all = std::min(kMaxDecisions, ro.n_dec + co.n_dec);
       for (int k = 0; k < 4; ++k) rgba[4 * p + k] = co.rgba[k];
-      if (n_dec) n_dec[p] = co.n_dec;
+      if (n_dec) n_dec[p] = n_all;
       if (n_contrib) n_contrib[p] = co.n_contrib;
       if (alt) {
         for (int f = 0; f < kMaxDecisions; ++f) {
-          if (f < co.n_dec) {
-            const CompositeOut ca = composite(cand, vg, *op, pair, f);
-            for (int k = 0; k < 4; ++k) alt[(p * kMaxDecisions + f) * 4 + k] = ca.rgba[k];
-          } else {
-            for (int k = 0; k < 4; ++k) alt[(p * kMaxDecisions + f) * 4 + k] = co.rgba[k];
+          CompositeOut ca = co;
+          if (f < ro.n_dec) {
+            std::vector<int64_t> swapped = ro.list;
+            std::swap(swapped[ro.swap_a[f]], swapped[ro.swap_b[f]]);
+            ca = composite(swapped, vg, *op, pair, -1);
+          } else if (f < n_all) {
+            ca = composite(cand, vg, *op, pair, f - ro.n_dec);
           }
+          for (int k = 0; k < 4; ++k) alt[(p * kMaxDecisions + f) * 4 + k] = ca.rgba[k];
         }
       }
     }
@@ -920,7 +973,8 @@ int orc_render_supersampled(const orc_gaussians* g, const orc_camera* cam, const
           continue;
         }
         auto pair = [&](int64_t k) { return pair_response(vg.pre[k], o, d, d, d, op); };
-        const CompositeOut co = composite(vg.order, vg, op, pair, -1);
+        const CompositeOut co =
+            composite(op.order_mode == 1 ? ray_order(vg.order, op, pair).list : vg.order, vg, op, pair, -1);
         for (int k = 0; k < 4; ++k) acc[k] += co.rgba[k];
       }
       for (int k = 0; k < 4; ++k) rgba[4 * p + k] = acc[k] / (double)n_sub;
@@ -986,6 +1040,8 @@ void orc_bake_rho2(const orc_gaussians* g, const orc_camera* cams, int32_t n_cam
 int orc_grad(const orc_gaussians* g, const orc_camera* cam, const orc_opts* op, const float* grad_rgba,
              const uint8_t* skip_px, int n_threads, double* d_means, double* d_log_scales, double* d_quats,
              double* d_opacity, double* d_color) {
+  // the compositing derivative below follows the per-Gaussian key order only
+  if (op->order_mode != 0) return -2;
   const orc_camera& c = *cam;
   const ViewGauss vg = setup_view(*g, c, *op);
   const double o[3] = {c.origin[0], c.origin[1], c.origin[2]};

@@ -42,17 +42,19 @@ class _Opts(C.Structure):
     _fields_ = [
         ("filter_mode", C.c_int32), ("use_floor", C.c_int32), ("composition", C.c_int32),
         ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("T_min", C.c_float), ("t_near", C.c_float),
-        ("bg", C.c_float * 3), ("footprint_scale", C.c_float),
+        ("bg", C.c_float * 3), ("footprint_scale", C.c_float), ("order_mode", C.c_int32),
     ]
 
 
 class Opts:
     """Render options (same meaning as the library's): filter_mode 0 centre ray,
     1 anisotropic footprint, 2 isotropic; use_floor applies Eq. 10 with rho^2;
-    composition 0 marginal (Eq. 12), 1 additive."""
+    composition 0 marginal (Eq. 12), 1 additive; order_mode 0 composites by the
+    per-Gaussian key |mu - o|, 1 by each ray's own max-response depth t*."""
 
     def __init__(self, filter_mode=1, use_floor=0, composition=0, alpha_min=1.0 / 255.0,
-                 alpha_max=0.99, T_min=1e-4, t_near=0.2, bg=(0.0, 0.0, 0.0), footprint_scale=1.0):
+                 alpha_max=0.99, T_min=1e-4, t_near=0.2, bg=(0.0, 0.0, 0.0), footprint_scale=1.0,
+                 order_mode=0):
         self.filter_mode = filter_mode
         self.use_floor = use_floor
         self.composition = composition
@@ -62,6 +64,7 @@ class Opts:
         self.t_near = t_near
         self.bg = tuple(bg)
         self.footprint_scale = footprint_scale
+        self.order_mode = order_mode
 
     @staticmethod
     def smooth(**kw):
@@ -82,6 +85,7 @@ class Opts:
         o.t_near = self.t_near
         o.bg[:] = list(self.bg)
         o.footprint_scale = self.footprint_scale
+        o.order_mode = self.order_mode
         return o
 
 
@@ -277,7 +281,9 @@ def grad(scene: dict, cams, grad_rgba, opts: Opts = None, skip=None, n_threads: 
         c = _cam(cam)
         g = np.ascontiguousarray(g, dtype=np.float32)
         skc = None if sk is None else np.ascontiguousarray(sk, dtype=np.uint8)
-        lib().orc_grad(_byref(s.c), _byref(c), _byref(o), _ptr(g), _ptr(skc), int(n_threads),
-                       _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
-                       _ptr(out["opacity_logits"]), _ptr(out["color"]))
+        rc = lib().orc_grad(_byref(s.c), _byref(c), _byref(o), _ptr(g), _ptr(skc), int(n_threads),
+                            _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+                            _ptr(out["opacity_logits"]), _ptr(out["color"]))
+        if rc != 0:
+            raise ValueError("the gradient oracle follows the per-Gaussian key order only (order_mode 0)")
     return out
