@@ -72,6 +72,29 @@ def build_workload(torch, R, synth, device):
     return scene_np, scene, cams
 
 
+def order_ray_bench(torch, R, scene, cams, out_key, steps, warmup):
+    """Per-ray compositing order (order_mode RAY) on the forward workload: throughput,
+    pending-buffer overflows, and how far its image is from the key-order image."""
+    opts = R.RenderOpts(filter_mode=R.FILTER_ANISOTROPIC, use_floor=True, order_mode=R.ORDER_RAY)
+    npx = out_key.shape[0]
+    out = torch.empty_like(out_key)
+    _, info, _ = R.render_forward(scene, cams, opts, out=out)
+    for _ in range(warmup):
+        R.render_forward(scene, cams, opts, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        R.render_forward(scene, cams, opts, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    diff = (out.double() - out_key.double()).abs().amax(dim=1)
+    return {"value": npx * steps / dt / 1e6, "unit": "Mpix/s", "ms_per_step": dt / steps * 1e3, "steps": steps,
+            "n_order_overflow": int(info["n_order_overflow"]),
+            "overflow_per_pixel": info["n_order_overflow"] / npx,
+            "diff_vs_key_order": {"max": float(diff.max()), "rmse": float(diff.pow(2).mean().sqrt()),
+                                  "frac_pixels_above_2e-4": float((diff > 2e-4).double().mean())}}
+
+
 def train_step_bench(torch, R, synth, device, steps, warmup):
     """fwd + L1 + bwd on the training-step workload: 1M Gaussians, 2 orbit pinholes + 2
     centre fisheyes at 1280x720, L1 loss against the render of a perturbed copy of the
@@ -267,6 +290,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-order", action="store_true", help="skip the per-ray compositing order leg")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
@@ -351,6 +375,15 @@ def main():
     if tr is not None:
         roofline["traffic"] = tr["bytes_per_launch"]
 
+    order_ray = None
+    if not args.no_order:
+        print("bench: per-ray compositing order", file=sys.stderr, flush=True)
+        R.render_forward(scene, cams, opts, out=out)
+        order_ray = order_ray_bench(torch, R, scene, cams, out.clone(), max(3, args.steps // 4),
+                                    max(1, args.warmup // 2))
+        print(f"bench: per-ray order {order_ray['ms_per_step']:.3f} ms/step, overflow "
+              f"{order_ray['n_order_overflow']}", file=sys.stderr, flush=True)
+
     fwd_bwd = None
     if not args.no_train:
         print("bench: training step (fwd + L1 + bwd)", file=sys.stderr, flush=True)
@@ -381,6 +414,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd,
+        "order_ray": order_ray,
         "serving": serving_res,
         "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in stages.items() if v["launches"]},
     }

@@ -95,6 +95,7 @@ typedef struct {
 
 enum { CG_FILTER_CENTER_RAY = 0, CG_FILTER_ANISOTROPIC = 1, CG_FILTER_ISOTROPIC = 2 };
 enum { CG_COMPOSE_MARGINAL = 0, CG_COMPOSE_ADDITIVE = 1 };
+enum { CG_ORDER_KEY = 0, CG_ORDER_RAY = 1 };
 
 /* Render options.  cg_default_opts fills the defaults given in brackets.
  *   filter_mode     CG_FILTER_* [ANISOTROPIC]: centre ray = Eq. 3 with C = 1;
@@ -111,7 +112,16 @@ enum { CG_COMPOSE_MARGINAL = 0, CG_COMPOSE_ADDITIVE = 1 };
  *   bg[3]           [0]     background, added as T_final * bg.
  *   footprint_scale [1]     multiplies the neighbour-ray differentials (0 = centre ray).
  *   count_pairs     [0]     when set, cg_fwd_stats also receives the pair counts below
- *                   (a counting variant of the render kernel; results are identical). */
+ *                   (a counting variant of the render kernel; results are identical).
+ *   order_mode      CG_ORDER_* [KEY]: the front-to-back order of Eq. 4.  KEY: one key
+ *                   per view and Gaussian, |mu - o| (ties by Gaussian index).  RAY: each
+ *                   pixel's pairs by their own max-response depth t* along its ray
+ *                   (Sec. 3).  RAY holds up to 16 pending pairs per pixel and composites
+ *                   one as soon as no later Gaussian of the tile's list can have a
+ *                   smaller t* (every record bounds its t* from below); a full buffer
+ *                   composites its smallest t* early, counted in
+ *                   cg_fwd_stats.n_order_overflow.  RAY is forward-only: state_out must
+ *                   be NULL (CG_ERR_UNSUPPORTED otherwise). */
 typedef struct {
   int32_t filter_mode;
   int32_t use_floor;
@@ -120,6 +130,7 @@ typedef struct {
   float bg[3];
   float footprint_scale;
   int32_t count_pairs;
+  int32_t order_mode;
 } cg_render_opts;
 
 /* Scratch allocator.  alloc returns device memory usable in stream order on `stream`
@@ -149,6 +160,8 @@ typedef struct {
   int64_t n_full;           /* ... that passed the cheap rejection (full Eq. 9 work) */
   int64_t n_contrib;        /* ... that were composited (alpha >= alpha_min, before
                                termination): the method's unit of work              */
+  int64_t n_order_overflow; /* order_mode RAY: pairs composited early because a
+                               pixel's pending buffer was full (else -1)            */
 } cg_fwd_stats;
 
 int cg_version(void);

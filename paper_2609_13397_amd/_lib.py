@@ -44,6 +44,7 @@ class CgOpts(C.Structure):
         ("filter_mode", C.c_int32), ("use_floor", C.c_int32), ("composition", C.c_int32),
         ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("T_min", C.c_float), ("t_near", C.c_float),
         ("bg", C.c_float * 3), ("footprint_scale", C.c_float), ("count_pairs", C.c_int32),
+        ("order_mode", C.c_int32),
     ]
 
 
@@ -58,7 +59,8 @@ class CgAllocator(C.Structure):
 class CgStats(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("n_tiles", C.c_int64), ("n_pixels", C.c_int64),
                 ("n_gaussian_views", C.c_int64), ("sort_bits", C.c_int32), ("reserved", C.c_int32),
-                ("n_evaluated", C.c_int64), ("n_full", C.c_int64), ("n_contrib", C.c_int64)]
+                ("n_evaluated", C.c_int64), ("n_full", C.c_int64), ("n_contrib", C.c_int64),
+                ("n_order_overflow", C.c_int64)]
 
 
 # Every symbol the header declares, with its ctypes signature.

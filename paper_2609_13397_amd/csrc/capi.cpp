@@ -122,6 +122,7 @@ Opts make_opts(const cg_render_opts& o) {
   CG_CHECK_ARG(std::isfinite(o.T_min) && o.T_min >= 0.f && o.T_min < 1.f, "T_min must be in [0, 1)");
   CG_CHECK_ARG(std::isfinite(o.t_near) && o.t_near >= 0.f, "t_near must be >= 0");
   CG_CHECK_ARG(std::isfinite(o.footprint_scale) && o.footprint_scale >= 0.f, "footprint_scale must be >= 0");
+  CG_CHECK_ARG(o.order_mode == CG_ORDER_KEY || o.order_mode == CG_ORDER_RAY, "order_mode must be 0 or 1");
   Opts r;
   r.filter_mode = o.filter_mode;
   r.use_floor = o.use_floor ? 1 : 0;
@@ -132,6 +133,8 @@ Opts make_opts(const cg_render_opts& o) {
   r.t_near = o.t_near;
   for (int k = 0; k < 3; ++k) r.bg[k] = o.bg[k];
   r.fs = o.footprint_scale;
+  r.order_mode = o.order_mode;
+  r.count_pairs = o.count_pairs ? 1 : 0;
   return r;
 }
 
@@ -176,6 +179,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
   CG_CHECK_ARG(n_views >= 1 && n_views <= 4096, "n_views must be in [1, 4096]");
   const GaussPtrs g = make_gauss(*g_in);
   const Opts o = make_opts(*opts_in);
+  if (o.order_mode == CG_ORDER_RAY && state_out)
+    throw Error(CG_ERR_UNSUPPORTED, "order_mode RAY is forward-only: pass state_out = NULL");
   std::vector<DevCamera> hc(n_views);
   int64_t total_tiles = 0, total_groups = 0, total_px = 0;
   for (int v = 0; v < n_views; ++v) {
@@ -298,25 +303,35 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
       CG_HIP(launch_tile_ranges(skeys, svals, slot_gid, P, ranges, st ? sorted_gid : nullptr, s));
     }
+    // counters [0..2]: pair counts (count_pairs); [3]: early composites (order_mode RAY)
+    const bool ray_order = o.order_mode == CG_ORDER_RAY;
     unsigned long long* counters = nullptr;
-    if (opts_in->count_pairs) {
+    if (opts_in->count_pairs || ray_order) {
       counters = sc.get_n<unsigned long long>(4);
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, s));
     }
+    float* tlo_suffix = nullptr;
+    if (ray_order && P > 0) {
+      ProfScope ps(ST_RANGES, s);
+      tlo_suffix = sc.get_n<float>(P);
+      CG_HIP(launch_order_bounds(dcams, n_views, (int)total_tiles, rec, n, ranges, sorted_gid, tlo_suffix, s));
+    }
     {
       ProfScope ps(ST_RENDER, s);
-      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sorted_gid, out_rgba, final_T,
-                               n_last, counters, s));
+      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sorted_gid, tlo_suffix, out_rgba,
+                               final_T, n_last, counters, s));
     }
-    unsigned long long host_counters[3] = {~0ull, ~0ull, ~0ull};
-    if (counters) {
+    unsigned long long host_counters[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+    if (counters && (opts_in->count_pairs || stats)) {
       CG_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
       CG_HIP(hipStreamSynchronize(s));
     }
+    if (!opts_in->count_pairs) host_counters[0] = host_counters[1] = host_counters[2] = ~0ull;
     if (stats) {
       stats->n_evaluated = (int64_t)host_counters[0];
       stats->n_full = (int64_t)host_counters[1];
       stats->n_contrib = (int64_t)host_counters[2];
+      stats->n_order_overflow = ray_order ? (int64_t)host_counters[3] : -1;
       stats->n_pairs = P;
       stats->n_tiles = total_tiles;
       stats->n_pixels = total_px;
@@ -373,6 +388,8 @@ void cg_default_opts(cg_render_opts* o) {
   o->t_near = 0.2f;
   o->bg[0] = o->bg[1] = o->bg[2] = 0.f;
   o->footprint_scale = 1.f;
+  o->count_pairs = 0;
+  o->order_mode = CG_ORDER_KEY;
 }
 
 cg_status cg_render_forward(const cg_gaussians* g, const cg_camera* cams, int32_t n_views,

@@ -69,6 +69,8 @@ struct Opts {
   float alpha_min, alpha_max, T_min, t_near;
   float bg[3];
   float fs;  // footprint scale
+  int order_mode;
+  int count_pairs;
 };
 
 struct GaussPtrs {
@@ -123,9 +125,15 @@ hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_al
                                int end_bit, void* temp, int* result_in_alt, hipStream_t s);
 
 // render_fwd.hip
+// Per pair of the sorted tile lists: the smallest lower bound of t* over the pair and
+// every later pair of its tile (order_mode RAY).
+hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_tiles, const Record* rec,
+                               int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* tlo_suffix,
+                               hipStream_t s);
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* out_rgba,
-                             float* final_T, uint32_t* n_last, unsigned long long* counters, hipStream_t s);
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid,
+                             const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
+                             unsigned long long* counters, hipStream_t s);
 
 // bake.hip
 hipError_t launch_bake_rho2(const GaussPtrs& g, const DevCamera* cams, int n_views, float t_near, float* rho2,

@@ -157,41 +157,264 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
 }
 
+// ---------------------------------------------------------------------------- per-ray order
+// order_mode RAY: each pixel composites its pairs in the order of their own t* along
+// its ray (Sec. 3).  The tile list is in key order, and every record bounds from below
+// the t* of any pair it can form (record_tstar_lower); with the suffix minimum of those
+// bounds over the rest of the list, a pending pair whose t* is at most that minimum can
+// no longer be preceded and is composited.  Pending pairs (t*, alpha, record index)
+// wait in a per-pixel buffer in registers; when it is full, its smallest t* is
+// composited early (counted: the order is exact when no pixel overflowed).
+constexpr int kRayBuf = 16;
+
+// Lower bound of t* over the pairs record R can form: pair_cheap admits only D <=
+// D_max (the tangent-cone test; D_max^2 = sum s'^2 / (tr S prod s'^2) from S =
+// Sigma' / (D_max^2 P^2)), and the max-response point lies within s'_max D of the
+// mean, so t* >= |v| - s'_max D_max.  Culled records give +inf, unbounded ones -inf.
+__device__ __forceinline__ float record_tstar_lower(const Record& R) {
+  if (R.lim < 0.f) return INFINITY;
+  const float trS = R.S[0] + R.S[3] + R.S[5];
+  if (!(trS > 0.f)) return -INFINITY;
+  const float vlen = sqrtf(R.vx * R.vx + R.vy * R.vy + R.vz * R.vz);
+  const float P2 = R.sp2[0] * R.sp2[1] * R.sp2[2];
+  const float dmax2 = (R.sp2[0] + R.sp2[1] + R.sp2[2]) / (trS * P2);
+  const float smax = sqrtf(fmaxf(R.sp2[0], fmaxf(R.sp2[1], R.sp2[2])));
+  return vlen * (1.f - 1e-5f) - smax * sqrtf(dmax2) * 1.0001f - 1e-6f;
+}
+
+// One workgroup per tile: tlo_suffix[j] = min of record_tstar_lower over list entries
+// j.. end of the tile, walking the list from its end in chunks of 256.
+__global__ __launch_bounds__(256) void k_order_bounds(const DevCamera* __restrict__ cams, int n_views,
+                                                      const Record* __restrict__ rec, int64_t n_gauss,
+                                                      const uint2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ sorted_gid,
+                                                      float* __restrict__ tlo_suffix) {
+  __shared__ float sm[256];
+  const int t = blockIdx.x;
+  const int v = view_of_tile(cams, n_views, t);
+  const Record* vrec = rec + (int64_t)v * n_gauss;
+  const uint2 rg = ranges[t];
+  float carry = INFINITY;
+  for (int64_t end = rg.y; end > (int64_t)rg.x; end -= 256) {
+    const int64_t idx = end - 1 - threadIdx.x;  // thread 0 holds the chunk's last entry
+    float x = idx >= (int64_t)rg.x ? record_tstar_lower(vrec[sorted_gid[idx]]) : INFINITY;
+    // inclusive min-scan over thread order = suffix minimum in list order
+    sm[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const float y = threadIdx.x >= (unsigned)off ? sm[threadIdx.x - off] : INFINITY;
+      __syncthreads();
+      x = fminf(x, y);
+      sm[threadIdx.x] = x;
+      __syncthreads();
+    }
+    if (idx >= (int64_t)rg.x) tlo_suffix[idx] = fminf(x, carry);
+    carry = fminf(carry, sm[255]);
+    __syncthreads();
+  }
+}
+
+template <int FILTER, bool MARGINAL, bool COUNT>
+__global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
+                                                    int per_xcd, Opts o, const Record* __restrict__ rec,
+                                                    int64_t n_gauss, const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ sorted_gid,
+                                                    const float* __restrict__ tlo_suffix,
+                                                    unsigned long long* __restrict__ counters) {
+  __shared__ Record srec[kFwdBatch];
+  __shared__ float slo[kFwdBatch + 1];
+  __shared__ unsigned int scount[4];
+  uint32_t c_eval = 0, c_full = 0, c_contrib = 0, c_over = 0;
+  const int b = blockIdx.x;
+  const int t = (b & 7) * per_xcd + (b >> 3);
+  if (t >= total_tiles) return;
+  const int v = view_of_tile(cams, n_views, t);
+  const DevCamera& c = cams[v];
+  const int lt = t - c.tile_offset;
+  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int j = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = i < c.crop_w && j < c.crop_h;
+  PixelRay r;
+  r.valid = false;
+  if (inside) r = pixel_ray(c, i, j, o.fs);
+  const PairPixel px = make_pair_pixel(r);
+  const Origin org = make_origin(c);
+  const WaveCone wc = wave_cone(r);
+
+  float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !r.valid;
+  const Record* vrec = rec + (int64_t)v * n_gauss;
+  // pending pairs: t* (INFINITY = empty slot), alpha, Gaussian index; bmin = smallest t*
+  float bt[kRayBuf], ba[kRayBuf];
+  uint32_t bgid[kRayBuf];
+#pragma unroll
+  for (int q = 0; q < kRayBuf; ++q) {
+    bt[q] = INFINITY;
+    ba[q] = 0.f;
+    bgid[q] = 0u;
+  }
+  float bmin = INFINITY;
+  // composites the pending pair with the smallest t*; called only with bmin < INFINITY,
+  // so every call removes one entry and each flush loop ends
+  auto pop_min = [&]() {
+    float a = 0.f;
+    uint32_t gi = 0u;
+    bool taken = false;
+#pragma unroll
+    for (int q = 0; q < kRayBuf; ++q)
+      if (!taken && bt[q] == bmin) {
+        a = ba[q];
+        gi = bgid[q];
+        bt[q] = INFINITY;
+        taken = true;
+      }
+    bmin = bt[0];
+#pragma unroll
+    for (int q = 1; q < kRayBuf; ++q) bmin = fminf(bmin, bt[q]);
+    const float test = Ttr * (1.f - a);
+    if (test < o.T_min) {
+      done = true;
+      return;
+    }
+    if (COUNT) ++c_contrib;
+    const float* rgb = vrec[gi].rgb;
+    const float w = Ttr * a;
+    C0 = fmaf(w, rgb[0], C0);
+    C1 = fmaf(w, rgb[1], C1);
+    C2 = fmaf(w, rgb[2], C2);
+    Ttr = test;
+  };
+
+  const uint2 rg = ranges[t];
+  for (uint32_t base = rg.x; base < rg.y; base += kFwdBatch) {
+    if (__syncthreads_count(!done) == 0) break;
+    const uint32_t idx = base + threadIdx.x;
+    const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - base);
+    if ((int)threadIdx.x < kFwdBatch && idx < rg.y) srec[threadIdx.x] = vrec[sorted_gid[idx]];
+    if ((int)threadIdx.x <= cnt) slo[threadIdx.x] = idx < rg.y ? tlo_suffix[idx] : INFINITY;
+    __syncthreads();
+    if (wc.live && __ballot(!done) != 0) {
+      for (int sub = 0; sub < cnt; sub += 64) {
+        bool rel = false;
+        if (sub + lane < cnt) rel = record_reaches_cone(srec[sub + lane], wc.ax, wc.ay, wc.az, wc.rad);
+        uint64_t m = __ballot(rel);
+        while (m) {
+          const int k = sub + (int)__builtin_ctzll(m);
+          m &= m - 1;
+          if (!done) {
+            if (COUNT) ++c_eval;
+            const Record& R = srec[k];
+            PairGeom g;
+            if (pair_cheap<FILTER>(R, px, org, o, g)) {
+              if (COUNT) ++c_full;
+              const float alpha = fminf(pair_full<FILTER, MARGINAL>(R, px, g), o.alpha_max);
+              if (alpha >= o.alpha_min) {
+                bool full = true;
+#pragma unroll
+                for (int q = 0; q < kRayBuf; ++q) full = full && bt[q] < INFINITY;
+                if (full) {  // composite the smallest t* early: the order may be inexact here
+                  ++c_over;
+                  pop_min();
+                }
+                bool placed = done;
+#pragma unroll
+                for (int q = 0; q < kRayBuf; ++q)
+                  if (!placed && !(bt[q] < INFINITY)) {
+                    bt[q] = g.tstar;
+                    ba[q] = alpha;
+                    bgid[q] = sorted_gid[base + k];
+                    placed = true;
+                  }
+                if (!done) bmin = fminf(bmin, g.tstar);
+              }
+            }
+            // no record after k can precede a pending t* at or below this bound
+            const float bound = slo[k + 1];
+            while (!done && bmin < INFINITY && bmin <= bound) pop_min();
+          }
+          if (__ballot(!done) == 0) break;
+        }
+        if (__ballot(!done) == 0) break;
+      }
+    }
+    while (!done && bmin < INFINITY && bmin <= slo[cnt]) pop_min();
+    __syncthreads();
+  }
+  while (!done && bmin < INFINITY) pop_min();
+  if (inside) {
+    float4 out;
+    out.x = C0 + Ttr * o.bg[0];
+    out.y = C1 + Ttr * o.bg[1];
+    out.z = C2 + Ttr * o.bg[2];
+    out.w = 1.f - Ttr;
+    reinterpret_cast<float4*>(c.out)[(int64_t)j * c.crop_w + i] = out;
+  }
+  if (threadIdx.x < 4) scount[threadIdx.x] = 0;
+  __syncthreads();
+  if (COUNT) {
+    atomicAdd(&scount[0], c_eval);
+    atomicAdd(&scount[1], c_full);
+    atomicAdd(&scount[2], c_contrib);
+  }
+  if (c_over) atomicAdd(&scount[3], c_over);
+  __syncthreads();
+  if (threadIdx.x < 4 && scount[threadIdx.x]) atomicAdd(&counters[threadIdx.x], (unsigned long long)scount[threadIdx.x]);
+}
+
 template <int FILTER, bool MARGINAL>
 static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                           int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* out_rgba,
-                           float* final_T, uint32_t* n_last, unsigned long long* counters, hipStream_t s) {
+                           int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float* tlo_suffix,
+                           float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
+                           hipStream_t s) {
   const int per_xcd = (total_tiles + 7) / 8;
-  if (counters)
-    k_render<FILTER, MARGINAL, true><<<dim3(per_xcd * 8), dim3(256), 0, s>>>(
-        cams, n_views, total_tiles, per_xcd, o, rec, n_gauss, ranges, sorted_gid, out_rgba, final_T, n_last,
-        counters);
-  else
-    k_render<FILTER, MARGINAL, false><<<dim3(per_xcd * 8), dim3(256), 0, s>>>(
-        cams, n_views, total_tiles, per_xcd, o, rec, n_gauss, ranges, sorted_gid, out_rgba, final_T, n_last,
-        nullptr);
+  const dim3 grid(per_xcd * 8), block(256);
+  if (o.order_mode == CG_ORDER_RAY) {
+    if (o.count_pairs)
+      k_render_ray<FILTER, MARGINAL, true><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
+                                                                   n_gauss, ranges, sorted_gid, tlo_suffix, counters);
+    else
+      k_render_ray<FILTER, MARGINAL, false><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
+                                                                    n_gauss, ranges, sorted_gid, tlo_suffix, counters);
+  } else if (o.count_pairs) {
+    k_render<FILTER, MARGINAL, true><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
+                                                             ranges, sorted_gid, out_rgba, final_T, n_last, counters);
+  } else {
+    k_render<FILTER, MARGINAL, false><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
+                                                              ranges, sorted_gid, out_rgba, final_T, n_last, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_tiles, const Record* rec,
+                               int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* tlo_suffix,
+                               hipStream_t s) {
+  if (total_tiles == 0) return hipSuccess;
+  k_order_bounds<<<dim3(total_tiles), dim3(256), 0, s>>>(cams, n_views, rec, n_gauss, ranges, sorted_gid, tlo_suffix);
   return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* out_rgba,
-                             float* final_T, uint32_t* n_last, unsigned long long* counters, hipStream_t s) {
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid,
+                             const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
+                             unsigned long long* counters, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
   switch (o.filter_mode) {
     case CG_FILTER_CENTER_RAY:
-      return launch_t<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, out_rgba, final_T,
-                                n_last, counters, s);
+      return launch_t<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix, out_rgba,
+                                final_T, n_last, counters, s);
     case CG_FILTER_ISOTROPIC:
-      return marginal ? launch_t<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, out_rgba,
-                                          final_T, n_last, counters, s)
-                      : launch_t<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, out_rgba,
-                                           final_T, n_last, counters, s);
+      return marginal ? launch_t<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+                                          out_rgba, final_T, n_last, counters, s)
+                      : launch_t<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+                                           tlo_suffix, out_rgba, final_T, n_last, counters, s);
     default:
-      return marginal ? launch_t<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, out_rgba,
-                                          final_T, n_last, counters, s)
-                      : launch_t<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, out_rgba,
-                                           final_T, n_last, counters, s);
+      return marginal ? launch_t<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+                                          out_rgba, final_T, n_last, counters, s)
+                      : launch_t<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+                                           tlo_suffix, out_rgba, final_T, n_last, counters, s);
   }
 }
 

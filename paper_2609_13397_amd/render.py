@@ -17,6 +17,7 @@ from . import _lib
 
 FILTER_CENTER_RAY, FILTER_ANISOTROPIC, FILTER_ISOTROPIC = 0, 1, 2
 COMPOSE_MARGINAL, COMPOSE_ADDITIVE = 0, 1
+ORDER_KEY, ORDER_RAY = 0, 1
 
 PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "color")
 
@@ -33,6 +34,7 @@ class RenderOpts:
     bg: tuple = (0.0, 0.0, 0.0)
     footprint_scale: float = 1.0
     count_pairs: bool = False
+    order_mode: int = ORDER_KEY
 
     def to_c(self) -> _lib.CgOpts:
         o = _lib.CgOpts()
@@ -46,6 +48,7 @@ class RenderOpts:
         o.bg[:] = list(self.bg)
         o.footprint_scale = self.footprint_scale
         o.count_pairs = 1 if self.count_pairs else 0
+        o.order_mode = int(self.order_mode)
         return o
 
 
@@ -174,7 +177,7 @@ def render_forward(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None, 
     fs = ForwardState(state, (scene, out)) if need_state else None
     info = {"n_pairs": stats.n_pairs, "n_tiles": stats.n_tiles, "n_pixels": stats.n_pixels,
             "sort_bits": stats.sort_bits, "n_evaluated": stats.n_evaluated, "n_full": stats.n_full,
-            "n_contrib": stats.n_contrib}
+            "n_contrib": stats.n_contrib, "n_order_overflow": stats.n_order_overflow}
     return out, info, fs
 
 

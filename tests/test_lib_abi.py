@@ -45,6 +45,7 @@ def test_default_opts_and_errors_without_gpu():
     L.cg_default_opts(_lib.byref(o))
     assert o.filter_mode == 1 and abs(o.alpha_min - 1 / 255) < 1e-9 and abs(o.alpha_max - 0.99) < 1e-7
     assert abs(o.T_min - 1e-4) < 1e-9 and abs(o.t_near - 0.2) < 1e-7 and o.footprint_scale == 1.0
+    assert o.count_pairs == 0 and o.order_mode == 0
     # an invalid camera is rejected with CG_ERR_INVALID_ARG and a message
     cam = _lib.CgCamera()
     cam.model = 7
@@ -75,3 +76,28 @@ def test_default_opts_and_errors_without_gpu():
     o.alpha_min = 0.0
     st = L.cg_render_forward(_lib.byref(g), _lib.byref(cam), 1, _lib.byref(o), None, None, None, None, None)
     assert st == -1 and b"alpha_min" in L.cg_last_error()
+
+
+def test_order_mode_validation_without_gpu():
+    """order_mode is 0 or 1, and the per-ray order (1) is forward-only: asking it for a
+    backward state is refused before any device work."""
+    import ctypes as C
+
+    from paper_2609_13397_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    L = _lib.lib()
+    o = _lib.CgOpts()
+    L.cg_default_opts(_lib.byref(o))
+    g = _lib.CgGaussians()
+    g.n = 0
+    g.color_mode = 0
+    cam = _lib.CgCamera()
+    o.order_mode = 2
+    st = L.cg_render_forward(_lib.byref(g), _lib.byref(cam), 1, _lib.byref(o), None, None, None, None, None)
+    assert st == -1 and b"order_mode" in L.cg_last_error()
+    o.order_mode = 1
+    state = C.c_void_p(0)
+    st = L.cg_render_forward(_lib.byref(g), _lib.byref(cam), 1, _lib.byref(o), None, None, _lib.byref(state),
+                             None, None)
+    assert st == -2 and b"forward-only" in L.cg_last_error()
