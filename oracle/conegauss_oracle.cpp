@@ -66,6 +66,7 @@ struct orc_opts {
   float bg[3];
   float footprint_scale; // multiplies the neighbour-ray differentials
   int32_t order_mode;    // 0 per-Gaussian key |mu - o|; 1 per-ray max-response depth t*
+  int32_t backbone;      // 0 max response (w = delta(t - t*), C = 1); 1 ray integral (w = 1)
 };
 
 }  // extern "C"
@@ -419,6 +420,22 @@ struct PairResult {
 // matrix and zero its negative eigenvalues.  filter_mode 0 drops the footprint
 // (Eq. 3 with C = 1); filter_mode 2 replaces the footprint by the isotropic
 // in-plane covariance with the same trace.
+// Longitudinal factor C[w] of the weighted ray response for w = 1 (the ray integral
+// of Sec. 3): with G normalised as exp(-q^2/2) / (Z_G sqrt(det Sigma)), the integral of
+// exp(-|o_u + t d_u|^2 / 2) over t is sqrt(2 pi) / |d_u| exp(-D^2 / 2), so
+// C = sqrt(2 pi) / (Z_G sqrt(det Sigma) |d_u|).  Z_G is not given by the paper; the
+// reading taken here is Z_G = sqrt(2 pi) det(Sigma)^(-1/3), the value for which an
+// isotropic Gaussian's integral response equals its max response (C = 1).  Sigma is
+// the effective covariance R S'^2 R^T.  nn = |d_u|^2.
+double geer_factor(const GaussPre& G, double nn) {
+  double WiT[3][3], Sig[3][3];
+  transpose(G.Winv, WiT);
+  matmul(G.Winv, WiT, Sig);
+  const double detS = det3(Sig);
+  const double ZG = std::sqrt(2.0 * kPi) * std::pow(detS, -1.0 / 3.0);
+  return std::sqrt(2.0 * kPi) / (ZG * std::sqrt(detS) * std::sqrt(nn));
+}
+
 PairResult pair_response(const GaussPre& G, const double o[3], const double d[3], const double dx[3],
                          const double dy[3], const orc_opts& op) {
   PairResult res{0.0, 0.0, 0.0, 0.0};
@@ -486,6 +503,7 @@ PairResult pair_response(const GaussPre& G, const double o[3], const double d[3]
     matvec(Ai, q, Aq);
     T = G.sigma / std::sqrt(det3(A)) * std::exp(-0.5 * dot3(q, Aq));
   }
+  if (op.backbone == 1) T *= geer_factor(G, nn);
   res.T_raw = T;
   res.T = (ts <= (double)op.t_near) ? 0.0 : T;
   return res;
@@ -669,11 +687,13 @@ Cone influence_cone(const GaussPre& G, const double o[3], double cmax, const orc
   const double dist = std::sqrt(dot3(v, v));
   for (int k = 0; k < 3; ++k) cn.axis[k] = dist > 0 ? v[k] / dist : 0.0;
   cn.half = kPi;
-  if (G.sigma <= op.alpha_min) { cn.half = -1.0; return cn; }  // never reaches alpha_min
-  if (dist <= 0) { cn.all = true; return cn; }
-  const double L = 2.0 * std::log(G.sigma / op.alpha_min);
   const double smax = std::max(G.sp[0], std::max(G.sp[1], G.sp[2]));
   const double smin = std::min(G.sp[0], std::min(G.sp[1], G.sp[2]));
+  // the ray-integral factor is at most s'_max / (geometric mean of s') (|d_u| >= 1/s'_max)
+  const double sig_b = G.sigma * (op.backbone == 1 ? smax / std::cbrt(G.sp[0] * G.sp[1] * G.sp[2]) : 1.0);
+  if (sig_b <= op.alpha_min) { cn.half = -1.0; return cn; }  // never reaches alpha_min
+  if (dist <= 0) { cn.all = true; return cn; }
+  const double L = 2.0 * std::log(sig_b / op.alpha_min);
   const double r = smax / smin;
   const double c = (op.filter_mode == 0) ? 0.0 : cmax;
   // Isotropic mode spreads the in-plane trace over both whitened directions, so its

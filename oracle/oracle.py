@@ -43,6 +43,7 @@ class _Opts(C.Structure):
         ("filter_mode", C.c_int32), ("use_floor", C.c_int32), ("composition", C.c_int32),
         ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("T_min", C.c_float), ("t_near", C.c_float),
         ("bg", C.c_float * 3), ("footprint_scale", C.c_float), ("order_mode", C.c_int32),
+        ("backbone", C.c_int32),
     ]
 
 
@@ -50,11 +51,12 @@ class Opts:
     """Render options (same meaning as the library's): filter_mode 0 centre ray,
     1 anisotropic footprint, 2 isotropic; use_floor applies Eq. 10 with rho^2;
     composition 0 marginal (Eq. 12), 1 additive; order_mode 0 composites by the
-    per-Gaussian key |mu - o|, 1 by each ray's own max-response depth t*."""
+    per-Gaussian key |mu - o|, 1 by each ray's own max-response depth t*; backbone 0 is
+    the max response (C = 1), 1 the ray integral (w = 1, with the Z_G reading)."""
 
     def __init__(self, filter_mode=1, use_floor=0, composition=0, alpha_min=1.0 / 255.0,
                  alpha_max=0.99, T_min=1e-4, t_near=0.2, bg=(0.0, 0.0, 0.0), footprint_scale=1.0,
-                 order_mode=0):
+                 order_mode=0, backbone=0):
         self.filter_mode = filter_mode
         self.use_floor = use_floor
         self.composition = composition
@@ -65,6 +67,7 @@ class Opts:
         self.bg = tuple(bg)
         self.footprint_scale = footprint_scale
         self.order_mode = order_mode
+        self.backbone = backbone
 
     @staticmethod
     def smooth(**kw):
@@ -86,6 +89,7 @@ class Opts:
         o.bg[:] = list(self.bg)
         o.footprint_scale = self.footprint_scale
         o.order_mode = self.order_mode
+        o.backbone = self.backbone
         return o
 
 

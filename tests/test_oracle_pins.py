@@ -621,7 +621,7 @@ def test_culled_mode_equals_brute_force():
         rho = O.bake_rho2(scene, [cam])
         sc = dict(scene)
         sc["rho2"] = rho.astype(np.float32)
-        for opts in (O.Opts(), O.Opts(use_floor=1), O.Opts(filter_mode=2)):
+        for opts in (O.Opts(), O.Opts(use_floor=1), O.Opts(filter_mode=2), O.Opts(use_floor=1, backbone=1)):
             a = O.render(sc, cam, opts, mode="brute")
             b = O.render(sc, cam, opts, mode="culled")
             np.testing.assert_array_equal(a["rgba"], b["rgba"])
@@ -668,3 +668,57 @@ def test_oracle_gradient_matches_finite_differences():
         fd = (loss(sp) - loss(sm)) / (np.float64(xp) - np.float64(xm))
         an = g[name][idx]
         assert an == pytest.approx(fd, rel=2e-4, abs=1e-6), (name, idx, an, fd)
+
+
+# ----------------------------------------------------------------------------- ray-integral backbone
+
+def test_ray_integral_backbone_equals_quadrature():
+    """backbone 1 (w = 1 in the weighted ray response of Sec. 3): the oracle's T equals
+    sigma times the numerical integral along the ray of the normalised Gaussian
+    exp(-(x - mu)^T Sigma^-1 (x - mu) / 2) / (Z_G sqrt(det Sigma)), with the Z_G reading
+    sqrt(2 pi) det(Sigma)^(-1/3), for anisotropic Gaussians and oblique rays."""
+    from scipy.integrate import quad
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        mu = rng.normal(0, 0.3, 3)
+        log_s = rng.normal(-1.5, 0.6, 3)
+        quat = rng.normal(0, 1, 4)
+        logit = float(rng.normal())
+        scene = one_gaussian_scene(mu, log_s, quat=quat, logit=logit)
+        o = np.array([0.2, -0.1, -4.0])
+        d = (mu + rng.normal(0, 0.4, 3)) - o
+        d /= np.linalg.norm(d)
+        rays = np.concatenate([d, d, d])[None]
+        T = O.pair_batch(scene, 0, o, rays, O.Opts(filter_mode=0, backbone=1))[0, 1]
+        s = np.exp(np.float32(log_s).astype(np.float64))
+        R = quat_to_R(np.float32(quat).astype(np.float64))
+        Sig = R @ np.diag(s * s) @ R.T
+        Si = np.linalg.inv(Sig)
+        detS = np.linalg.det(Sig)
+        ZG = math.sqrt(2 * math.pi) * detS ** (-1.0 / 3.0)
+        m = np.float32(mu).astype(np.float64)
+
+        def g(t):
+            x = o + t * d - m
+            return math.exp(-0.5 * x @ Si @ x) / (ZG * math.sqrt(detS))
+
+        tc = float((m - o) @ d)
+        span = 12.0 * float(np.max(s))
+        val, err = quad(g, tc - span, tc + span, epsabs=0, epsrel=1e-12, limit=200)
+        expect = sigmoid(float(np.float32(logit))) * val
+        assert T == pytest.approx(expect, rel=1e-8), trial
+
+
+def test_ray_integral_backbone_is_max_response_for_isotropic():
+    """With the Z_G reading the ray integral of an isotropic Gaussian equals its max
+    response (C = 1), for any ray."""
+    scene = one_gaussian_scene((0.1, 0.0, 0.2), (-2.0, -2.0, -2.0), quat=(0.3, 0.1, -0.7, 0.2), logit=0.3)
+    rng = np.random.default_rng(4)
+    o = np.array([0.0, 0.0, -3.0])
+    for _ in range(5):
+        d = np.array([0.1, 0.0, 0.2]) + rng.normal(0, 0.1, 3) - o
+        d /= np.linalg.norm(d)
+        rays = np.concatenate([d, d, d])[None]
+        a = O.pair_batch(scene, 0, o, rays, O.Opts(filter_mode=0, backbone=0))[0, 1]
+        b = O.pair_batch(scene, 0, o, rays, O.Opts(filter_mode=0, backbone=1))[0, 1]
+        assert b == pytest.approx(a, rel=1e-12)
