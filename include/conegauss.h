@@ -96,6 +96,7 @@ typedef struct {
 enum { CG_FILTER_CENTER_RAY = 0, CG_FILTER_ANISOTROPIC = 1, CG_FILTER_ISOTROPIC = 2 };
 enum { CG_COMPOSE_MARGINAL = 0, CG_COMPOSE_ADDITIVE = 1 };
 enum { CG_ORDER_KEY = 0, CG_ORDER_RAY = 1 };
+enum { CG_BACKBONE_MAX_RESPONSE = 0, CG_BACKBONE_RAY_INTEGRAL = 1 };
 
 /* Render options.  cg_default_opts fills the defaults given in brackets.
  *   filter_mode     CG_FILTER_* [ANISOTROPIC]: centre ray = Eq. 3 with C = 1;
@@ -121,7 +122,14 @@ enum { CG_ORDER_KEY = 0, CG_ORDER_RAY = 1 };
  *                   smaller t* (every record bounds its t* from below); a full buffer
  *                   composites its smallest t* early, counted in
  *                   cg_fwd_stats.n_order_overflow.  RAY is forward-only: state_out must
- *                   be NULL (CG_ERR_UNSUPPORTED otherwise). */
+ *                   be NULL (CG_ERR_UNSUPPORTED otherwise).
+ *   backbone        CG_BACKBONE_* [MAX_RESPONSE]: the longitudinal factor C[w] of the
+ *                   weighted ray response (Sec. 3) that multiplies Eq. 9.  MAX_RESPONSE:
+ *                   w = delta(t - t*), C = 1.  RAY_INTEGRAL: w = 1, C = sqrt(2 pi) /
+ *                   (Z_G sqrt(det Sigma_eff) |W d|); the paper leaves Z_G open, and the
+ *                   value taken is sqrt(2 pi) det(Sigma_eff)^(-1/3), for which an
+ *                   isotropic Gaussian gets C = 1; then C = 1 / (g |W d|) with g the
+ *                   geometric mean of s'. */
 typedef struct {
   int32_t filter_mode;
   int32_t use_floor;
@@ -131,6 +139,7 @@ typedef struct {
   float footprint_scale;
   int32_t count_pairs;
   int32_t order_mode;
+  int32_t backbone;
 } cg_render_opts;
 
 /* Scratch allocator.  alloc returns device memory usable in stream order on `stream`

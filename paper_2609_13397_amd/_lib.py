@@ -44,7 +44,7 @@ class CgOpts(C.Structure):
         ("filter_mode", C.c_int32), ("use_floor", C.c_int32), ("composition", C.c_int32),
         ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("T_min", C.c_float), ("t_near", C.c_float),
         ("bg", C.c_float * 3), ("footprint_scale", C.c_float), ("count_pairs", C.c_int32),
-        ("order_mode", C.c_int32),
+        ("order_mode", C.c_int32), ("backbone", C.c_int32),
     ]
 
 

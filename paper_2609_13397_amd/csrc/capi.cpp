@@ -123,6 +123,8 @@ Opts make_opts(const cg_render_opts& o) {
   CG_CHECK_ARG(std::isfinite(o.t_near) && o.t_near >= 0.f, "t_near must be >= 0");
   CG_CHECK_ARG(std::isfinite(o.footprint_scale) && o.footprint_scale >= 0.f, "footprint_scale must be >= 0");
   CG_CHECK_ARG(o.order_mode == CG_ORDER_KEY || o.order_mode == CG_ORDER_RAY, "order_mode must be 0 or 1");
+  CG_CHECK_ARG(o.backbone == CG_BACKBONE_MAX_RESPONSE || o.backbone == CG_BACKBONE_RAY_INTEGRAL,
+               "backbone must be 0 or 1");
   Opts r;
   r.filter_mode = o.filter_mode;
   r.use_floor = o.use_floor ? 1 : 0;
@@ -135,6 +137,7 @@ Opts make_opts(const cg_render_opts& o) {
   r.fs = o.footprint_scale;
   r.order_mode = o.order_mode;
   r.count_pairs = o.count_pairs ? 1 : 0;
+  r.backbone = o.backbone;
   return r;
 }
 
@@ -390,6 +393,7 @@ void cg_default_opts(cg_render_opts* o) {
   o->footprint_scale = 1.f;
   o->count_pairs = 0;
   o->order_mode = CG_ORDER_KEY;
+  o->backbone = CG_BACKBONE_MAX_RESPONSE;
 }
 
 cg_status cg_render_forward(const cg_gaussians* g, const cg_camera* cams, int32_t n_views,

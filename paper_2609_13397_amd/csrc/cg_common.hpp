@@ -71,6 +71,7 @@ struct Opts {
   float fs;  // footprint scale
   int order_mode;
   int count_pairs;
+  int backbone;  // 1: ray-integral factor 1 / (g |W d|) (the record's sigma carries 1 / g)
 };
 
 struct GaussPtrs {

@@ -192,24 +192,26 @@ __device__ __forceinline__ bool pair_cheap(const Record& R, const PairPixel& p, 
 // C = 1); 1: anisotropic (Eq. 9); 2: isotropic in-plane covariance of the same trace.
 // MARGINAL: floor composition by Eq. 12 (records with rho2 = 0 take the plain path).
 // The footprint and floor state are left in f and fl for the backward.
-template <int FILTER, bool MARGINAL>
+template <int FILTER, bool MARGINAL, bool GEER>
 __device__ __forceinline__ float pair_full_keep(const Record& R, const PairPixel& p, const PairGeom& g, PairFoot& f,
                                                 PairFloor& fl, bool& filt) {
+  // GEER: ray-integral backbone, C = 1 / (g_mean |W d|); R.sigma carries 1 / g_mean
+  const float C = GEER ? sqrtf(g.rn) : 1.f;
   filt = true;
-  if (FILTER == 0) return R.sigma * __expf(-0.5f * g.D2);
+  if (FILTER == 0) return C * R.sigma * __expf(-0.5f * g.D2);
   pair_foot(R, p, g, f);
   fl.G11 = 1.f;
   fl.G12 = 0.f;
   fl.G22 = 1.f;
   fl.P11 = fl.P12 = fl.P22 = fl.dd = fl.rr = fl.lp = fl.lm = fl.gp = 0.f;
   if (MARGINAL && R.rho2 > 0.f) filt = floor_G(R, f, fl);
-  if (!filt) return R.sigma * __expf(-0.5f * g.D2);
+  if (!filt) return C * R.sigma * __expf(-0.5f * g.D2);
   const float G11 = fl.G11, G12 = fl.G12, G22 = fl.G22;
   if (FILTER == 2) {
     const float tau = (MARGINAL && R.rho2 > 0.f) ? (G11 * f.K11 + 2.f * G12 * f.K12 + G22 * f.K22) : (f.K11 + f.K22);
     const float s = 1.f + 0.5f * tau;
     const float is = fast_rcp(s);
-    return R.sigma * is * __expf(-0.5f * g.D2 * is);
+    return C * R.sigma * is * __expf(-0.5f * g.D2 * is);
   }
   float det, quad;
   if (MARGINAL && R.rho2 > 0.f) {
@@ -225,24 +227,24 @@ __device__ __forceinline__ float pair_full_keep(const Record& R, const PairPixel
     det = P11 * P22 - P12 * P12;
     quad = (P22 * f.h1 * f.h1 - 2.f * P12 * f.h1 * f.h2 + P11 * f.h2 * f.h2) * fast_rcp(det);
   }
-  return R.sigma * rsqrtf(det) * __expf(-0.5f * (g.D2 - quad));
+  return C * R.sigma * rsqrtf(det) * __expf(-0.5f * (g.D2 - quad));
 }
 
-template <int FILTER, bool MARGINAL>
+template <int FILTER, bool MARGINAL, bool GEER>
 __device__ __forceinline__ float pair_full(const Record& R, const PairPixel& p, const PairGeom& g) {
   PairFoot f;
   PairFloor fl;
   bool filt;
-  return pair_full_keep<FILTER, MARGINAL>(R, p, g, f, fl, filt);
+  return pair_full_keep<FILTER, MARGINAL, GEER>(R, p, g, f, fl, filt);
 }
 
 // Both parts; false when the pair cannot reach alpha_min (T is then not set).
-template <int FILTER, bool MARGINAL>
+template <int FILTER, bool MARGINAL, bool GEER>
 __device__ __forceinline__ bool pair_response(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
                                               float& T) {
   PairGeom g;
   if (!pair_cheap<FILTER>(R, p, O, o, g)) return false;
-  T = pair_full<FILTER, MARGINAL>(R, p, g);
+  T = pair_full<FILTER, MARGINAL, GEER>(R, p, g);
   return true;
 }
 
@@ -258,7 +260,7 @@ namespace cg {
 // composition) is differentiated in closed form: with both eigenvalues above rho^2,
 // G = I - rho^2 Phi^{-1}; with one, G = g+ u u^T (u the leading eigenvector); at the
 // clamp kink the clamped branch's (zero) derivative is used.
-template <int FILTER, bool MARGINAL>
+template <int FILTER, bool MARGINAL, bool GEER>
 __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, const PairGeom& gm, const PairFoot& ft,
                                           const PairFloor& fl, bool filt, float dT, float T,
                                           float* __restrict__ g) {
@@ -279,6 +281,8 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
 #pragma unroll
   for (int k = 0; k < 9; ++k) dW[k] = 0.f;
   float dsp0 = 0.f, dsp1 = 0.f, dsp2 = 0.f;
+  // ray-integral backbone: T carries sqrt(rn) = 1 / |a|
+  if (GEER) drn += 0.5f * dlogT / gm.rn;
 
   if (FILTER == 0) {
     dD2 = -0.5f * dlogT;

@@ -64,7 +64,16 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
     for (int b = 0; b < 3; ++b) r.W[3 * a + b] = R[3 * b + a] * inv;
   }
   r.mu[0] = mu[0]; r.mu[1] = mu[1]; r.mu[2] = mu[2];
+  // ray-integral backbone: C = 1 / (g |W d|) with g the geometric mean of s'; the record
+  // carries sigma_eff / g and the render multiplies by 1 / |W d|.  C <= s'_max / g, which
+  // bounds the response for the culling below.
+  float sig_bound = sig_eff;
   r.sigma = sig_eff;
+  if (o.backbone == CG_BACKBONE_RAY_INTEGRAL) {
+    const double g = pow((double)sp2[0] * (double)sp2[1] * (double)sp2[2], 1.0 / 6.0);
+    r.sigma = (float)((double)sig_eff / g);
+    sig_bound = (float)((double)sig_eff * sqrt((double)fmaxf(sp2[0], fmaxf(sp2[1], sp2[2]))) / g * 1.0001);
+  }
   r.sp2[0] = sp2[0]; r.sp2[1] = sp2[1]; r.sp2[2] = sp2[2];
   r.rho2 = rho2;
   const float sp2min = fminf(sp2[0], fminf(sp2[1], sp2[2]));
@@ -89,8 +98,8 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
 
   depth_key[out] = __float_as_uint(depth_key_f32(mu[0], mu[1], mu[2], c.of[0], c.of[1], c.of[2]));
 
-  // Influence cone.  If T >= alpha_min then q^T A^{-1} q <= L = 2 ln(sigma_eff /
-  // alpha_min), and
+  // Influence cone.  If T >= alpha_min then q^T A^{-1} q <= L = 2 ln(sigma_b /
+  // alpha_min) (sigma_b = sigma_eff times the backbone's largest factor), and
   //  (i) the max-response point x* = o + t* d lies within rho of the mean: |x* - mu| =
   //      |W^{-1} q| <= s'_max |q| <= s'_max sqrt(L lambda_max(A)), with lambda_max(A) <=
   //      1 + t*^2 c / s'_min^2 (c: the pixel footprint coefficient) and t* <= |v| + rho,
@@ -102,8 +111,8 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
   //      most s'_max^2 + t*^2 c.
   // The half-angle is asin(min(p, rho) / |v|).  FP64 with relative margins.
   float gamma = -1.f;
-  if (dist > 0.0 && sig_eff > o.alpha_min) {
-    const double L = 2.0 * log((double)sig_eff / (double)o.alpha_min);
+  if (dist > 0.0 && sig_bound > o.alpha_min) {
+    const double L = 2.0 * log((double)sig_bound / (double)o.alpha_min);
     r.Lg = (float)L;
     const double smax = sqrt((double)fmaxf(sp2[0], fmaxf(sp2[1], sp2[2])));
     const double smin = sqrt((double)sp2min);

@@ -57,7 +57,7 @@ __device__ __forceinline__ WaveConeB wave_cone_b(const PixelRay& r) {
 
 // Four waves per SIMD: the register budget (128 VGPRs) that pair_grad fits in without
 // spilling.
-template <int FILTER, bool MARGINAL>
+template <int FILTER, bool MARGINAL, bool GEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                     int per_xcd, Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
           PairFloor fl;
           bool filt = true;
           if (pair_cheap<FILTER>(R, px, org, o, gm)) {
-            const float T = pair_full_keep<FILTER, MARGINAL>(R, px, gm, ft, fl, filt);
+            const float T = pair_full_keep<FILTER, MARGINAL, GEER>(R, px, gm, ft, fl, filt);
             const float alpha = fminf(T, o.alpha_max);
             if (alpha >= o.alpha_min) {
               const float test = Ttr * (1.f - alpha);
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 gv[16] = G0 * w;
                 gv[17] = G1 * w;
                 gv[18] = G2 * w;
-                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL>(R, px, gm, ft, fl, filt, dalpha, T, gv);
+                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL, GEER>(R, px, gm, ft, fl, filt, dalpha, T, gv);
                 Ttr = test;
               }
             }
@@ -321,6 +321,15 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
     }
   }
   // sigma_eff = sigma * prod s / s'
+  if (o.backbone == CG_BACKBONE_RAY_INTEGRAL) {
+    // the record carries sigma_eff / g with g = (prod s'^2)^(1/6) (as in the forward)
+    const double gm = pow((double)sp2[0] * (double)sp2[1] * (double)sp2[2], 1.0 / 6.0);
+    const float ig = (float)(1.0 / gm);
+    const float sig_rec = sigma * ratio * ig;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dsp2[k] += dsig_eff * sig_rec * (-1.f / (6.f * sp2[k]));
+    dsig_eff *= ig;
+  }
   const float dsig = dsig_eff * ratio;
   const float dratio = dsig_eff * sigma;
   for (int k = 0; k < 3; ++k) {
@@ -346,13 +355,22 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
   d_quats[3 * n + i] = (dz - dot * z) * qn;
 }
 
+template <int FILTER, bool MARGINAL, bool GEER>
+static void launch_bwd_g(const cg_fwd_state* st, const float* grad_rgba, float* partial, unsigned int* mismatch,
+                         hipStream_t s) {
+  const int per_xcd = (int)((st->total_tiles + 7) / 8);
+  k_render_bwd<FILTER, MARGINAL, GEER><<<dim3(per_xcd * 8), dim3(256), 0, s>>>(
+      st->dcams, st->n_views, (int)st->total_tiles, per_xcd, st->opts, st->rec, st->g.n, st->ranges, st->sorted_gid,
+      st->sorted_slots, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
+}
+
 template <int FILTER, bool MARGINAL>
 static void launch_bwd_t(const cg_fwd_state* st, const float* grad_rgba, float* partial, unsigned int* mismatch,
                          hipStream_t s) {
-  const int per_xcd = (int)((st->total_tiles + 7) / 8);
-  k_render_bwd<FILTER, MARGINAL><<<dim3(per_xcd * 8), dim3(256), 0, s>>>(
-      st->dcams, st->n_views, (int)st->total_tiles, per_xcd, st->opts, st->rec, st->g.n, st->ranges, st->sorted_gid,
-      st->sorted_slots, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
+  if (st->opts.backbone == CG_BACKBONE_RAY_INTEGRAL)
+    launch_bwd_g<FILTER, MARGINAL, true>(st, grad_rgba, partial, mismatch, s);
+  else
+    launch_bwd_g<FILTER, MARGINAL, false>(st, grad_rgba, partial, mismatch, s);
 }
 
 void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, float* d_log_scales, float* d_quats,

@@ -54,7 +54,7 @@ __device__ __forceinline__ WaveCone wave_cone(const PixelRay& r) {
 
 // COUNT: also count, per pixel, the pairs that reached the per-pixel tests, those that
 // needed the full footprint arithmetic and those composited, into counters[0..2].
-template <int FILTER, bool MARGINAL, bool COUNT>
+template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                 int per_xcd, Opts o, const Record* __restrict__ rec, int64_t n_gauss,
                                                 const uint2* __restrict__ ranges,
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
           if (!done) {
             float T;
             if (COUNT) ++c_eval;
-            if (pair_response<FILTER, MARGINAL>(srec[k], px, org, o, T)) {
+            if (pair_response<FILTER, MARGINAL, GEER>(srec[k], px, org, o, T)) {
               if (COUNT) ++c_full;
               const float alpha = fminf(T, o.alpha_max);
               if (alpha >= o.alpha_min) {
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_order_bounds(const DevCamera* __restric
   }
 }
 
-template <int FILTER, bool MARGINAL, bool COUNT>
+template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
 __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                     int per_xcd, Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
             PairGeom g;
             if (pair_cheap<FILTER>(R, px, org, o, g)) {
               if (COUNT) ++c_full;
-              const float alpha = fminf(pair_full<FILTER, MARGINAL>(R, px, g), o.alpha_max);
+              const float alpha = fminf(pair_full<FILTER, MARGINAL, GEER>(R, px, g), o.alpha_max);
               if (alpha >= o.alpha_min) {
                 bool full = true;
 #pragma unroll
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   if (threadIdx.x < 4 && scount[threadIdx.x]) atomicAdd(&counters[threadIdx.x], (unsigned long long)scount[threadIdx.x]);
 }
 
-template <int FILTER, bool MARGINAL>
+template <int FILTER, bool MARGINAL, bool GEER>
 static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
                            int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float* tlo_suffix,
                            float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
@@ -372,19 +372,31 @@ static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, 
   const dim3 grid(per_xcd * 8), block(256);
   if (o.order_mode == CG_ORDER_RAY) {
     if (o.count_pairs)
-      k_render_ray<FILTER, MARGINAL, true><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
+      k_render_ray<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
                                                                    n_gauss, ranges, sorted_gid, tlo_suffix, counters);
     else
-      k_render_ray<FILTER, MARGINAL, false><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
+      k_render_ray<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
                                                                     n_gauss, ranges, sorted_gid, tlo_suffix, counters);
   } else if (o.count_pairs) {
-    k_render<FILTER, MARGINAL, true><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
+    k_render<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
                                                              ranges, sorted_gid, out_rgba, final_T, n_last, counters);
   } else {
-    k_render<FILTER, MARGINAL, false><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
+    k_render<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
                                                               ranges, sorted_gid, out_rgba, final_T, n_last, nullptr);
   }
   return hipGetLastError();
+}
+
+template <int FILTER, bool MARGINAL>
+static hipError_t launch_fm(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
+                            int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float* tlo_suffix,
+                            float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
+                            hipStream_t s) {
+  if (o.backbone == CG_BACKBONE_RAY_INTEGRAL)
+    return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
+  return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+                                           out_rgba, final_T, n_last, counters, s);
 }
 
 hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_tiles, const Record* rec,
@@ -403,17 +415,17 @@ hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles
   const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
   switch (o.filter_mode) {
     case CG_FILTER_CENTER_RAY:
-      return launch_t<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix, out_rgba,
+      return launch_fm<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix, out_rgba,
                                 final_T, n_last, counters, s);
     case CG_FILTER_ISOTROPIC:
-      return marginal ? launch_t<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+      return marginal ? launch_fm<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
                                           out_rgba, final_T, n_last, counters, s)
-                      : launch_t<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+                      : launch_fm<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
     default:
-      return marginal ? launch_t<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+      return marginal ? launch_fm<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
                                           out_rgba, final_T, n_last, counters, s)
-                      : launch_t<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+                      : launch_fm<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
   }
 }

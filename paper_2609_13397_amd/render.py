@@ -18,6 +18,7 @@ from . import _lib
 FILTER_CENTER_RAY, FILTER_ANISOTROPIC, FILTER_ISOTROPIC = 0, 1, 2
 COMPOSE_MARGINAL, COMPOSE_ADDITIVE = 0, 1
 ORDER_KEY, ORDER_RAY = 0, 1
+BACKBONE_MAX_RESPONSE, BACKBONE_RAY_INTEGRAL = 0, 1
 
 PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "color")
 
@@ -35,6 +36,7 @@ class RenderOpts:
     footprint_scale: float = 1.0
     count_pairs: bool = False
     order_mode: int = ORDER_KEY
+    backbone: int = BACKBONE_MAX_RESPONSE
 
     def to_c(self) -> _lib.CgOpts:
         o = _lib.CgOpts()
@@ -49,6 +51,7 @@ class RenderOpts:
         o.footprint_scale = self.footprint_scale
         o.count_pairs = 1 if self.count_pairs else 0
         o.order_mode = int(self.order_mode)
+        o.backbone = int(self.backbone)
         return o
 
 

@@ -82,7 +82,8 @@ def upstream(cams, refs, seed=7):
     return out
 
 
-@pytest.mark.parametrize("case", ["floor_marginal", "no_floor", "centre_ray", "isotropic_floor", "rgb_additive"])
+@pytest.mark.parametrize("case", ["floor_marginal", "no_floor", "centre_ray", "isotropic_floor", "rgb_additive",
+                                  "ray_integral_floor"])
 def test_backward_matches_oracle_gradient(case):
     from paper_2609_13397_amd import render as R
     color = "rgb" if case == "rgb_additive" else "sh3"
@@ -92,7 +93,8 @@ def test_backward_matches_oracle_gradient(case):
           "no_floor": dict(),
           "centre_ray": dict(filter_mode=0, use_floor=True),
           "isotropic_floor": dict(filter_mode=2, use_floor=True),
-          "rgb_additive": dict(use_floor=True, composition=1)}[case]
+          "rgb_additive": dict(use_floor=True, composition=1),
+          "ray_integral_floor": dict(use_floor=True, backbone=1)}[case]
     if kw.get("use_floor"):
         scene["rho2"] = O.bake_rho2(scene, [synth.scale_camera(c, 2.0) for c in cams]).astype(np.float32)
     oopts = O.Opts(**{k: (int(v) if isinstance(v, bool) else v) for k, v in kw.items()})

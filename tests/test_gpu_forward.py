@@ -105,6 +105,8 @@ TINY_VARIANTS = [
     dict(filter_mode=2),
     dict(filter_mode=1, bg=(0.2, 0.4, 0.6)),
     dict(filter_mode=1, footprint_scale=3.0),
+    dict(filter_mode=1, backbone=1),
+    dict(filter_mode=0, backbone=1),
 ]
 
 
@@ -122,21 +124,22 @@ def test_tiny_forward_parity(kw):
         check_view(img, scene, c, oopts)
 
 
-@pytest.mark.parametrize("composition", [0, 1])
-def test_tiny_forward_floor_parity(composition):
+@pytest.mark.parametrize("composition,backbone", [(0, 0), (1, 0), (0, 1)])
+def test_tiny_forward_floor_parity(composition, backbone):
     """Floor on, with rho^2 baked (by the oracle, Eq. 11) from the same camera at x2
     resolution, so the floor partly covers the render footprint."""
     scene, cam = synth.tiny_config()
     scene = dict(scene)
     scene["rho2"] = O.bake_rho2(scene, [synth.scale_camera(cam, 2.0)]).astype(np.float32)
-    gopts, oopts = _opts_pair(use_floor=True, composition=composition)
+    gopts, oopts = _opts_pair(use_floor=True, composition=composition, backbone=backbone)
     oopts.use_floor = 1
-    _say(f"tiny floor composition={composition}")
+    _say(f"tiny floor composition={composition} backbone={backbone}")
     imgs, _ = gpu_render(scene, [cam], gopts)
     check_view(imgs[0], scene, cam, oopts)
 
 
-def test_fisheye_and_equirect_small_parity():
+@pytest.mark.parametrize("backbone", [0, 1])
+def test_fisheye_and_equirect_small_parity(backbone):
     """Wide cameras with sheared peripheral footprints: a 190-degree KB fisheye and an
     equirectangular view, 2000 Gaussians around the camera, floor on."""
     scene = synth.make_scene(2000, seed=22, layout="clusters", color="sh3", log_scale_mean=-3.0, log_scale_std=0.6)
@@ -148,9 +151,9 @@ def test_fisheye_and_equirect_small_parity():
     for c in cams:
         c["origin"] = (0.0, -1.0, 0.3)
     scene["rho2"] = O.bake_rho2(scene, [synth.scale_camera(c, 2.0) for c in cams]).astype(np.float32)
-    gopts, oopts = _opts_pair(use_floor=True)
+    gopts, oopts = _opts_pair(use_floor=True, backbone=backbone)
     oopts.use_floor = 1
-    _say("fisheye + equirect small")
+    _say(f"fisheye + equirect small, backbone {backbone}")
     imgs, info = gpu_render(scene, cams, gopts)
     _say(f"   pairs {info['n_pairs']}")
     for img, c in zip(imgs, cams):
