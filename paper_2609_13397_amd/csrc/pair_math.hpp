@@ -150,14 +150,18 @@ __device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, Pair
   fl.lm = m - fl.rr;
   const float rho2 = R.rho2;
   if (fl.lp <= rho2) return false;
-  fl.gp = 1.f - rho2 / fl.lp;
+  // hardware reciprocals (about 1 ulp) instead of IEEE divisions: this runs for every
+  // floored pair, and the forward and its backward replay share it
+  const float ilp = fast_rcp(fl.lp);
+  fl.gp = 1.f - rho2 * ilp;
   float gm, beta;
   if (fl.lm > rho2) {
-    gm = 1.f - rho2 / fl.lm;
-    beta = rho2 / (fl.lp * fl.lm);
+    const float ilm = fast_rcp(fl.lm);
+    gm = 1.f - rho2 * ilm;
+    beta = rho2 * ilp * ilm;
   } else {
-    gm = 0.f;
-    beta = fl.gp / (2.f * fl.rr);
+    gm = 0.f;  // lm <= rho2 < lp, so rr > 0
+    beta = fl.gp * fast_rcp(2.f * fl.rr);
   }
   const float gbar = 0.5f * (fl.gp + gm);
   fl.G11 = gbar + beta * fl.dd;
@@ -271,7 +275,8 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
   const float f = ya * gm.rn;
 
   // adjoints
-  float dsig = dT * T / R.sigma;
+  // reverse mode only: hardware reciprocals are accurate enough for the gradients
+  float dsig = dT * T * fast_rcp(R.sigma);
   const float dlogT = dT * T;
   float dD2 = 0.f;
   float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
@@ -282,7 +287,7 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
   for (int k = 0; k < 9; ++k) dW[k] = 0.f;
   float dsp0 = 0.f, dsp1 = 0.f, dsp2 = 0.f;
   // ray-integral backbone: T carries sqrt(rn) = 1 / |a|
-  if (GEER) drn += 0.5f * dlogT / gm.rn;
+  if (GEER) drn += 0.5f * dlogT * fast_rcp(gm.rn);
 
   if (FILTER == 0) {
     dD2 = -0.5f * dlogT;
@@ -300,8 +305,9 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
         detP = P11 * P22 - P12 * P12;
       } else {
         gcase = 2;
-        c2 = fl.dd / rr;
-        s2 = P12 / rr;
+        const float irr = fast_rcp(rr);
+        c2 = fl.dd * irr;
+        s2 = P12 * irr;
       }
     }
     float dK11 = 0.f, dK12 = 0.f, dK22 = 0.f, dh1 = 0.f, dh2 = 0.f;
@@ -311,7 +317,7 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
     } else if (FILTER == 2) {
       const float tau = floor_on ? (G11 * ft.K11 + 2.f * G12 * ft.K12 + G22 * ft.K22) : (ft.K11 + ft.K22);
       const float s = 1.f + 0.5f * tau;
-      const float is = 1.f / s;
+      const float is = fast_rcp(s);
       dD2 = -0.5f * is * dlogT;
       const float ds = dlogT * (-is + 0.5f * gm.D2 * is * is);
       const float dtau = 0.5f * ds;
@@ -329,7 +335,7 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
         const float M11 = 1.f + ft.K11 * G11 + ft.K12 * G12, M12 = ft.K11 * G12 + ft.K12 * G22;
         const float M21 = ft.K12 * G11 + ft.K22 * G12, M22 = 1.f + ft.K12 * G12 + ft.K22 * G22;
         const float det = M11 * M22 - M12 * M21;
-        const float idet = 1.f / det;
+        const float idet = fast_rcp(det);
         const float N11 = G11 * M22 - G12 * M21, N12 = G12 * M11 - G11 * M12;
         const float N21 = G12 * M22 - G22 * M21, N22 = G22 * M11 - G12 * M12;
         const float num = ft.h1 * (N11 * ft.h1 + N12 * ft.h2) + ft.h2 * (N21 * ft.h1 + N22 * ft.h2);
@@ -358,7 +364,7 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
       } else {
         const float Q11 = 1.f + ft.K11, Q22 = 1.f + ft.K22, Q12 = ft.K12;
         const float det = Q11 * Q22 - Q12 * Q12;
-        const float idet = 1.f / det;
+        const float idet = fast_rcp(det);
         const float num = Q22 * ft.h1 * ft.h1 - 2.f * Q12 * ft.h1 * ft.h2 + Q11 * ft.h2 * ft.h2;
         const float quad = num * idet;
         const float ddet = -0.5f * dlogT * idet - dquad * quad * idet;
@@ -374,7 +380,7 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
     float dP11 = 0.f, dP12 = 0.f, dP22 = 0.f;
     if (gcase == 1) {
       // G11 = 1 - rho2 P22/det, G22 = 1 - rho2 P11/det, G12 = rho2 P12/det
-      const float r2 = R.rho2, id = 1.f / detP;
+      const float r2 = R.rho2, id = fast_rcp(detP);
       const float Gp11 = -r2 * P22 * id, Gp22 = -r2 * P11 * id, Gp12 = r2 * P12 * id;  // G - I
       // d(1/det) = -(P22 dP11 + P11 dP22 - 2 P12 dP12) / det^2
       const float s = dG11 * Gp11 + dG22 * Gp22 + dG12 * Gp12;  // sum dG * (G - I)
@@ -384,11 +390,12 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
     } else if (gcase == 2) {
       const float dgp = 0.5f * (dG11 * (1.f + c2) + dG22 * (1.f - c2) + dG12 * s2);
       const float dc2 = 0.5f * gp * (dG11 - dG22), ds2 = 0.5f * gp * dG12;
-      const float dlp = dgp * R.rho2 / (lp * lp);
+      const float ilp = fast_rcp(lp), irr = fast_rcp(rr);
+      const float dlp = dgp * R.rho2 * ilp * ilp;
       float dm = dlp, drr = dlp;
-      float ddd = dc2 / rr;
-      drr += -dc2 * c2 / rr - ds2 * s2 / rr;
-      float dpq = ds2 / rr;
+      float ddd = dc2 * irr;
+      drr += (-dc2 * c2 - ds2 * s2) * irr;
+      float dpq = ds2 * irr;
       ddd += drr * c2;
       dpq += drr * s2;
       dP11 += 0.5f * (dm + ddd);

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 C0 = fmaf(w, R.rgb[0], C0);
                 C1 = fmaf(w, R.rgb[1], C1);
                 C2 = fmaf(w, R.rgb[2], C2);
-                const float inv1 = 1.f / (1.f - alpha);
+                const float inv1 = fast_rcp(1.f - alpha);
                 // colour behind this pair (excluding the background term)
                 const float S0 = Cf0 - C0, S1 = Cf1 - C1, S2 = Cf2 - C2;
                 float dalpha = Ga * Tfin * inv1;
