@@ -64,6 +64,12 @@ struct alignas(16) Record {
 };
 static_assert(sizeof(Record) == 128, "Record layout");
 
+// Hardware square root, reciprocal square root and reciprocal (about 1 ulp, no
+// correctly-rounded expansion): for per-pair arithmetic whose tolerance is far above
+// float32 rounding, and for conservative bounds that carry relative margins.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 struct Opts {
   int filter_mode, use_floor, composition;
   float alpha_min, alpha_max, T_min, t_near;

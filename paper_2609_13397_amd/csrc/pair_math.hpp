@@ -145,7 +145,7 @@ __device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, Pair
   fl.P22 = (R.sp2[0] * f.ey0 * f.ey0 + R.sp2[1] * f.ey1 * f.ey1 + R.sp2[2] * f.ey2 * f.ey2) * third;
   const float m = 0.5f * (fl.P11 + fl.P22);
   fl.dd = 0.5f * (fl.P11 - fl.P22);
-  fl.rr = sqrtf(fl.dd * fl.dd + fl.P12 * fl.P12);
+  fl.rr = fast_sqrt(fl.dd * fl.dd + fl.P12 * fl.P12);
   fl.lp = m + fl.rr;
   fl.lm = m - fl.rr;
   const float rho2 = R.rho2;
@@ -200,7 +200,7 @@ template <int FILTER, bool MARGINAL, bool GEER>
 __device__ __forceinline__ float pair_full_keep(const Record& R, const PairPixel& p, const PairGeom& g, PairFoot& f,
                                                 PairFloor& fl, bool& filt) {
   // GEER: ray-integral backbone, C = 1 / (g_mean |W d|); R.sigma carries 1 / g_mean
-  const float C = GEER ? sqrtf(g.rn) : 1.f;
+  const float C = GEER ? fast_sqrt(g.rn) : 1.f;
   filt = true;
   if (FILTER == 0) return C * R.sigma * __expf(-0.5f * g.D2);
   pair_foot(R, p, g, f);
@@ -231,7 +231,7 @@ __device__ __forceinline__ float pair_full_keep(const Record& R, const PairPixel
     det = P11 * P22 - P12 * P12;
     quad = (P22 * f.h1 * f.h1 - 2.f * P12 * f.h1 * f.h2 + P11 * f.h2 * f.h2) * fast_rcp(det);
   }
-  return C * R.sigma * rsqrtf(det) * __expf(-0.5f * (g.D2 - quad));
+  return C * R.sigma * fast_rsq(det) * __expf(-0.5f * (g.D2 - quad));
 }
 
 template <int FILTER, bool MARGINAL, bool GEER>

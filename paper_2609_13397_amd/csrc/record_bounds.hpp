@@ -20,8 +20,8 @@ __device__ __forceinline__ bool tangent_cone_reaches(const Record& R, float ax, 
   const float wx = W[0] * ax + W[1] * ay + W[2] * az;
   const float wy = W[3] * ax + W[4] * ay + W[5] * az;
   const float wz = W[6] * ax + W[7] * ay + W[8] * az;
-  const float lo = sqrtf(fmaxf(nsn, 0.f)) * 0.9999f - sqrtf(S[0] + S[3] + S[5]) * sqrtf(vv) * rad;
-  const float hi = sqrtf(wx * wx + wy * wy + wz * wz) * 1.0001f + sqrtf(R.kg) * rad * 1.0001f;
+  const float lo = fast_sqrt(fmaxf(nsn, 0.f)) * 0.9999f - fast_sqrt(S[0] + S[3] + S[5]) * fast_sqrt(vv) * rad;
+  const float hi = fast_sqrt(wx * wx + wy * wy + wz * wz) * 1.0001f + fast_sqrt(R.kg) * rad * 1.0001f;
   return lo <= hi;
 }
 
