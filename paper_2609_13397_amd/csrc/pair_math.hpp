@@ -176,20 +176,33 @@ __device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, Pair
 // <= t*^2 c_pix / s'_min^2, which bounds q^T A^{-1} q from below (Sigma_render^u is
 // dominated by Sigma_fp^u).  False means the pair cannot reach alpha_min.  On true, g
 // holds the geometry of Eq. 2.
-template <int FILTER>
-__device__ __forceinline__ bool pair_cheap(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
-                                           PairGeom& g) {
+// Tangent-cone test of pair_cheap; on true, g holds a = W d and aa = |a|^2.
+__device__ __forceinline__ bool pair_tangent(const Record& R, const PairPixel& p, PairGeom& g, float& aa) {
   const float nx = R.vy * p.a2 - R.vz * p.a1;
   const float ny = R.vz * p.a0 - R.vx * p.a2;
   const float nz = R.vx * p.a1 - R.vy * p.a0;
-  const float aa = pair_dir(R, p, g);
+  aa = pair_dir(R, p, g);
   const float* S = R.S;
   const float nsn = nx * (S[0] * nx + S[1] * ny + S[2] * nz) + ny * (S[3] * ny + S[4] * nz) + S[5] * nz * nz;
-  if (nsn > aa) return false;
+  return nsn <= aa;
+}
+
+// The tests of pair_cheap after the tangent-cone test (g holds a, aa = |a|^2).
+template <int FILTER>
+__device__ __forceinline__ bool pair_cheap_rest(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
+                                                PairGeom& g, float aa) {
   g.rn = fast_rcp(aa);
   if (!pair_geom_rest(R, p, O, o.t_near, g)) return false;
   if (FILTER == 0) return g.D2 <= R.Lg;
   return g.D2 <= R.Lg * fmaf(g.tstar * g.tstar * p.cpix, R.kg, 1.f) * 1.0001f + 1e-6f;
+}
+
+template <int FILTER>
+__device__ __forceinline__ bool pair_cheap(const Record& R, const PairPixel& p, const Origin& O, const Opts& o,
+                                           PairGeom& g) {
+  float aa;
+  if (!pair_tangent(R, p, g, aa)) return false;
+  return pair_cheap_rest<FILTER>(R, p, O, o, g, aa);
 }
 
 // Filtered response T of a pair that passed pair_cheap.  FILTER 0: centre ray (Eq. 3,
