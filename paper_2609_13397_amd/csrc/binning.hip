@@ -1,13 +1,16 @@
 // Angular-cone tile binning.  A (tile, Gaussian) pair is emitted when the tile's cone
-// of pixel-centre rays overlaps the Gaussian's influence cone; no projection is
-// involved, so the same test serves every central camera.
+// of pixel-centre rays can overlap the Gaussian's influence cone; no projection is
+// involved, so the same code serves every central camera.  Both cones are in chord
+// form (axis, chord radius), tested by the triangle inequality of the chord distance
+// (chords_overlap), which accepts every pair the exact angular test accepts.
 //
 // Layout of the work: a wavefront owns 64 Gaussians of one view.  Phase 1: each lane
 // tests its Gaussian against every 8x8 tile group of the view (a loop that is uniform
 // across the wave, reading the group cones through the scalar cache) and records the
 // groups it overlaps.  Phase 2: the wave walks the lanes' hit groups together, one
-// lane per tile of the group, so the 64 tile tests of a group run as one vector step
-// and their ballot gives both the count and, in the emit pass, each pair's position.
+// lane per member tile, reading the group-major member copy (one coalesced 1 KiB
+// load per group), so the 64 tile tests of a group run as one vector step and their
+// ballot gives both the count and, in the emit pass, each pair's position.
 #include "camera_dev.hpp"
 
 namespace cg {
@@ -23,11 +26,11 @@ __device__ __forceinline__ uint32_t readlane_u(uint32_t x, int l) {
 
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restrict__ cams,
-                                             const float4* __restrict__ cone, const TileCone* __restrict__ tiles,
-                                             const TileCone* __restrict__ groups, uint32_t* __restrict__ counts,
-                                             const uint32_t* __restrict__ offsets,
-                                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                             uint32_t* __restrict__ slot_gid) {
+                                             const float4* __restrict__ cone, const float4* __restrict__ groups,
+                                             const float4* __restrict__ members,
+                                             const uint32_t* __restrict__ member_tile, uint32_t* __restrict__ counts,
+                                             const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
+                                             uint32_t* __restrict__ vals, uint32_t* __restrict__ slot_gid) {
   __shared__ uint16_t hits[4][64][kMaxGroupHits];
   const int v = blockIdx.y;
   const DevCamera& c = cams[v];
@@ -35,55 +38,49 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = i < n;
   const int64_t gv = (int64_t)v * n + i;
-  const float4 cn = in ? cone[gv] : make_float4(0.f, 0.f, 1.f, -1.f);
-  const float sg = sinf(0.5f * cn.w), cg = cosf(0.5f * cn.w);
+  const float4 cn = in ? cone[gv] : make_float4(0.f, 0.f, 1.f, kChordNever);
   const int ng = c.groups_x * c.groups_y;
+  const float4* __restrict__ vgroups = groups + c.group_offset;
 
   // phase 1: overlapping groups of this lane's Gaussian
   int nh = 0;
   if (__ballot(cn.w >= 0.f) != 0) {
     for (int gi = 0; gi < ng; ++gi) {
-      const TileCone G = groups[c.group_offset + gi];
-      if (cones_overlap(G.ax, G.ay, G.az, G.beta, G.sb, G.cb, cn.x, cn.y, cn.z, cn.w, sg, cg)) {
+      if (chords_overlap(vgroups[gi], cn.x, cn.y, cn.z, cn.w)) {
         if (nh < kMaxGroupHits) hits[wave][lane][nh] = (uint16_t)gi;
         ++nh;
       }
     }
   }
 
-  // phase 2: tile tests, one lane per tile of a hit group
+  // phase 2: tile tests, one lane per member tile of a hit group
   uint32_t my_count = 0;
   const uint32_t my_base = (EMIT && in) ? offsets[gv] : 0u;
-  const int tl_x = lane % kGroup, tl_y = lane / kGroup;
+  const float4* __restrict__ vmem = members + (int64_t)c.group_offset * kGroupTiles + lane;
+  const uint32_t* __restrict__ vtile = member_tile + (int64_t)c.group_offset * kGroupTiles + lane;
   for (int l = 0; l < 64; ++l) {
     const int nh_l = __builtin_amdgcn_readlane(nh, l);
     if (nh_l == 0) continue;
     const float cx = readlane_f(cn.x, l), cy = readlane_f(cn.y, l), cz = readlane_f(cn.z, l);
-    const float cw = readlane_f(cn.w, l), csg = readlane_f(sg, l), ccg = readlane_f(cg, l);
+    const float cw = readlane_f(cn.w, l);
     const uint32_t base = EMIT ? readlane_u(my_base, l) : 0u;
     const bool ovf = nh_l > kMaxGroupHits;
     const int n_iter = ovf ? ng : nh_l;
     uint32_t cnt = 0;
     for (int h = 0; h < n_iter; ++h) {
-      const int gi = ovf ? h : (int)hits[wave][l][h];
+      int gi;
       if (ovf) {
-        const TileCone G = groups[c.group_offset + gi];
-        if (!cones_overlap(G.ax, G.ay, G.az, G.beta, G.sb, G.cb, cx, cy, cz, cw, csg, ccg)) continue;
+        gi = h;
+        if (!chords_overlap(vgroups[gi], cx, cy, cz, cw)) continue;
+      } else {
+        gi = __builtin_amdgcn_readfirstlane((int)hits[wave][l][h]);
       }
-      const int gx = gi % c.groups_x, gy = gi / c.groups_x;
-      const int tx = gx * kGroup + tl_x, ty = gy * kGroup + tl_y;
-      bool hit = false;
-      int tile = 0;
-      if (tx < c.tiles_x && ty < c.tiles_y) {
-        tile = c.tile_offset + ty * c.tiles_x + tx;
-        const TileCone T = tiles[tile];
-        hit = cones_overlap(T.ax, T.ay, T.az, T.beta, T.sb, T.cb, cx, cy, cz, cw, csg, ccg);
-      }
+      const bool hit = chords_overlap(vmem[gi * kGroupTiles], cx, cy, cz, cw);
       const uint64_t m = __ballot(hit);
       if (EMIT && hit) {
         const uint32_t pos = base + cnt + (uint32_t)__popcll(m & __lanemask_lt());
         const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63) + l);
-        keys[pos] = (uint32_t)tile;
+        keys[pos] = vtile[gi * kGroupTiles];
         if (slot_gid) {
           vals[pos] = pos;
           slot_gid[pos] = gid;
@@ -98,20 +95,22 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
   if (!EMIT && in) counts[gv] = my_count;
 }
 
-hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone,
-                            const TileCone* tiles, const TileCone* groups, uint32_t* counts, hipStream_t s) {
+hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
+                            const float4* members, uint32_t* counts, hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
-  k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, tiles, groups, counts, nullptr, nullptr, nullptr, nullptr);
+  k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, nullptr, counts, nullptr, nullptr, nullptr,
+                                          nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const TileCone* tiles,
-                           const TileCone* groups, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
-                           uint32_t* slot_gid, hipStream_t s) {
+hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
+                           const float4* members, const uint32_t* member_tile, const uint32_t* offsets,
+                           uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
-  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, tiles, groups, nullptr, offsets, keys, vals, slot_gid);
+  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, member_tile, nullptr, offsets, keys, vals,
+                                         slot_gid);
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Camera kernels: Pi^{-1} for a list of coordinates, and the per-tile / per-group
 // ray cones used by the angular binning (camera-agnostic: only unit ray directions
 // are compared, so the same code serves fields of view beyond 180 degrees).
-#include "camera_dev.hpp"
+#include "pixel_buf.hpp"
 
 namespace cg {
 
@@ -49,20 +49,24 @@ __device__ __forceinline__ float block_max(float v, float* sh) {
 // One workgroup per 16x16 tile: the cone around the tile's pixel-centre rays (axis =
 // normalised mean direction, half-angle = largest angle to a pixel ray plus a small
 // margin) and the tile's largest footprint coefficient (|d_x-d|^2 + |d_y-d|^2) / 3,
-// whose per-view maximum bounds every pixel's footprint in the Gaussian cones.
+// whose per-view maximum (taken by k_group_cones) bounds every pixel's footprint in
+// the Gaussian cones.  Each thread also stores its pixel's rays in the pixel buffer (pixel_buf.hpp), in the
+// slot of the render thread that shades that pixel.
 __global__ __launch_bounds__(256) void k_tile_cones(const DevCamera* __restrict__ cams, int n_views, float fs,
-                                                    TileCone* __restrict__ tiles, float* __restrict__ view_cmax) {
+                                                    int64_t n_slots, TileCone* __restrict__ tiles,
+                                                    float4* __restrict__ pix) {
   __shared__ float sh[4];
   const int t = blockIdx.x;
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
-  const int lt = t - c.tile_offset;
-  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
-  const int i = tx * kTile + (threadIdx.x & (kTile - 1));
-  const int j = ty * kTile + (threadIdx.x / kTile);
+  int i, j;
+  tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
   PixelRay r;
   r.valid = false;
   if (i < c.crop_w && j < c.crop_h) r = pixel_ray(c, i, j, fs);
+  PairPixel pp{};
+  if (r.valid) pp = make_pair_pixel(r);
+  store_pair_pixel(pix, n_slots, (int64_t)t * kTilePx + threadIdx.x, pp);
   const float w = r.valid ? 1.f : 0.f;
   const float sx = block_sum(r.valid ? r.df[0] : 0.f, sh);
   const float sy = block_sum(r.valid ? r.df[1] : 0.f, sh);
@@ -84,23 +88,26 @@ __global__ __launch_bounds__(256) void k_tile_cones(const DevCamera* __restrict_
     if (nrm < 0.5f * cnt) beta = kPiF;  // rays spread too widely for a mean axis
     tc = TileCone{ax, ay, az, beta, sinf(0.5f * beta), cosf(0.5f * beta), cm, 0.f};
   }
-  if (threadIdx.x == 0) {
-    tiles[t] = tc;
-    // positive floats order like their bit patterns
-    atomicMax(reinterpret_cast<unsigned int*>(&view_cmax[v]), __float_as_uint(cm));
-  }
+  if (threadIdx.x == 0) tiles[t] = tc;
 }
 
 hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles, float fs, TileCone* tiles,
-                             float* view_cmax, hipStream_t s) {
+                             float4* pix, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  k_tile_cones<<<dim3(total_tiles), dim3(256), 0, s>>>(cams, n_views, fs, tiles, view_cmax);
+  k_tile_cones<<<dim3(total_tiles), dim3(kTilePx), 0, s>>>(cams, n_views, fs, (int64_t)total_tiles * kTilePx, tiles,
+                                                          pix);
   return hipGetLastError();
 }
 
-// One wave per 8x8 group of tiles: a cone containing every member tile's cone.
+// One wave per 8x8 group of tiles: a cone containing every member tile's cone, the
+// group-major copy of the member tiles' chord cones and tile indices that the binning
+// reads one group at a time, and the group's share of the per-view maximum footprint
+// coefficient (one atomic per group: same-address atomics from every tile would
+// contend across the XCDs).
 __global__ __launch_bounds__(64) void k_group_cones(const DevCamera* __restrict__ cams, int n_views,
-                                                   const TileCone* __restrict__ tiles, TileCone* __restrict__ groups) {
+                                                   const TileCone* __restrict__ tiles, float4* __restrict__ groups,
+                                                   float4* __restrict__ members, uint32_t* __restrict__ member_tile,
+                                                   float* __restrict__ view_cmax) {
   const int g = blockIdx.x;
   const int v = view_of_group(cams, n_views, g);
   const DevCamera& c = cams[v];
@@ -108,18 +115,25 @@ __global__ __launch_bounds__(64) void k_group_cones(const DevCamera* __restrict_
   const int gx = lg % c.groups_x, gy = lg / c.groups_x;
   const int tx = gx * kGroup + (threadIdx.x % kGroup), ty = gy * kGroup + (threadIdx.x / kGroup);
   TileCone tc{0.f, 0.f, 1.f, -1.f, 0.f, 1.f, 0.f, 0.f};
-  if (tx < c.tiles_x && ty < c.tiles_y) tc = tiles[c.tile_offset + ty * c.tiles_x + tx];
+  uint32_t tile = 0;
+  if (tx < c.tiles_x && ty < c.tiles_y) {
+    tile = (uint32_t)(c.tile_offset + ty * c.tiles_x + tx);
+    tc = tiles[tile];
+  }
   const bool live = tc.beta >= 0.f;
+  members[(int64_t)g * kGroupTiles + threadIdx.x] = make_float4(tc.ax, tc.ay, tc.az, chord_radius(tc.beta));
+  member_tile[(int64_t)g * kGroupTiles + threadIdx.x] = tile;
   float sx = live ? tc.ax : 0.f, sy = live ? tc.ay : 0.f, sz = live ? tc.az : 0.f, cnt = live ? 1.f : 0.f;
-  float bmax = live ? tc.beta : -1.f;
+  float bmax = live ? tc.beta : -1.f, cm = live ? tc.cmax : 0.f;
   for (int o = 32; o > 0; o >>= 1) {
     sx += __shfl_xor(sx, o);
     sy += __shfl_xor(sy, o);
     sz += __shfl_xor(sz, o);
     cnt += __shfl_xor(cnt, o);
     bmax = fmaxf(bmax, __shfl_xor(bmax, o));
+    cm = fmaxf(cm, __shfl_xor(cm, o));
   }
-  TileCone out{0.f, 0.f, 1.f, -1.f, 0.f, 1.f, 0.f, 0.f};
+  float4 out = make_float4(0.f, 0.f, 1.f, kChordNever);
   if (cnt > 0.f) {
     const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
     const float ax = sx / nrm, ay = sy / nrm, az = sz / nrm;
@@ -131,15 +145,21 @@ __global__ __launch_bounds__(64) void k_group_cones(const DevCamera* __restrict_
     for (int o = 32; o > 0; o >>= 1) ang = fmaxf(ang, __shfl_xor(ang, o));
     float beta = ang * 1.0001f + 2e-6f;
     if (bmax >= kPiF || nrm < 0.5f * cnt) beta = kPiF;
-    out = TileCone{ax, ay, az, beta, sinf(0.5f * beta), cosf(0.5f * beta), 0.f, 0.f};
+    out = make_float4(ax, ay, az, chord_radius(beta));
   }
-  if (threadIdx.x == 0) groups[g] = out;
+  if (threadIdx.x == 0) {
+    groups[g] = out;
+    // non-negative floats order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned int*>(&view_cmax[v]), __float_as_uint(cm));
+  }
 }
 
 hipError_t launch_group_cones(const DevCamera* cams, int n_views, int total_groups, const TileCone* tiles,
-                              TileCone* groups, hipStream_t s) {
+                              float4* groups, float4* members, uint32_t* member_tile, float* view_cmax,
+                              hipStream_t s) {
   if (total_groups == 0) return hipSuccess;
-  k_group_cones<<<dim3(total_groups), dim3(64), 0, s>>>(cams, n_views, tiles, groups);
+  k_group_cones<<<dim3(total_groups), dim3(kGroupTiles), 0, s>>>(cams, n_views, tiles, groups, members, member_tile,
+                                                                view_cmax);
   return hipGetLastError();
 }
 

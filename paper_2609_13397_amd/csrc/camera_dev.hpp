@@ -155,17 +155,20 @@ __device__ __forceinline__ int view_of_group(const DevCamera* cams, int n_views,
   return v;
 }
 
-// Cone-versus-cone overlap: the angle between the axes is at most beta + gamma.  The
-// test uses the chord |a - b| = 2 sin(angle / 2), accurate for small angles in
-// float32, with an absolute margin of 1e-5 rad.
-__device__ __forceinline__ bool cones_overlap(float ax, float ay, float az, float beta, float sb, float cb, float bx,
-                                              float by, float bz, float gamma, float sg, float cg) {
-  if (beta < 0.f || gamma < 0.f) return false;
-  if (beta + gamma >= kPiF) return true;
-  const float s = sb * cg + cb * sg;  // sin((beta + gamma) / 2)
-  const float dx = ax - bx, dy = ay - by, dz = az - bz;
-  const float lim = 2.f * s + 1e-5f;
-  return dx * dx + dy * dy + dz * dz <= lim * lim;
+// Chord-cone overlap test (the chord form of cg_common.hpp): |a - b| <= w_a + w_b,
+// written as |a - b|^2 <= lim |lim| so that a negative sum (an empty cone) fails.
+__device__ __forceinline__ bool chords_overlap(const float4& a, float bx, float by, float bz, float bw) {
+  const float dx = a.x - bx, dy = a.y - by, dz = a.z - bz;
+  const float lim = a.w + bw;
+  return dx * dx + dy * dy + dz * dz <= lim * fabsf(lim);
+}
+
+// Chord radius of a cone of half angle beta, with a 5e-6 absolute margin for the
+// float32 rounding of the test (each side of a test carries one).
+__device__ __forceinline__ float chord_radius(float beta) {
+  if (beta < 0.f) return kChordNever;
+  if (beta >= kPiF) return kChordAll;
+  return 2.f * sinf(0.5f * beta) + 5e-6f;
 }
 
 }  // namespace cg

@@ -216,8 +216,11 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     DevCamera* dcams = sc.get_n<DevCamera>(n_views);
     CG_HIP(hipMemcpyAsync(dcams, hc.data(), sizeof(DevCamera) * n_views, hipMemcpyHostToDevice, s));
     TileCone* tiles = sc.get_n<TileCone>(total_tiles);
-    TileCone* groups = sc.get_n<TileCone>(total_groups);
+    float4* groups = sc.get_n<float4>(total_groups);
+    float4* members = sc.get_n<float4>(total_groups * kGroupTiles);
+    uint32_t* member_tile = sc.get_n<uint32_t>(total_groups * kGroupTiles);
     float* view_cmax = sc.get_n<float>(n_views);
+    float4* pix = sc.get_n<float4>(std::max<int64_t>(total_tiles, 1) * kTilePx * 4);
     Record* rec = sc.get_n<Record>(std::max<int64_t>(nv, 1));
     uint32_t* depth_key = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
     float4* cone = sc.get_n<float4>(std::max<int64_t>(nv, 1));
@@ -228,8 +231,9 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     {
       ProfScope ps(ST_CAMERA, s);
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(view_cmax), 0u, n_views, s));
-      CG_HIP(launch_tile_cones(dcams, n_views, (int)total_tiles, o.fs, tiles, view_cmax, s));
-      CG_HIP(launch_group_cones(dcams, n_views, (int)total_groups, tiles, groups, s));
+      CG_HIP(launch_tile_cones(dcams, n_views, (int)total_tiles, o.fs, tiles, pix, s));
+      CG_HIP(launch_group_cones(dcams, n_views, (int)total_groups, tiles, groups, members, member_tile,
+                                view_cmax, s));
     }
     {
       ProfScope ps(ST_PREPROCESS, s);
@@ -237,7 +241,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     }
     {
       ProfScope ps(ST_BIN_COUNT, s);
-      CG_HIP(launch_bin_count(n, n_views, dcams, cone, tiles, groups, counts, s));
+      CG_HIP(launch_bin_count(n, n_views, dcams, cone, groups, members, counts, s));
     }
     // compositing order of the (view, Gaussian) items, then pair offsets in that order
     const int view_bits = bits_for(std::max(n_views - 1, 1));
@@ -288,7 +292,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     if (P > 0) {
       {
         ProfScope ps(ST_BIN_EMIT, s);
-        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, tiles, groups, offsets, keys, vals, slot_gid, s));
+        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, member_tile, offsets, keys, vals,
+                               slot_gid, s));
       }
       {
         ProfScope ps(ST_SORT, s);
@@ -321,8 +326,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     }
     {
       ProfScope ps(ST_RENDER, s);
-      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sorted_gid, tlo_suffix, out_rgba,
-                               final_T, n_last, counters, s));
+      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sorted_gid, pix, tlo_suffix,
+                               out_rgba, final_T, n_last, counters, s));
     }
     unsigned long long host_counters[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (counters && (opts_in->count_pairs || stats)) {
@@ -357,6 +362,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       st->sorted_slots = sslots;
       st->sorted_gid = sorted_gid;
       st->ranges = ranges;
+      st->pix = pix;
       st->final_T = final_T;
       st->n_last = n_last;
       st->out_rgba = out_rgba;

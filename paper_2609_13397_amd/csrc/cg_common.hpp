@@ -13,6 +13,7 @@ namespace cg {
 constexpr int kTile = 16;             // tile edge in pixels (one workgroup of 256 threads)
 constexpr int kTilePx = kTile * kTile;
 constexpr int kGroup = 8;             // tile group edge in tiles (64 tiles = one wave64)
+constexpr int kGroupTiles = kGroup * kGroup;
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -37,12 +38,20 @@ struct DevCamera {
   float pad1;
 };
 
-// Bounding cone of the pixel-centre rays of a tile or tile group: unit axis, half
-// angle beta (< 0: empty; >= pi: everything) and sin/cos of beta/2.
+// Bounding cone of the pixel-centre rays of a tile: unit axis, half angle beta (< 0:
+// empty; >= pi: everything), sin/cos of beta/2 and the tile's largest footprint
+// coefficient.
 struct TileCone {
   float ax, ay, az, beta;
   float sb, cb, cmax, pad;
 };
+
+// Chord form of a cone, as the binning tests use it (a float4): unit axis (x, y, z) and
+// chord radius w, the cone holding the unit directions d with |d - axis| <= w.  Two
+// cones can share a direction only if |a - b| <= w_a + w_b (triangle inequality for
+// the chord distance on the unit sphere).  kChordNever marks an empty cone (it
+// overlaps nothing, even a kChordAll one); kChordAll one that holds every direction.
+constexpr float kChordNever = -8.f, kChordAll = 4.f;
 
 // Per (view, Gaussian) render record (128 bytes).  Cull cone: a ray direction d can
 // reach the Gaussian only if |d - u| <= lim, u = v / |v| (the influence cone of the
@@ -97,10 +106,16 @@ struct GaussPtrs {
 // camera.hip
 hipError_t launch_unproject(const DevCamera* cam, int64_t n, const float* pix_xy, float* dirs, uint8_t* valid,
                             hipStream_t s);
+// pix: the per-pixel ray buffer, 4 * 16 bytes per slot, total_tiles * 256 slots
 hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles, float fs, TileCone* tiles,
-                             float* view_cmax, hipStream_t s);
+                             float4* pix, hipStream_t s);
+// Per 8x8 tile group: its chord cone (groups), and a group-major copy of its 64 member
+// tiles' chord cones (members, kChordNever for tiles outside the view) with their
+// global tile indices (member_tile).  view_cmax: per-view maximum footprint
+// coefficient, zeroed beforehand.
 hipError_t launch_group_cones(const DevCamera* cams, int n_views, int total_groups, const TileCone* tiles,
-                              TileCone* groups, hipStream_t s);
+                              float4* groups, float4* members, uint32_t* member_tile, float* view_cmax,
+                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
 // preprocess.hip
@@ -108,11 +123,12 @@ hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_vi
                              const Opts& o, Record* rec, uint32_t* depth_key, float4* cone, hipStream_t s);
 
 // binning.hip
-hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone,
-                            const TileCone* tiles, const TileCone* groups, uint32_t* counts, hipStream_t s);
-hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const TileCone* tiles,
-                           const TileCone* groups, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
-                           uint32_t* slot_gid, hipStream_t s);
+// cone: per (view, Gaussian) chord cone of its influence cone (from the preprocess)
+hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
+                            const float4* members, uint32_t* counts, hipStream_t s);
+hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
+                           const float4* members, const uint32_t* member_tile, const uint32_t* offsets,
+                           uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, hipStream_t s);
 hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,
                               hipStream_t s);
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
@@ -138,7 +154,7 @@ hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_til
                                int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* tlo_suffix,
                                hipStream_t s);
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid,
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix,
                              const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
                              unsigned long long* counters, hipStream_t s);
 

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
   else if (gamma >= kPiF) r.lim = 3.f;
   else r.lim = 2.f * sinf(0.5f * gamma) + 1e-5f;
   rec[out] = r;
-  cone[out] = make_float4(ux, uy, uz, gamma);
+  cone[out] = make_float4(ux, uy, uz, chord_radius(gamma));
 }
 
 hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,

@@ -17,43 +17,12 @@
 #include <algorithm>
 
 #include "fwd_state.hpp"
-#include "pair_math.hpp"
+#include "pixel_buf.hpp"
 #include "sh.hpp"
-#include "wave_ops.hpp"
 
 namespace cg {
 
 constexpr int kGradLen = 20;  // dW[9] dmu[3] dsigma dsp2[3] drgb[3] pad (zero)
-
-struct WaveConeB {
-  float ax, ay, az, rad;
-  bool live;
-};
-
-__device__ __forceinline__ WaveConeB wave_cone_b(const PixelRay& r) {
-  float sx = r.valid ? r.df[0] : 0.f, sy = r.valid ? r.df[1] : 0.f, sz = r.valid ? r.df[2] : 0.f;
-  float cnt = r.valid ? 1.f : 0.f;
-  sx = wave_total(sx);
-  sy = wave_total(sy);
-  sz = wave_total(sz);
-  cnt = wave_total(cnt);
-  WaveConeB w;
-  w.live = cnt > 0.f;
-  const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
-  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
-  w.ax = sx * inv;
-  w.ay = sy * inv;
-  w.az = sz * inv;
-  float ch = 0.f;
-  if (r.valid) {
-    const float dx = w.ax - r.df[0], dy = w.ay - r.df[1], dz = w.az - r.df[2];
-    ch = sqrtf(dx * dx + dy * dy + dz * dz);
-  }
-  ch = wave_max(ch);
-  w.rad = ch * 1.0001f + 2e-6f;
-  if (nrm < 0.5f * cnt) w.rad = 3.f;
-  return w;
-}
 
 // Four waves per SIMD: the register budget (128 VGPRs) that pair_grad fits in without
 // spilling.
@@ -63,6 +32,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ sorted_gid,
                                                     const uint32_t* __restrict__ sorted_slots,
+                                                    const float4* __restrict__ pix,
                                                     const float* __restrict__ out_rgba,
                                                     const float* __restrict__ final_T,
                                                     const float* __restrict__ grad_rgba, float* __restrict__ partial,
@@ -74,18 +44,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (t >= total_tiles) return;
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
-  const int lt = t - c.tile_offset;
-  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int j = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  int i, j;
+  tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
   const bool inside = i < c.crop_w && j < c.crop_h;
-  PixelRay r;
-  r.valid = false;
-  if (inside) r = pixel_ray(c, i, j, o.fs);
-  const PairPixel px = make_pair_pixel(r);
+  const PairPixel px = load_pair_pixel(pix, (int64_t)total_tiles * kTilePx, (int64_t)t * kTilePx + threadIdx.x);
+  const bool valid = pixel_valid(px);
   const Origin org = make_origin(c);
-  const WaveConeB wc = wave_cone_b(r);
+  const WaveCone wc = wave_cone(px, valid);
   const int red_idx = wave_sum20_index(lane);  // which gradient component this lane's wave sum holds
 
   // upstream gradient and forward result of this pixel
@@ -105,7 +71,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
   const uint2 rg = ranges[t];
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  bool done = !r.valid;
+  bool done = !valid;
   const Record* vrec = rec + (int64_t)v * n_gauss;
   uint32_t stop_at = rg.y;
   for (uint32_t base = rg.x; base < rg.y; base += 64) {
@@ -185,7 +151,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (int64_t e = threadIdx.x; e < (int64_t)(rg.y - stop_at) * kGradLen; e += 256)
     partial[(int64_t)sorted_slots[stop_at + e / kGradLen] * kGradLen + e % kGradLen] = 0.f;
   // pixels that ran to the end of their list must have reached the stored transmittance
-  if (r.valid && !done && Ttr != Tfin) atomicAdd(mismatch, 1u);
+  if (valid && !done && Ttr != Tfin) atomicAdd(mismatch, 1u);
 }
 
 // Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt),
@@ -361,7 +327,7 @@ static void launch_bwd_g(const cg_fwd_state* st, const float* grad_rgba, float* 
   const int per_xcd = (int)((st->total_tiles + 7) / 8);
   k_render_bwd<FILTER, MARGINAL, GEER><<<dim3(per_xcd * 8), dim3(256), 0, s>>>(
       st->dcams, st->n_views, (int)st->total_tiles, per_xcd, st->opts, st->rec, st->g.n, st->ranges, st->sorted_gid,
-      st->sorted_slots, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
+      st->sorted_slots, st->pix, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
 }
 
 template <int FILTER, bool MARGINAL>

@@ -5,8 +5,7 @@
 // closed-form response of Eq. 9 (with the marginal floor composition of Eq. 12) and
 // composites front to back (Eq. 4).  The workgroup stops fetching batches once every
 // pixel has terminated.
-#include "pair_math.hpp"
-#include "wave_ops.hpp"
+#include "pixel_buf.hpp"
 
 namespace cg {
 
@@ -17,48 +16,14 @@ namespace cg {
 constexpr int kFwdBatch = 128;
 static_assert(kFwdBatch % 64 == 0 && kFwdBatch <= 256, "one record per thread, whole waves");
 
-// Wave-level view of a tile: wave w renders the 8x8 quadrant (w % 2, w / 2) of the
-// 16x16 tile.  Its cone (axis = normalised mean of the quadrant's centre rays, chord
-// radius = largest chord from the axis to one of them) lets the wave drop, 64 records
-// at a time, every record whose influence cone cannot reach any of its pixels:
-// |a - u| > lim + radius implies |d - u| > lim for every ray d of the quadrant.
-struct WaveCone {
-  float ax, ay, az, rad;
-  bool live;
-};
-
-__device__ __forceinline__ WaveCone wave_cone(const PixelRay& r) {
-  float sx = r.valid ? r.df[0] : 0.f, sy = r.valid ? r.df[1] : 0.f, sz = r.valid ? r.df[2] : 0.f;
-  float cnt = r.valid ? 1.f : 0.f;
-  sx = wave_total(sx);
-  sy = wave_total(sy);
-  sz = wave_total(sz);
-  cnt = wave_total(cnt);
-  WaveCone w;
-  w.live = cnt > 0.f;
-  const float nrm = sqrtf(sx * sx + sy * sy + sz * sz);
-  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
-  w.ax = sx * inv;
-  w.ay = sy * inv;
-  w.az = sz * inv;
-  float ch = 0.f;
-  if (r.valid) {
-    const float dx = w.ax - r.df[0], dy = w.ay - r.df[1], dz = w.az - r.df[2];
-    ch = sqrtf(dx * dx + dy * dy + dz * dz);
-  }
-  ch = wave_max(ch);
-  w.rad = ch * 1.0001f + 2e-6f;
-  if (nrm < 0.5f * cnt) w.rad = 3.f;  // rays spread too widely for a mean axis
-  return w;
-}
-
 // COUNT: also count, per pixel, the pairs that reached the per-pixel tests, those that
 // needed the full footprint arithmetic and those composited, into counters[0..2].
 template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                 int per_xcd, Opts o, const Record* __restrict__ rec, int64_t n_gauss,
                                                 const uint2* __restrict__ ranges,
-                                                const uint32_t* __restrict__ sorted_gid, float* __restrict__ out_rgba,
+                                                const uint32_t* __restrict__ sorted_gid,
+                                                const float4* __restrict__ pix, float* __restrict__ out_rgba,
                                                 float* __restrict__ final_T, uint32_t* __restrict__ n_last,
                                                 unsigned long long* __restrict__ counters) {
   __shared__ Record srec[kFwdBatch];
@@ -71,22 +36,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   if (t >= total_tiles) return;
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
-  const int lt = t - c.tile_offset;
-  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int j = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const int lane = threadIdx.x & 63;
+  int i, j;
+  tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
   const bool inside = i < c.crop_w && j < c.crop_h;
-  PixelRay r;
-  r.valid = false;
-  if (inside) r = pixel_ray(c, i, j, o.fs);
-  const PairPixel px = make_pair_pixel(r);
+  const PairPixel px = load_pair_pixel(pix, (int64_t)total_tiles * kTilePx, (int64_t)t * kTilePx + threadIdx.x);
+  const bool valid = pixel_valid(px);
   const Origin org = make_origin(c);
-  const WaveCone wc = wave_cone(r);
+  const WaveCone wc = wave_cone(px, valid);
 
   const uint2 rg = ranges[t];
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  bool done = !r.valid;
+  bool done = !valid;
   uint32_t last = rg.x;
   const Record* vrec = rec + (int64_t)v * n_gauss;
   for (uint32_t base = rg.x; base < rg.y; base += kFwdBatch) {
@@ -144,7 +105,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     out.w = 1.f - Ttr;
     reinterpret_cast<float4*>(c.out)[(int64_t)j * c.crop_w + i] = out;
     if (final_T) final_T[p] = Ttr;
-    if (n_last) n_last[p] = r.valid ? last : rg.x;
+    if (n_last) n_last[p] = valid ? last : rg.x;
   }
   if (COUNT) {
     if (threadIdx.x < 3) scount[threadIdx.x] = 0;
@@ -219,6 +180,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
                                                     int per_xcd, Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ sorted_gid,
+                                                    const float4* __restrict__ pix,
                                                     const float* __restrict__ tlo_suffix,
                                                     unsigned long long* __restrict__ counters) {
   __shared__ Record srec[kFwdBatch];
@@ -230,21 +192,17 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   if (t >= total_tiles) return;
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
-  const int lt = t - c.tile_offset;
-  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int j = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const int lane = threadIdx.x & 63;
+  int i, j;
+  tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
   const bool inside = i < c.crop_w && j < c.crop_h;
-  PixelRay r;
-  r.valid = false;
-  if (inside) r = pixel_ray(c, i, j, o.fs);
-  const PairPixel px = make_pair_pixel(r);
+  const PairPixel px = load_pair_pixel(pix, (int64_t)total_tiles * kTilePx, (int64_t)t * kTilePx + threadIdx.x);
+  const bool valid = pixel_valid(px);
   const Origin org = make_origin(c);
-  const WaveCone wc = wave_cone(r);
+  const WaveCone wc = wave_cone(px, valid);
 
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  bool done = !r.valid;
+  bool done = !valid;
   const Record* vrec = rec + (int64_t)v * n_gauss;
   // pending pairs: t* (INFINITY = empty slot), alpha, Gaussian index; bmin = smallest t*
   float bt[kRayBuf], ba[kRayBuf];
@@ -365,7 +323,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
 
 template <int FILTER, bool MARGINAL, bool GEER>
 static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                           int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float* tlo_suffix,
+                           int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
                            float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
                            hipStream_t s) {
   const int per_xcd = (total_tiles + 7) / 8;
@@ -373,29 +331,29 @@ static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, 
   if (o.order_mode == CG_ORDER_RAY) {
     if (o.count_pairs)
       k_render_ray<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
-                                                                   n_gauss, ranges, sorted_gid, tlo_suffix, counters);
+                                                                   n_gauss, ranges, sorted_gid, pix, tlo_suffix, counters);
     else
       k_render_ray<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
-                                                                    n_gauss, ranges, sorted_gid, tlo_suffix, counters);
+                                                                    n_gauss, ranges, sorted_gid, pix, tlo_suffix, counters);
   } else if (o.count_pairs) {
     k_render<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
-                                                             ranges, sorted_gid, out_rgba, final_T, n_last, counters);
+                                                             ranges, sorted_gid, pix, out_rgba, final_T, n_last, counters);
   } else {
     k_render<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
-                                                              ranges, sorted_gid, out_rgba, final_T, n_last, nullptr);
+                                                              ranges, sorted_gid, pix, out_rgba, final_T, n_last, nullptr);
   }
   return hipGetLastError();
 }
 
 template <int FILTER, bool MARGINAL>
 static hipError_t launch_fm(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                            int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float* tlo_suffix,
+                            int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
                             float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
                             hipStream_t s) {
   if (o.backbone == CG_BACKBONE_RAY_INTEGRAL)
-    return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+    return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix,
                                             tlo_suffix, out_rgba, final_T, n_last, counters, s);
-  return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+  return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix,
                                            out_rgba, final_T, n_last, counters, s);
 }
 
@@ -408,24 +366,24 @@ hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_til
 }
 
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid,
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix,
                              const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
                              unsigned long long* counters, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
   switch (o.filter_mode) {
     case CG_FILTER_CENTER_RAY:
-      return launch_fm<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix, out_rgba,
+      return launch_fm<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix, out_rgba,
                                 final_T, n_last, counters, s);
     case CG_FILTER_ISOTROPIC:
-      return marginal ? launch_fm<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+      return marginal ? launch_fm<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix,
                                           out_rgba, final_T, n_last, counters, s)
-                      : launch_fm<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+                      : launch_fm<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix,
                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
     default:
-      return marginal ? launch_fm<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, tlo_suffix,
+      return marginal ? launch_fm<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix,
                                           out_rgba, final_T, n_last, counters, s)
-                      : launch_fm<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid,
+                      : launch_fm<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix,
                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
   }
 }
