@@ -24,15 +24,35 @@ __device__ __forceinline__ double kb_slope(const DevCamera& c, double th) {
   return 1.0 + t2 * (3.0 * c.k[0] + t2 * (5.0 * c.k[1] + t2 * (7.0 * c.k[2] + t2 * 9.0 * c.k[3])));
 }
 
-// theta_d(theta) = thd on [0, theta_max] by bracketed Newton (bisection when a step
-// leaves the bracket).  theta_d is increasing there (checked on the host).
+// theta_d(theta) = thd on [0, theta_max] (theta_d is increasing there, checked on the
+// host).  A float32 bracketed Newton solve gives a start within about 1e-6; FP64
+// bracketed Newton then converges from it in two or three steps.  Each FP64 step
+// divides by the slope through a float32 reciprocal: its relative error (~1e-7) only
+// scales a step that is already small, and the loop runs until the step is below
+// 1e-15, so the root is the FP64 one.  A step that leaves the bracket (or is not a
+// number) is replaced by bisection.
 __device__ inline double kb_solve(const DevCamera& c, double thd) {
+  const float k0 = (float)c.k[0], k1 = (float)c.k[1], k2 = (float)c.k[2], k3 = (float)c.k[3];
+  const float tdf = (float)thd;
+  float lof = 0.f, hif = (float)c.theta_max;
+  float tf = fminf(tdf, hif);
+  for (int it = 0; it < 32; ++it) {
+    const float t2 = tf * tf;
+    const float f = tf * (1.f + t2 * (k0 + t2 * (k1 + t2 * (k2 + t2 * k3)))) - tdf;
+    const float sl = 1.f + t2 * (3.f * k0 + t2 * (5.f * k1 + t2 * (7.f * k2 + t2 * 9.f * k3)));
+    if (f > 0.f) hif = tf; else lof = tf;
+    float nt = tf - f * __builtin_amdgcn_rcpf(sl);
+    if (!(nt > lof && nt < hif)) nt = 0.5f * (lof + hif);
+    const bool conv = fabsf(nt - tf) < 1e-6f || hif - lof < 1e-6f;
+    tf = nt;
+    if (conv) break;
+  }
   double lo = 0.0, hi = c.theta_max;
-  double th = fmin(thd, hi);
+  double th = fmin(fmax((double)tf, 0.0), hi);
   for (int it = 0; it < 64; ++it) {
     const double f = kb_theta_d(c, th) - thd;
     if (f > 0.0) hi = th; else lo = th;
-    double nt = th - f / kb_slope(c, th);
+    double nt = th - f * (double)__builtin_amdgcn_rcpf((float)kb_slope(c, th));
     if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
     const bool conv = fabs(nt - th) < 1e-15 || hi - lo < 1e-15;
     th = nt;
@@ -123,19 +143,37 @@ struct PixelRay {
 __device__ inline PixelRay pixel_ray(const DevCamera& c, int i, int j, float fs) {
   PixelRay r;
   const double px = c.crop_x0 + i + 0.5, py = c.crop_y0 + j + 0.5;
-  r.valid = cam_unproject(c, px, py, r.d);
-  if (!r.valid) {
-    for (int k = 0; k < 3; ++k) { r.d[k] = 0.0; r.df[k] = 0.f; r.dx[k] = 0.f; r.dy[k] = 0.f; }
-    r.cpix = 0.f;
-    return r;
+  double ex[3], ey[3];
+  if (c.model == CG_EQUIRECT) {
+    // Pi^{-1} separates in (phi(x), lambda(y)), and the forward half-pixel offsets
+    // are always in the domain: the edge rays reuse the centre's sines and cosines
+    // through the angle-addition formulas with the camera's fixed half-pixel steps.
+    const double phi = 2.0 * kPi * (px * c.inv_w - 0.5);
+    const double lam = kPi * (0.5 - py * c.inv_h);
+    double sp, cp, sl, cl;
+    sincos(phi, &sp, &cp);
+    sincos(lam, &sl, &cl);
+    const double sp1 = sp * c.eq_step[0] + cp * c.eq_step[1], cp1 = cp * c.eq_step[0] - sp * c.eq_step[1];
+    const double sl1 = sl * c.eq_step[2] + cl * c.eq_step[3], cl1 = cl * c.eq_step[2] - sl * c.eq_step[3];
+    const double dc[3] = {cl * sp, -sl, cl * cp}, xc[3] = {cl * sp1, -sl, cl * cp1}, yc[3] = {cl1 * sp, -sl1, cl1 * cp};
+    rot(c.R, dc, r.d);
+    rot(c.R, xc, ex);
+    rot(c.R, yc, ey);
+    r.valid = true;
+  } else {
+    r.valid = cam_unproject(c, px, py, r.d);
+    if (!r.valid) {
+      for (int k = 0; k < 3; ++k) { r.d[k] = 0.0; r.df[k] = 0.f; r.dx[k] = 0.f; r.dy[k] = 0.f; }
+      r.cpix = 0.f;
+      return r;
+    }
+    if (!cam_unproject(c, px + 0.5, py, ex) && !cam_unproject(c, px - 0.5, py, ex))
+      for (int k = 0; k < 3; ++k) ex[k] = r.d[k];
+    if (!cam_unproject(c, px, py + 0.5, ey) && !cam_unproject(c, px, py - 0.5, ey))
+      for (int k = 0; k < 3; ++k) ey[k] = r.d[k];
   }
-  double e[3];
-  if (!cam_unproject(c, px + 0.5, py, e) && !cam_unproject(c, px - 0.5, py, e))
-    for (int k = 0; k < 3; ++k) e[k] = r.d[k];
-  for (int k = 0; k < 3; ++k) r.dx[k] = (float)((e[k] - r.d[k]) * (double)fs);
-  if (!cam_unproject(c, px, py + 0.5, e) && !cam_unproject(c, px, py - 0.5, e))
-    for (int k = 0; k < 3; ++k) e[k] = r.d[k];
-  for (int k = 0; k < 3; ++k) r.dy[k] = (float)((e[k] - r.d[k]) * (double)fs);
+  for (int k = 0; k < 3; ++k) r.dx[k] = (float)((ex[k] - r.d[k]) * (double)fs);
+  for (int k = 0; k < 3; ++k) r.dy[k] = (float)((ey[k] - r.d[k]) * (double)fs);
   for (int k = 0; k < 3; ++k) r.df[k] = (float)r.d[k];
   r.cpix = (r.dx[0] * r.dx[0] + r.dx[1] * r.dx[1] + r.dx[2] * r.dx[2] + r.dy[0] * r.dy[0] + r.dy[1] * r.dy[1] +
             r.dy[2] * r.dy[2]) * (1.0f / 3.0f);

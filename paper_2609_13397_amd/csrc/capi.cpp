@@ -109,6 +109,11 @@ DevCamera make_dev_camera(const cg_camera& c) {
   }
   d.theta_max = c.theta_max;
   d.thd_max = c.model == CG_FISHEYE_KB ? kb_poly(c, (double)c.theta_max) : 0.0;
+  const double dphi = kPi * d.inv_w, dlam = -0.5 * kPi * d.inv_h;
+  d.eq_step[0] = std::cos(dphi);
+  d.eq_step[1] = std::sin(dphi);
+  d.eq_step[2] = std::cos(dlam);
+  d.eq_step[3] = std::sin(dlam);
   return d;
 }
 

@@ -34,6 +34,7 @@ struct DevCamera {
   double Rinv[9];        // inverse of R (world-to-camera)
   double o[3];
   double theta_max, thd_max;
+  double eq_step[4];     // equirect: cos, sin of the half-pixel steps pi / W and -pi / (2 H)
   float of[3];           // origin as given (float32), for the float32 depth key
   float pad1;
 };
