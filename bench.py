@@ -31,16 +31,19 @@ TRANSC_PER_PAIR = {True: 8, False: 4}
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 # Algorithmic HBM bytes of one render launch: per pair a 4-byte list entry and its
-# 128-byte record; per pixel the 16-byte RGBA output.
+# 128-byte record; per pixel the 64-byte ray record it reads and the 16-byte RGBA output.
 BYTES_PER_PAIR = 132
-BYTES_PER_PIXEL = 16
+BYTES_PER_PIXEL = 80
 
 # sources whose change invalidates the measured HBM traffic of the render kernel (the
 # kernel itself, the pair arithmetic and culling it inlines, and the records it reads)
 RENDER_SOURCES = ["paper_2609_13397_amd/csrc/render_fwd.hip", "paper_2609_13397_amd/csrc/pair_math.hpp",
                   "paper_2609_13397_amd/csrc/record_bounds.hpp", "paper_2609_13397_amd/csrc/camera_dev.hpp",
-                  "paper_2609_13397_amd/csrc/cg_common.hpp", "paper_2609_13397_amd/csrc/preprocess.hip"]
-TRAFFIC_KERNEL = "cg::k_render<1, true, false>"  # the anisotropic + marginal-floor variant the bench times
+                  "paper_2609_13397_amd/csrc/cg_common.hpp", "paper_2609_13397_amd/csrc/preprocess.hip",
+                  "paper_2609_13397_amd/csrc/pixel_buf.hpp", "paper_2609_13397_amd/csrc/wave_ops.hpp",
+                  "paper_2609_13397_amd/csrc/camera.hip"]
+# the anisotropic, marginal-floor, max-response variant the bench times
+TRAFFIC_KERNEL = "cg::k_render<1, true, false, false>"
 
 
 def render_source_hash() -> str:
@@ -287,7 +290,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--cpu-rows", type=int, default=160)
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-order", action="store_true", help="skip the per-ray compositing order leg")
