@@ -271,7 +271,7 @@ namespace cg {
 
 // ---------------------------------------------------------------------------- backward
 // Gradient of one pair's response T with respect to its record: dL/dT = dT is given;
-// the result g[19] = (dW[9], dmu[3], dsigma, dsp2[3], pad...) is ADDED to.  gm, ft, fl
+// the result is written to g[0..15] = (dW[9], dmu[3], dsigma, dsp2[3]).  gm, ft, fl
 // and filt are the forward intermediates left by pair_cheap and pair_full_keep for this
 // pair; every step is differentiated in reverse order.  G = g(Phi) (the marginal
 // composition) is differentiated in closed form: with both eigenvalues above rho^2,
@@ -509,14 +509,14 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
   const float dmu1 = dw1 - dwd * p.a1 + dte * p.a1;
   const float dmu2 = dw2 - dwd * p.a2 + dte * p.a2;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) g[k] += dW[k];
-  g[9] += dmu0;
-  g[10] += dmu1;
-  g[11] += dmu2;
-  g[12] += dsig;
-  g[13] += dsp0;
-  g[14] += dsp1;
-  g[15] += dsp2;
+  for (int k = 0; k < 9; ++k) g[k] = dW[k];
+  g[9] = dmu0;
+  g[10] = dmu1;
+  g[11] = dmu2;
+  g[12] = dsig;
+  g[13] = dsp0;
+  g[14] = dsp1;
+  g[15] = dsp2;
 }
 
 }  // namespace cg

@@ -92,9 +92,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       while (m) {
         const int k = (int)__builtin_ctzll(m);
         m &= m - 1;
-        float gv[kGradLen];
-#pragma unroll
-        for (int q = 0; q < kGradLen; ++q) gv[q] = 0.f;
+        float gv[kGradLen];  // written by the contributing lanes, zeroed for the others below
         bool contrib = false;
         if (!done) {
           const Record& R = srec[k];
@@ -127,13 +125,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 gv[16] = G0 * w;
                 gv[17] = G1 * w;
                 gv[18] = G2 * w;
-                if (T < o.alpha_max) pair_grad<FILTER, MARGINAL, GEER>(R, px, gm, ft, fl, filt, dalpha, T, gv);
+                if (T < o.alpha_max) {
+                  pair_grad<FILTER, MARGINAL, GEER>(R, px, gm, ft, fl, filt, dalpha, T, gv);
+                } else {  // alpha clamped at alpha_max: no gradient through T
+#pragma unroll
+                  for (int q = 0; q < 16; ++q) gv[q] = 0.f;
+                }
                 Ttr = test;
               }
             }
           }
         }
         if (__ballot(contrib) != 0) {
+          if (!contrib) {
+#pragma unroll
+            for (int q = 0; q < kGradLen; ++q) gv[q] = 0.f;
+          }
+          gv[kGradLen - 1] = 0.f;  // padding component
           const float s = wave_sum20(gv, lane);
           if (red_idx >= 0) gacc[wave][k][red_idx] = s;
         }
