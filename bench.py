@@ -267,6 +267,58 @@ def summarize_traffic(fetch_csv: str, write_csv: str, commands) -> dict:
     return out
 
 
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES",
+               "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU"]
+N_SIMD = 256 * 4          # MI355X: 256 CUs x 4 SIMDs
+CLOCK_GHZ = 2.4
+VALU_CYCLES_PER_INST = 4  # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+
+
+def summarize_valu(sq_csv: str, trace_csv: str, out_md: str, commands, kernels) -> None:
+    """VALU utilisation of the given kernels from one rocprofv3 --pmc run of SQ_COUNTERS
+    (per-dispatch values) and a --kernel-trace run of the same command (per-dispatch
+    durations, kernel_trace.csv), grouped by kernel and grid size (one row per workload).
+    VALU issue = VALU instructions x 4 cycles / (duration x clock x SIMDs); lane
+    utilisation = active-lane VALU cycles / (64 x wave VALU cycles)."""
+    import csv
+    with open(sq_csv) as f:
+        rows = list(csv.DictReader(f))
+    with open(trace_csv) as f:
+        trace = list(csv.DictReader(f))
+    lines = ["# VALU utilisation: " + ", ".join(kernels), "", "Commands (run from the repository root on the GPU box):", "",
+             "```", *commands, "```", "",
+             f"VALU issue = SQ_INSTS_VALU x {VALU_CYCLES_PER_INST} cycles / (average duration in the kernel trace x "
+             f"{CLOCK_GHZ} GHz x {N_SIMD} SIMDs). Lane utilisation = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU). "
+             "Counters and durations are averaged over the dispatches of each kernel and grid size "
+             "(4657152 threads: fisheye_1M; 3686400: train_1M).", "",
+             "| kernel | grid (threads) | dispatches | avg duration (ms) | waves | VALU inst | SALU inst | LDS inst | "
+             "VALU issue | lane utilisation |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in kernels:
+        groups = {}
+        for r in rows:
+            if k in r["Kernel_Name"] and r["Counter_Name"] in SQ_COUNTERS:
+                groups.setdefault(int(r["Grid_Size"]), {}).setdefault(r["Counter_Name"], []).append(
+                    float(r["Counter_Value"]))
+        if not groups:
+            raise SystemExit(f"no {k} dispatches in {sq_csv}")
+        for grid in sorted(groups, reverse=True):
+            per = groups[grid]
+            avg = {c: sum(v) / len(v) for c, v in per.items()}
+            ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
+                  if k in r["Kernel_Name"] and int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) == grid]
+            if not ns:
+                raise SystemExit(f"no {k} with grid {grid} in {trace_csv}")
+            t = sum(ns) / len(ns) * 1e-9
+            issue = avg["SQ_INSTS_VALU"] * VALU_CYCLES_PER_INST / (t * CLOCK_GHZ * 1e9 * N_SIMD)
+            lane = avg["SQ_THREAD_CYCLES_VALU"] / (64.0 * avg["SQ_ACTIVE_INST_VALU"])
+            lines.append(f"| `{k}` | {grid} | {len(per['SQ_INSTS_VALU'])} | {t * 1e3:.3f} | {avg['SQ_WAVES']:.0f} | "
+                         f"{avg['SQ_INSTS_VALU']:.3e} | {avg['SQ_INSTS_SALU']:.3e} | {avg['SQ_INSTS_LDS']:.3e} | "
+                         f"{issue:.2f} | {lane:.2f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def summarize_trace(stats_csv: str, out_md: str, title: str, commands, notes: str = ""):
     """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
     import csv
@@ -300,6 +352,8 @@ def main():
     # offline summaries of rocprofv3 output into profiles/ (no GPU needed)
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT_MD"))
+    ap.add_argument("--summarize-valu", nargs=3, metavar=("SQ_COUNTER_CSV", "KERNEL_TRACE_CSV", "OUT_MD"))
+    ap.add_argument("--kernel", action="append", default=[], help="kernel name (substring) for --summarize-valu")
     ap.add_argument("--title", default="")
     ap.add_argument("--notes", default="")
     ap.add_argument("--command", action="append", default=[], help="profiling command recorded in the summary")
@@ -310,6 +364,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, args.title, args.command, args.notes)
+        return
+    if args.summarize_valu:
+        summarize_valu(*args.summarize_valu, args.command, args.kernel)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
