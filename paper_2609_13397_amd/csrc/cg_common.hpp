@@ -14,6 +14,21 @@ constexpr int kTile = 16;             // tile edge in pixels (one workgroup of 2
 constexpr int kTilePx = kTile * kTile;
 constexpr int kGroup = 8;             // tile group edge in tiles (64 tiles = one wave64)
 constexpr int kGroupTiles = kGroup * kGroup;
+
+// XCD-aware tile order of the render launches.  Workgroup b runs on XCD b % 8.  Tiles
+// are dealt to the XCDs in chunks of kXcdChunk consecutive tiles, round-robin, so every
+// XCD works through a spread of the image (dense and sparse regions alike), while the
+// neighbouring tiles of a chunk, which share most of their Gaussians, share one L2.
+constexpr int kXcdChunk = 16;
+// Workgroups per XCD for total_tiles tiles (a whole number of chunks); the launch has
+// 8 times as many, and workgroups mapped past the last tile exit at once.
+inline int xcd_blocks_per_xcd(int64_t total_tiles) {
+  return (int)((total_tiles + 8 * kXcdChunk - 1) / (8 * kXcdChunk)) * kXcdChunk;
+}
+__device__ __forceinline__ int xcd_tile(int b) {
+  const int x = b & 7, q = b >> 3;
+  return ((q / kXcdChunk) * 8 + x) * kXcdChunk + q % kXcdChunk;
+}
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr double kPi = 3.14159265358979323846;
 

@@ -28,7 +28,7 @@ constexpr int kGradLen = 20;  // dW[9] dmu[3] dsigma dsp2[3] drgb[3] pad (zero)
 // spilling.
 template <int FILTER, bool MARGINAL, bool GEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
-                                                    int per_xcd, Opts o, const Record* __restrict__ rec,
+                                                    Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ sorted_gid,
                                                     const uint32_t* __restrict__ sorted_slots,
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   __shared__ Record srec[64];
   __shared__ float gacc[4][64][kGradLen + 1];
   const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
+  const int t = xcd_tile(b);
   if (t >= total_tiles) return;
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
@@ -332,9 +332,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
 template <int FILTER, bool MARGINAL, bool GEER>
 static void launch_bwd_g(const cg_fwd_state* st, const float* grad_rgba, float* partial, unsigned int* mismatch,
                          hipStream_t s) {
-  const int per_xcd = (int)((st->total_tiles + 7) / 8);
-  k_render_bwd<FILTER, MARGINAL, GEER><<<dim3(per_xcd * 8), dim3(256), 0, s>>>(
-      st->dcams, st->n_views, (int)st->total_tiles, per_xcd, st->opts, st->rec, st->g.n, st->ranges, st->sorted_gid,
+  k_render_bwd<FILTER, MARGINAL, GEER><<<dim3(xcd_blocks_per_xcd(st->total_tiles) * 8), dim3(256), 0, s>>>(
+      st->dcams, st->n_views, (int)st->total_tiles, st->opts, st->rec, st->g.n, st->ranges, st->sorted_gid,
       st->sorted_slots, st->pix, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
 }
 

@@ -20,7 +20,7 @@ static_assert(kFwdBatch % 64 == 0 && kFwdBatch <= 256, "one record per thread, w
 // needed the full footprint arithmetic and those composited, into counters[0..2].
 template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
-                                                int per_xcd, Opts o, const Record* __restrict__ rec, int64_t n_gauss,
+                                                Opts o, const Record* __restrict__ rec, int64_t n_gauss,
                                                 const uint2* __restrict__ ranges,
                                                 const uint32_t* __restrict__ sorted_gid,
                                                 const float4* __restrict__ pix, float* __restrict__ out_rgba,
@@ -29,10 +29,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __shared__ Record srec[kFwdBatch];
   __shared__ unsigned int scount[3];
   uint32_t c_eval = 0, c_full = 0, c_contrib = 0;
-  // Workgroup b is dispatched to XCD b % 8: hand each XCD a contiguous band of tiles,
-  // so neighbouring tiles (which share most of their Gaussians) share one L2.
+  // XCD-aware tile order (xcd_tile)
   const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
+  const int t = xcd_tile(b);
   if (t >= total_tiles) return;
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
@@ -177,7 +176,7 @@ __global__ __launch_bounds__(256) void k_order_bounds(const DevCamera* __restric
 
 template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
 __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
-                                                    int per_xcd, Opts o, const Record* __restrict__ rec,
+                                                    Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ sorted_gid,
                                                     const float4* __restrict__ pix,
@@ -188,7 +187,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   __shared__ unsigned int scount[4];
   uint32_t c_eval = 0, c_full = 0, c_contrib = 0, c_over = 0;
   const int b = blockIdx.x;
-  const int t = (b & 7) * per_xcd + (b >> 3);
+  const int t = xcd_tile(b);
   if (t >= total_tiles) return;
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
@@ -326,20 +325,19 @@ static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, 
                            int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
                            float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
                            hipStream_t s) {
-  const int per_xcd = (total_tiles + 7) / 8;
-  const dim3 grid(per_xcd * 8), block(256);
+  const dim3 grid(xcd_blocks_per_xcd(total_tiles) * 8), block(256);
   if (o.order_mode == CG_ORDER_RAY) {
     if (o.count_pairs)
-      k_render_ray<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
+      k_render_ray<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec,
                                                                    n_gauss, ranges, sorted_gid, pix, tlo_suffix, counters);
     else
-      k_render_ray<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec,
+      k_render_ray<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec,
                                                                     n_gauss, ranges, sorted_gid, pix, tlo_suffix, counters);
   } else if (o.count_pairs) {
-    k_render<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
+    k_render<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss,
                                                              ranges, sorted_gid, pix, out_rgba, final_T, n_last, counters);
   } else {
-    k_render<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, per_xcd, o, rec, n_gauss,
+    k_render<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss,
                                                               ranges, sorted_gid, pix, out_rgba, final_T, n_last, nullptr);
   }
   return hipGetLastError();
