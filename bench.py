@@ -271,15 +271,14 @@ SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ
                "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU"]
 N_SIMD = 256 * 4          # MI355X: 256 CUs x 4 SIMDs
 CLOCK_GHZ = 2.4
-VALU_CYCLES_PER_INST = 4  # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
 
 
 def summarize_valu(sq_csv: str, trace_csv: str, out_md: str, commands, kernels) -> None:
     """VALU utilisation of the given kernels from one rocprofv3 --pmc run of SQ_COUNTERS
     (per-dispatch values) and a --kernel-trace run of the same command (per-dispatch
     durations, kernel_trace.csv), grouped by kernel and grid size (one row per workload).
-    VALU issue = VALU instructions x 4 cycles / (duration x clock x SIMDs); lane
-    utilisation = active-lane VALU cycles / (64 x wave VALU cycles)."""
+    VALU rate = wave64 VALU instructions per SIMD per cycle (duration x clock x SIMDs);
+    lane utilisation = active-lane VALU cycles / (64 x wave VALU cycles)."""
     import csv
     with open(sq_csv) as f:
         rows = list(csv.DictReader(f))
@@ -287,12 +286,13 @@ def summarize_valu(sq_csv: str, trace_csv: str, out_md: str, commands, kernels) 
         trace = list(csv.DictReader(f))
     lines = ["# VALU utilisation: " + ", ".join(kernels), "", "Commands (run from the repository root on the GPU box):", "",
              "```", *commands, "```", "",
-             f"VALU issue = SQ_INSTS_VALU x {VALU_CYCLES_PER_INST} cycles / (average duration in the kernel trace x "
-             f"{CLOCK_GHZ} GHz x {N_SIMD} SIMDs). Lane utilisation = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU). "
+             f"VALU rate = SQ_INSTS_VALU / (average duration in the kernel trace x {CLOCK_GHZ} GHz x {N_SIMD} SIMDs): "
+             "wave64 VALU instructions issued per SIMD per clock. Lane utilisation = SQ_THREAD_CYCLES_VALU / "
+             "(64 x SQ_ACTIVE_INST_VALU). "
              "Counters and durations are averaged over the dispatches of each kernel and grid size "
              "(4657152 threads: fisheye_1M; 3686400: train_1M).", "",
              "| kernel | grid (threads) | dispatches | avg duration (ms) | waves | VALU inst | SALU inst | LDS inst | "
-             "VALU issue | lane utilisation |",
+             "VALU rate (inst/SIMD/clk) | lane utilisation |",
              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for k in kernels:
         groups = {}
@@ -310,7 +310,7 @@ def summarize_valu(sq_csv: str, trace_csv: str, out_md: str, commands, kernels) 
             if not ns:
                 raise SystemExit(f"no {k} with grid {grid} in {trace_csv}")
             t = sum(ns) / len(ns) * 1e-9
-            issue = avg["SQ_INSTS_VALU"] * VALU_CYCLES_PER_INST / (t * CLOCK_GHZ * 1e9 * N_SIMD)
+            issue = avg["SQ_INSTS_VALU"] / (t * CLOCK_GHZ * 1e9 * N_SIMD)
             lane = avg["SQ_THREAD_CYCLES_VALU"] / (64.0 * avg["SQ_ACTIVE_INST_VALU"])
             lines.append(f"| `{k}` | {grid} | {len(per['SQ_INSTS_VALU'])} | {t * 1e3:.3f} | {avg['SQ_WAVES']:.0f} | "
                          f"{avg['SQ_INSTS_VALU']:.3e} | {avg['SQ_INSTS_SALU']:.3e} | {avg['SQ_INSTS_LDS']:.3e} | "

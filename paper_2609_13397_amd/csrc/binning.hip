@@ -178,4 +178,42 @@ hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const 
   return hipGetLastError();
 }
 
+// Heaviest-first tile order for the render launches: tiles bucketed by the bit length
+// of their pair count, buckets taken from the largest down, so the long tiles start
+// first and the short ones fill the end of the launch.  One workgroup.  The order
+// within a bucket follows the LDS atomics; it changes no result, since tiles are
+// rendered independently.
+constexpr int kOrderBuckets = 33;
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, int total_tiles,
+                                                     uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int t = threadIdx.x; t < total_tiles; t += blockDim.x) {
+    const uint2 r = ranges[t];
+    atomicAdd(&cnt[32 - __clz(r.y - r.x)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = kOrderBuckets - 1; k >= 0; --k) {
+      const uint32_t c = cnt[k];
+      cnt[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < total_tiles; t += blockDim.x) {
+    const uint2 r = ranges[t];
+    order[atomicAdd(&cnt[32 - __clz(r.y - r.x)], 1u)] = (uint32_t)t;
+  }
+}
+
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s) {
+  if (total_tiles == 0) return hipSuccess;
+  k_tile_order<<<dim3(1), dim3(1024), 0, s>>>(ranges, total_tiles, order);
+  return hipGetLastError();
+}
+
 }  // namespace cg

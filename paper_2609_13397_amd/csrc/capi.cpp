@@ -288,6 +288,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     uint32_t* slot_gid = st ? sc.get_n<uint32_t>(std::max<int64_t>(P, 1)) : nullptr;
     uint32_t* sorted_gid_buf = st ? sc.get_n<uint32_t>(std::max<int64_t>(P, 1)) : nullptr;
     uint2* ranges = sc.get_n<uint2>(std::max<int64_t>(total_tiles, 1));
+    uint32_t* tile_order = sc.get_n<uint32_t>(std::max<int64_t>(total_tiles, 1));
     void* sort_tmp = sc.get(radix_temp_bytes(P));
     float* final_T = st ? sc.get_n<float>(std::max<int64_t>(total_px, 1)) : nullptr;
     uint32_t* n_last = st ? sc.get_n<uint32_t>(std::max<int64_t>(total_px, 1)) : nullptr;
@@ -315,6 +316,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       ProfScope ps(ST_RANGES, s);
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
       CG_HIP(launch_tile_ranges(skeys, svals, slot_gid, P, ranges, st ? sorted_gid : nullptr, s));
+      CG_HIP(launch_tile_order(ranges, (int)total_tiles, tile_order, s));
     }
     // counters [0..2]: pair counts (count_pairs); [3]: early composites (order_mode RAY)
     const bool ray_order = o.order_mode == CG_ORDER_RAY;
@@ -331,8 +333,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     }
     {
       ProfScope ps(ST_RENDER, s);
-      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sorted_gid, pix, tlo_suffix,
-                               out_rgba, final_T, n_last, counters, s));
+      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, tile_order, sorted_gid, pix,
+                               tlo_suffix, out_rgba, final_T, n_last, counters, s));
     }
     unsigned long long host_counters[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (counters && (opts_in->count_pairs || stats)) {
@@ -367,6 +369,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       st->sorted_slots = sslots;
       st->sorted_gid = sorted_gid;
       st->ranges = ranges;
+      st->tile_order = tile_order;
       st->pix = pix;
       st->final_T = final_T;
       st->n_last = n_last;

@@ -15,20 +15,6 @@ constexpr int kTilePx = kTile * kTile;
 constexpr int kGroup = 8;             // tile group edge in tiles (64 tiles = one wave64)
 constexpr int kGroupTiles = kGroup * kGroup;
 
-// XCD-aware tile order of the render launches.  Workgroup b runs on XCD b % 8.  Tiles
-// are dealt to the XCDs in chunks of kXcdChunk consecutive tiles, round-robin, so every
-// XCD works through a spread of the image (dense and sparse regions alike), while the
-// neighbouring tiles of a chunk, which share most of their Gaussians, share one L2.
-constexpr int kXcdChunk = 16;
-// Workgroups per XCD for total_tiles tiles (a whole number of chunks); the launch has
-// 8 times as many, and workgroups mapped past the last tile exit at once.
-inline int xcd_blocks_per_xcd(int64_t total_tiles) {
-  return (int)((total_tiles + 8 * kXcdChunk - 1) / (8 * kXcdChunk)) * kXcdChunk;
-}
-__device__ __forceinline__ int xcd_tile(int b) {
-  const int x = b & 7, q = b >> 3;
-  return ((q / kXcdChunk) * 8 + x) * kXcdChunk + q % kXcdChunk;
-}
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -151,6 +137,8 @@ hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m
 hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const uint32_t* slot_gid, int64_t n,
                               uint2* ranges, uint32_t* sorted_gid, hipStream_t s);
+// order: a permutation of the tiles, heaviest (most pairs) first, for the render launches
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
 
 // sort.hip
 size_t scan_temp_bytes(int64_t n);
@@ -169,8 +157,10 @@ hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_al
 hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_tiles, const Record* rec,
                                int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* tlo_suffix,
                                hipStream_t s);
+// tile_order: the launch's tile sequence (launch_tile_order)
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix,
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order,
+                             const uint32_t* sorted_gid, const float4* pix,
                              const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
                              unsigned long long* counters, hipStream_t s);
 

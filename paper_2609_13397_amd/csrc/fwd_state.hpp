@@ -18,6 +18,7 @@ struct cg_fwd_state {
   uint32_t* sorted_slots = nullptr;   // emission slot of each sorted pair
   uint32_t* sorted_gid = nullptr;     // Gaussian of each sorted pair
   uint2* ranges = nullptr;            // per tile [start, end)
+  uint32_t* tile_order = nullptr;     // render launch order of the tiles (heaviest first)
   float4* pix = nullptr;              // per-pixel ray buffer (pixel_buf.hpp)
   float* final_T = nullptr;           // per pixel final transmittance
   uint32_t* n_last = nullptr;         // per pixel end of its walk through the tile list

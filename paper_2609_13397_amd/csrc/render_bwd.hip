@@ -30,6 +30,7 @@ template <int FILTER, bool MARGINAL, bool GEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                     Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ tile_order,
                                                     const uint32_t* __restrict__ sorted_gid,
                                                     const uint32_t* __restrict__ sorted_slots,
                                                     const float4* __restrict__ pix,
@@ -39,9 +40,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                     unsigned int* __restrict__ mismatch) {
   __shared__ Record srec[64];
   __shared__ float gacc[4][64][kGradLen + 1];
-  const int b = blockIdx.x;
-  const int t = xcd_tile(b);
-  if (t >= total_tiles) return;
+  const int t = (int)tile_order[blockIdx.x];
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -332,8 +331,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
 template <int FILTER, bool MARGINAL, bool GEER>
 static void launch_bwd_g(const cg_fwd_state* st, const float* grad_rgba, float* partial, unsigned int* mismatch,
                          hipStream_t s) {
-  k_render_bwd<FILTER, MARGINAL, GEER><<<dim3(xcd_blocks_per_xcd(st->total_tiles) * 8), dim3(256), 0, s>>>(
-      st->dcams, st->n_views, (int)st->total_tiles, st->opts, st->rec, st->g.n, st->ranges, st->sorted_gid,
+  k_render_bwd<FILTER, MARGINAL, GEER><<<dim3((unsigned)st->total_tiles), dim3(256), 0, s>>>(
+      st->dcams, st->n_views, (int)st->total_tiles, st->opts, st->rec, st->g.n, st->ranges, st->tile_order,
+      st->sorted_gid,
       st->sorted_slots, st->pix, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
 }
 

@@ -22,6 +22,7 @@ template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                 Opts o, const Record* __restrict__ rec, int64_t n_gauss,
                                                 const uint2* __restrict__ ranges,
+                                                const uint32_t* __restrict__ tile_order,
                                                 const uint32_t* __restrict__ sorted_gid,
                                                 const float4* __restrict__ pix, float* __restrict__ out_rgba,
                                                 float* __restrict__ final_T, uint32_t* __restrict__ n_last,
@@ -29,10 +30,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   __shared__ Record srec[kFwdBatch];
   __shared__ unsigned int scount[3];
   uint32_t c_eval = 0, c_full = 0, c_contrib = 0;
-  // XCD-aware tile order (xcd_tile)
-  const int b = blockIdx.x;
-  const int t = xcd_tile(b);
-  if (t >= total_tiles) return;
+  const int t = (int)tile_order[blockIdx.x];
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
   const int lane = threadIdx.x & 63;
@@ -178,6 +176,7 @@ template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
 __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                     Opts o, const Record* __restrict__ rec,
                                                     int64_t n_gauss, const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ tile_order,
                                                     const uint32_t* __restrict__ sorted_gid,
                                                     const float4* __restrict__ pix,
                                                     const float* __restrict__ tlo_suffix,
@@ -186,9 +185,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   __shared__ float slo[kFwdBatch + 1];
   __shared__ unsigned int scount[4];
   uint32_t c_eval = 0, c_full = 0, c_contrib = 0, c_over = 0;
-  const int b = blockIdx.x;
-  const int t = xcd_tile(b);
-  if (t >= total_tiles) return;
+  const int t = (int)tile_order[blockIdx.x];
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
   const int lane = threadIdx.x & 63;
@@ -322,36 +319,36 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
 
 template <int FILTER, bool MARGINAL, bool GEER>
 static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                           int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
+                           int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
                            float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
                            hipStream_t s) {
-  const dim3 grid(xcd_blocks_per_xcd(total_tiles) * 8), block(256);
+  const dim3 grid(total_tiles), block(256);
   if (o.order_mode == CG_ORDER_RAY) {
     if (o.count_pairs)
       k_render_ray<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec,
-                                                                   n_gauss, ranges, sorted_gid, pix, tlo_suffix, counters);
+                                                                   n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, counters);
     else
       k_render_ray<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec,
-                                                                    n_gauss, ranges, sorted_gid, pix, tlo_suffix, counters);
+                                                                    n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, counters);
   } else if (o.count_pairs) {
     k_render<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss,
-                                                             ranges, sorted_gid, pix, out_rgba, final_T, n_last, counters);
+                                                             ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last, counters);
   } else {
     k_render<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss,
-                                                              ranges, sorted_gid, pix, out_rgba, final_T, n_last, nullptr);
+                                                              ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last, nullptr);
   }
   return hipGetLastError();
 }
 
 template <int FILTER, bool MARGINAL>
 static hipError_t launch_fm(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                            int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
+                            int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
                             float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
                             hipStream_t s) {
   if (o.backbone == CG_BACKBONE_RAY_INTEGRAL)
-    return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix,
+    return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix,
                                             tlo_suffix, out_rgba, final_T, n_last, counters, s);
-  return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix,
+  return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,
                                            out_rgba, final_T, n_last, counters, s);
 }
 
@@ -364,24 +361,24 @@ hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_til
 }
 
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                             int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, const float4* pix,
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid, const float4* pix,
                              const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
                              unsigned long long* counters, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
   switch (o.filter_mode) {
     case CG_FILTER_CENTER_RAY:
-      return launch_fm<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix, out_rgba,
+      return launch_fm<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, out_rgba,
                                 final_T, n_last, counters, s);
     case CG_FILTER_ISOTROPIC:
-      return marginal ? launch_fm<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix,
+      return marginal ? launch_fm<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,
                                           out_rgba, final_T, n_last, counters, s)
-                      : launch_fm<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix,
+                      : launch_fm<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix,
                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
     default:
-      return marginal ? launch_fm<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix, tlo_suffix,
+      return marginal ? launch_fm<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,
                                           out_rgba, final_T, n_last, counters, s)
-                      : launch_fm<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sorted_gid, pix,
+                      : launch_fm<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix,
                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
   }
 }
