@@ -283,10 +283,15 @@ double cg_server_now(void);
 /* Per-stage GPU timing.  When enabled, every kernel launch of the library is
  * bracketed with HIP events on its stream.  cg_profile_collect synchronises on the
  * recorded events and adds their durations to per-stage totals; cg_profile_read
- * copies the totals (host arrays of length cg_profile_num_stages()) and resets them. */
+ * copies the totals (host arrays of length cg_profile_num_stages()) and resets them.
+ * cg_profile_enable(on) enables every stage (on != 0) or none; cg_profile_enable_stages
+ * enables the stages whose bit (1 << stage) is set in mask, so that a timed region can
+ * bracket only the kernels it reports (each bracket costs an event record on the
+ * stream). */
 int cg_profile_num_stages(void);
 const char* cg_profile_stage_name(int stage);
 void cg_profile_enable(int on);
+void cg_profile_enable_stages(uint32_t mask);
 cg_status cg_profile_collect(void);
 void cg_profile_read(double* total_ms /* host */, int64_t* launches /* host */);
 

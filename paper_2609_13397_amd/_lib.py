@@ -78,6 +78,7 @@ SIGNATURES = {
     "cg_profile_num_stages": (C.c_int, []),
     "cg_profile_stage_name": (C.c_char_p, [C.c_int]),
     "cg_profile_enable": (None, [C.c_int]),
+    "cg_profile_enable_stages": (None, [C.c_uint32]),
     "cg_profile_collect": (C.c_int, []),
     "cg_profile_read": (None, [_vp, _vp]),
     "cg_release_cached_memory": (C.c_int, []),

@@ -116,19 +116,27 @@ hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const 
 
 // Compositing order of the (view, Gaussian) items: key (view << 31 | float32 depth
 // key), sorted stably so that equal keys keep the Gaussian index order.
-__global__ void k_depth_items(const uint32_t* __restrict__ depth_key, int64_t n, int64_t nv, uint64_t* __restrict__ keys,
+template <class K>
+__global__ void k_depth_items(const uint32_t* __restrict__ depth_key, int64_t n, int64_t nv, K* __restrict__ keys,
                               uint32_t* __restrict__ items) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nv) return;
-  const uint64_t v = (uint64_t)(k / n);
-  keys[k] = (v << 31) | (uint64_t)depth_key[k];
+  const K v = (K)(k / n);
+  keys[k] = (v << 31) | (K)depth_key[k];
   items[k] = (uint32_t)k;
 }
 
 hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,
                               hipStream_t s) {
   if (nv == 0) return hipSuccess;
-  k_depth_items<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(depth_key, n, nv, keys, items);
+  k_depth_items<uint64_t><<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(depth_key, n, nv, keys, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_depth_items32(const uint32_t* depth_key, int64_t n, int64_t nv, uint32_t* keys, uint32_t* items,
+                                hipStream_t s) {
+  if (nv == 0) return hipSuccess;
+  k_depth_items<uint32_t><<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(depth_key, n, nv, keys, items);
   return hipGetLastError();
 }
 

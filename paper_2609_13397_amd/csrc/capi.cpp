@@ -262,8 +262,15 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       int d_alt = 0;
       {
         ProfScope ps(ST_DEPTH_SORT, s);
-        CG_HIP(launch_depth_items(depth_key, n, nv, dkeys, items, s));
-        CG_HIP(launch_radix_sort(dkeys, items, dkeys_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
+        if (31 + view_bits <= 32) {  // one or two views: 32-bit keys
+          uint32_t* k32 = reinterpret_cast<uint32_t*>(dkeys);
+          uint32_t* k32_alt = reinterpret_cast<uint32_t*>(dkeys_alt);
+          CG_HIP(launch_depth_items32(depth_key, n, nv, k32, items, s));
+          CG_HIP(launch_radix_sort32(k32, items, k32_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
+        } else {
+          CG_HIP(launch_depth_items(depth_key, n, nv, dkeys, items, s));
+          CG_HIP(launch_radix_sort(dkeys, items, dkeys_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
+        }
       }
       const uint32_t* sorted_items = d_alt ? items_alt : items;
       {

@@ -131,8 +131,12 @@ hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
                            const float4* members, const uint32_t* member_tile, const uint32_t* offsets,
                            uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, hipStream_t s);
+// compositing keys (view << 31 | float32 depth key) and item indices; the 32-bit form
+// holds up to two views
 hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,
                               hipStream_t s);
+hipError_t launch_depth_items32(const uint32_t* depth_key, int64_t n, int64_t nv, uint32_t* keys, uint32_t* items,
+                                hipStream_t s);
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
 hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const uint32_t* slot_gid, int64_t n,

@@ -138,7 +138,7 @@ struct Pending {
 };
 
 std::mutex g_prof_mu;
-bool g_prof_on = false;
+uint32_t g_prof_mask = 0;  // bit i: stage i is bracketed
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 double g_total_ms[ST_NUM];
@@ -161,14 +161,14 @@ hipEvent_t get_event() {
 }  // namespace
 
 void prof_begin(int stage, hipStream_t s) {
-  if (!g_prof_on) return;
+  if (!((g_prof_mask >> stage) & 1u)) return;
   hipEvent_t e = get_event();
   CG_HIP(hipEventRecord(e, s));
   t_open[stage] = e;
 }
 
 void prof_end(int stage, hipStream_t s) {
-  if (!g_prof_on || !t_open[stage]) return;
+  if (!t_open[stage]) return;
   hipEvent_t e = get_event();
   CG_HIP(hipEventRecord(e, s));
   std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -186,7 +186,9 @@ const char* cg_profile_stage_name(int stage) {
   return (stage >= 0 && stage < cg::ST_NUM) ? cg::kStageNames[stage] : "";
 }
 
-void cg_profile_enable(int on) { cg::g_prof_on = on != 0; }
+void cg_profile_enable(int on) { cg::g_prof_mask = on ? ~0u : 0u; }
+
+void cg_profile_enable_stages(uint32_t mask) { cg::g_prof_mask = mask; }
 
 cg_status cg_profile_collect(void) {
   std::vector<cg::Pending> pend;

@@ -266,16 +266,21 @@ def render(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None) -> torch
 
 
 class Profiler:
-    """Per-stage GPU time of the library's kernels (HIP events on their streams)."""
+    """Per-stage GPU time of the library's kernels (HIP events on their streams).
+    ``stages``: names of the stages to bracket (None: all)."""
 
-    def __init__(self):
+    def __init__(self, stages: Optional[Sequence[str]] = None):
         L = _lib.lib()
         self.names = [L.cg_profile_stage_name(i).decode() for i in range(L.cg_profile_num_stages())]
+        unknown = set(stages or []) - set(self.names)
+        if unknown:
+            raise ValueError(f"unknown profiling stages {sorted(unknown)}")
+        self.mask = 0xFFFFFFFF if stages is None else sum(1 << self.names.index(n) for n in stages)
 
     def __enter__(self):
         L = _lib.lib()
         L.cg_profile_read(None, None)
-        L.cg_profile_enable(1)
+        L.cg_profile_enable_stages(self.mask)
         return self
 
     def __exit__(self, *exc):
