@@ -163,9 +163,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 // Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt),
 // added in slot order.  20 lanes per item, one gradient component each, 3 items per
-// wave: a wave waits on the largest of 3 slot counts instead of 64, and each slot's
-// row is read as one contiguous 80-byte segment.
+// wave step: a wave waits on the largest of 3 slot counts instead of 64, and each
+// slot's row is read as one contiguous 80-byte segment.  The waves stride over the
+// item triples and load the next step's count and offset while the current step's
+// rows are in flight: the kernel is bound by memory latency, not bandwidth.
 constexpr int kReduceItemsPerWave = 64 / kGradLen;
+constexpr int kReduceBlocks = 16384;
 
 __global__ __launch_bounds__(256) void k_reduce_items(const uint32_t* __restrict__ counts,
                                                       const uint32_t* __restrict__ offsets, int64_t nv,
@@ -174,15 +177,30 @@ __global__ __launch_bounds__(256) void k_reduce_items(const uint32_t* __restrict
   const int lane = threadIdx.x & 63;
   const int sub = lane / kGradLen, q = lane - sub * kGradLen;
   if (sub >= kReduceItemsPerWave) return;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t it = wave * kReduceItemsPerWave + sub;
-  if (it >= nv) return;
-  const uint32_t cnt = counts[it];
-  const float* src = partial + (int64_t)offsets[it] * kGradLen + q;
-  float acc = 0.f;
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int64_t it = wave * kReduceItemsPerWave + sub;
+  uint32_t cnt = 0, off = 0;
+  if (it < nv) {
+    cnt = counts[it];
+    off = offsets[it];
+  }
+  for (; it < nv; wave += n_waves) {
+    const int64_t next = (wave + n_waves) * kReduceItemsPerWave + sub;
+    uint32_t ncnt = 0, noff = 0;
+    if (next < nv) {
+      ncnt = counts[next];
+      noff = offsets[next];
+    }
+    const float* src = partial + (int64_t)off * kGradLen + q;
+    float acc = 0.f;
 #pragma unroll 4
-  for (uint32_t k = 0; k < cnt; ++k) acc += src[(int64_t)k * kGradLen];
-  item_grad[it * kGradLen + q] = acc;
+    for (uint32_t k = 0; k < cnt; ++k) acc += src[(int64_t)k * kGradLen];
+    item_grad[it * kGradLen + q] = acc;
+    it = next;
+    cnt = ncnt;
+    off = noff;
+  }
 }
 
 // Preprocess backward: per Gaussian, the per-view record gradients back to the raw
@@ -379,8 +397,8 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
   {
     ProfScope ps(ST_BWD_REDUCE, s);
     const int64_t waves = (nv + kReduceItemsPerWave - 1) / kReduceItemsPerWave;
-    k_reduce_items<<<dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s>>>(st->counts, st->offsets, nv, partial,
-                                                                         item_grad);
+    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, kReduceBlocks);
+    k_reduce_items<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(st->counts, st->offsets, nv, partial, item_grad);
     CG_HIP(hipGetLastError());
   }
   {
