@@ -297,6 +297,10 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     uint2* ranges = sc.get_n<uint2>(std::max<int64_t>(total_tiles, 1));
     uint32_t* tile_order = sc.get_n<uint32_t>(std::max<int64_t>(total_tiles, 1));
     void* sort_tmp = sc.get(radix_temp_bytes(P));
+    // training: per wave, the pairs at which some pixel had alpha >= alpha_min (4 waves
+    // per tile; two words of slack so the backward can read the word after a batch)
+    const int64_t mask_words = P / 64 + 2;
+    unsigned long long* wmask = st ? sc.get_n<unsigned long long>(4 * mask_words) : nullptr;
     float* final_T = st ? sc.get_n<float>(std::max<int64_t>(total_px, 1)) : nullptr;
     uint32_t* n_last = st ? sc.get_n<uint32_t>(std::max<int64_t>(total_px, 1)) : nullptr;
 
@@ -340,8 +344,9 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     }
     {
       ProfScope ps(ST_RENDER, s);
+      if (wmask) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(wmask), 0u, 8 * mask_words, s));
       CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, tile_order, sorted_gid, pix,
-                               tlo_suffix, out_rgba, final_T, n_last, counters, s));
+                               tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, s));
     }
     unsigned long long host_counters[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (counters && (opts_in->count_pairs || stats)) {
@@ -378,6 +383,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       st->ranges = ranges;
       st->tile_order = tile_order;
       st->pix = pix;
+      st->wmask = wmask;
+      st->mask_words = mask_words;
       st->final_T = final_T;
       st->n_last = n_last;
       st->out_rgba = out_rgba;

@@ -161,11 +161,13 @@ hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_al
 hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_tiles, const Record* rec,
                                int64_t n_gauss, const uint2* ranges, const uint32_t* sorted_gid, float* tlo_suffix,
                                hipStream_t s);
-// tile_order: the launch's tile sequence (launch_tile_order)
+// tile_order: the launch's tile sequence (launch_tile_order).  wmask (training forward,
+// else NULL): 4 bitsets of mask_words 64-bit words, zeroed beforehand; bit p of bitset
+// w is set when some pixel of wave w had alpha >= alpha_min at sorted pair p.
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
                              int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order,
-                             const uint32_t* sorted_gid, const float4* pix,
-                             const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
+                             const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix, float* out_rgba,
+                             float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
                              unsigned long long* counters, hipStream_t s);
 
 // bake.hip

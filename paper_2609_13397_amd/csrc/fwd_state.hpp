@@ -20,6 +20,8 @@ struct cg_fwd_state {
   uint2* ranges = nullptr;            // per tile [start, end)
   uint32_t* tile_order = nullptr;     // render launch order of the tiles (heaviest first)
   float4* pix = nullptr;              // per-pixel ray buffer (pixel_buf.hpp)
+  unsigned long long* wmask = nullptr;  // per wave: pairs with some pixel at alpha >= alpha_min
+  int64_t mask_words = 0;             // 64-bit words per wave bitset
   float* final_T = nullptr;           // per pixel final transmittance
   uint32_t* n_last = nullptr;         // per pixel end of its walk through the tile list
   const float* out_rgba = nullptr;    // the forward output (caller-owned)

@@ -34,6 +34,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                     const uint32_t* __restrict__ sorted_gid,
                                                     const uint32_t* __restrict__ sorted_slots,
                                                     const float4* __restrict__ pix,
+                                                    const unsigned long long* __restrict__ wmask,
+                                                    int64_t mask_words,
                                                     const float* __restrict__ out_rgba,
                                                     const float* __restrict__ final_T,
                                                     const float* __restrict__ grad_rgba, float* __restrict__ partial,
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const PairPixel px = load_pair_pixel(pix, (int64_t)total_tiles * kTilePx, (int64_t)t * kTilePx + threadIdx.x);
   const bool valid = pixel_valid(px);
   const Origin org = make_origin(c);
-  const WaveCone wc = wave_cone(px, valid);
+  const unsigned long long* __restrict__ wm = wmask + (int64_t)wave * mask_words;
   const int red_idx = wave_sum20_index(lane);  // which gradient component this lane's wave sum holds
 
   // upstream gradient and forward result of this pixel
@@ -82,12 +84,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (threadIdx.x < 64 && (int)threadIdx.x < cnt) srec[threadIdx.x] = vrec[sorted_gid[base + threadIdx.x]];
     for (int k = lane; k < 64 * (kGradLen + 1); k += 64) (&gacc[wave][0][0])[k] = 0.f;
     __syncthreads();
-    if (wc.live && __ballot(!done) != 0) {
-      bool rel = false;
-      if (lane < cnt) {
-        rel = record_reaches_cone(srec[lane], wc.ax, wc.ay, wc.az, wc.rad);
-      }
-      uint64_t m = __ballot(rel);
+    if (__ballot(!done) != 0) {
+      // the pairs of this batch at which some pixel of the wave had alpha >= alpha_min in
+      // the forward: every other pair leaves every pixel's state unchanged
+      const uint32_t w0 = base >> 6, sh = base & 63u;
+      uint64_t m = wm[w0] >> sh;
+      if (sh) m |= wm[w0 + 1] << (64u - sh);
+      if (cnt < 64) m &= (1ull << cnt) - 1ull;
       while (m) {
         const int k = (int)__builtin_ctzll(m);
         m &= m - 1;
@@ -352,7 +355,7 @@ static void launch_bwd_g(const cg_fwd_state* st, const float* grad_rgba, float* 
   k_render_bwd<FILTER, MARGINAL, GEER><<<dim3((unsigned)st->total_tiles), dim3(256), 0, s>>>(
       st->dcams, st->n_views, (int)st->total_tiles, st->opts, st->rec, st->g.n, st->ranges, st->tile_order,
       st->sorted_gid,
-      st->sorted_slots, st->pix, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
+      st->sorted_slots, st->pix, st->wmask, st->mask_words, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
 }
 
 template <int FILTER, bool MARGINAL>

@@ -18,7 +18,10 @@ static_assert(kFwdBatch % 64 == 0 && kFwdBatch <= 256, "one record per thread, w
 
 // COUNT: also count, per pixel, the pairs that reached the per-pixel tests, those that
 // needed the full footprint arithmetic and those composited, into counters[0..2].
-template <int FILTER, bool MARGINAL, bool COUNT, bool GEER>
+// MASK (training forward): also set, per wave, the bit of every pair of the sorted list
+// for which some pixel of the wave had alpha >= alpha_min (it composited or terminated
+// there), in wmask[wave][pair / 64]; the backward replays only those pairs.
+template <int FILTER, bool MARGINAL, bool COUNT, bool GEER, bool MASK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render(const DevCamera* __restrict__ cams, int n_views, int total_tiles,
                                                 Opts o, const Record* __restrict__ rec, int64_t n_gauss,
                                                 const uint2* __restrict__ ranges,
@@ -26,6 +29,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                                                 const uint32_t* __restrict__ sorted_gid,
                                                 const float4* __restrict__ pix, float* __restrict__ out_rgba,
                                                 float* __restrict__ final_T, uint32_t* __restrict__ n_last,
+                                                unsigned long long* __restrict__ wmask, int64_t mask_words,
                                                 unsigned long long* __restrict__ counters) {
   __shared__ Record srec[kFwdBatch];
   __shared__ unsigned int scount[3];
@@ -41,6 +45,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const bool valid = pixel_valid(px);
   const Origin org = make_origin(c);
   const WaveCone wc = wave_cone(px, valid);
+  unsigned long long* const wm = MASK ? wmask + (int64_t)(threadIdx.x >> 6) * mask_words : nullptr;
 
   const uint2 rg = ranges[t];
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -60,9 +65,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
           rel = record_reaches_cone(srec[sub + lane], wc.ax, wc.ay, wc.az, wc.rad);
         }
         uint64_t m = __ballot(rel);
+        uint64_t hits = 0;  // MASK: bit k - sub for the pairs with some pixel at alpha >= alpha_min
         while (m) {
           const int k = sub + (int)__builtin_ctzll(m);
           m &= m - 1;
+          bool hit = false;
           if (!done) {
             float T;
             if (COUNT) ++c_eval;
@@ -70,6 +77,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
               if (COUNT) ++c_full;
               const float alpha = fminf(T, o.alpha_max);
               if (alpha >= o.alpha_min) {
+                hit = true;
                 const float test = Ttr * (1.f - alpha);
                 if (test < o.T_min) {
                   done = true;
@@ -85,7 +93,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
               }
             }
           }
+          if (MASK && __ballot(hit) != 0) hits |= 1ull << (k - sub);
           if (__ballot(!done) == 0) break;
+        }
+        if (MASK && hits != 0 && lane == 0) {  // pair base + sub is bit 0 of hits
+          const uint32_t r0 = base + (uint32_t)sub, sh = r0 & 63u;
+          atomicOr(&wm[r0 >> 6], (unsigned long long)(hits << sh));
+          if (sh != 0 && (hits >> (64u - sh)) != 0) atomicOr(&wm[(r0 >> 6) + 1], (unsigned long long)(hits >> (64u - sh)));
         }
         if (__ballot(!done) == 0) break;
       }
@@ -317,39 +331,60 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   if (threadIdx.x < 4 && scount[threadIdx.x]) atomicAdd(&counters[threadIdx.x], (unsigned long long)scount[threadIdx.x]);
 }
 
+template <int FILTER, bool MARGINAL, bool GEER, bool COUNT>
+static void launch_key(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
+                       int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid,
+                       const float4* pix, float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* wmask,
+                       int64_t mask_words, unsigned long long* counters, hipStream_t s) {
+  const dim3 grid(total_tiles), block(256);
+  if (wmask)
+    k_render<FILTER, MARGINAL, COUNT, GEER, true><<<grid, block, 0, s>>>(
+        cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last,
+        wmask, mask_words, counters);
+  else
+    k_render<FILTER, MARGINAL, COUNT, GEER, false><<<grid, block, 0, s>>>(
+        cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last,
+        nullptr, 0, counters);
+}
+
 template <int FILTER, bool MARGINAL, bool GEER>
 static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                           int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
-                           float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
-                           hipStream_t s) {
+                           int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid,
+                           const float4* pix, const float* tlo_suffix, float* out_rgba, float* final_T,
+                           uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
+                           unsigned long long* counters, hipStream_t s) {
   const dim3 grid(total_tiles), block(256);
   if (o.order_mode == CG_ORDER_RAY) {
     if (o.count_pairs)
-      k_render_ray<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec,
-                                                                   n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, counters);
+      k_render_ray<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(
+          cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, counters);
     else
-      k_render_ray<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec,
-                                                                    n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, counters);
+      k_render_ray<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(
+          cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, counters);
   } else if (o.count_pairs) {
-    k_render<FILTER, MARGINAL, true, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss,
-                                                             ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last, counters);
+    launch_key<FILTER, MARGINAL, GEER, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order,
+                                            sorted_gid, pix, out_rgba, final_T, n_last, wmask, mask_words, counters,
+                                            s);
   } else {
-    k_render<FILTER, MARGINAL, false, GEER><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss,
-                                                              ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last, nullptr);
+    launch_key<FILTER, MARGINAL, GEER, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order,
+                                             sorted_gid, pix, out_rgba, final_T, n_last, wmask, mask_words, nullptr,
+                                             s);
   }
   return hipGetLastError();
 }
 
 template <int FILTER, bool MARGINAL>
 static hipError_t launch_fm(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                            int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix,
-                            float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* counters,
-                            hipStream_t s) {
+                            int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order,
+                            const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix, float* out_rgba,
+                            float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
+                            unsigned long long* counters, hipStream_t s) {
   if (o.backbone == CG_BACKBONE_RAY_INTEGRAL)
-    return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix,
-                                            tlo_suffix, out_rgba, final_T, n_last, counters, s);
-  return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,
-                                           out_rgba, final_T, n_last, counters, s);
+    return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order,
+                                            sorted_gid, pix, tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words,
+                                            counters, s);
+  return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid,
+                                           pix, tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, s);
 }
 
 hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_tiles, const Record* rec,
@@ -361,26 +396,24 @@ hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_til
 }
 
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
-                             int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid, const float4* pix,
-                             const float* tlo_suffix, float* out_rgba, float* final_T, uint32_t* n_last,
+                             int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order,
+                             const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix, float* out_rgba,
+                             float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
                              unsigned long long* counters, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
+#define CG_FM(F, M)                                                                                                  \
+  launch_fm<F, M>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,     \
+                  out_rgba, final_T, n_last, wmask, mask_words, counters, s)
   switch (o.filter_mode) {
     case CG_FILTER_CENTER_RAY:
-      return launch_fm<0, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix, out_rgba,
-                                final_T, n_last, counters, s);
+      return CG_FM(0, false);
     case CG_FILTER_ISOTROPIC:
-      return marginal ? launch_fm<2, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,
-                                          out_rgba, final_T, n_last, counters, s)
-                      : launch_fm<2, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix,
-                                           tlo_suffix, out_rgba, final_T, n_last, counters, s);
+      return marginal ? CG_FM(2, true) : CG_FM(2, false);
     default:
-      return marginal ? launch_fm<1, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,
-                                          out_rgba, final_T, n_last, counters, s)
-                      : launch_fm<1, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix,
-                                           tlo_suffix, out_rgba, final_T, n_last, counters, s);
+      return marginal ? CG_FM(1, true) : CG_FM(1, false);
   }
+#undef CG_FM
 }
 
 }  // namespace cg
