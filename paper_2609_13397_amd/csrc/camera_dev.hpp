@@ -29,8 +29,9 @@ __device__ __forceinline__ double kb_slope(const DevCamera& c, double th) {
 // bracketed Newton then converges from it in two or three steps.  Each FP64 step
 // divides by the slope through a float32 reciprocal: its relative error (~1e-7) only
 // scales a step that is already small, and the loop runs until the step is below
-// 1e-15, so the root is the FP64 one.  A step that leaves the bracket (or is not a
-// number) is replaced by bisection.
+// 1e-15, so the root is the FP64 one.  A residual of exactly zero ends the solve (the
+// iterate is the root; a Newton step from it would sit on the bracket's end); a step
+// that leaves the bracket (or is not a number) is replaced by bisection.
 __device__ inline double kb_solve(const DevCamera& c, double thd) {
   const float k0 = (float)c.k[0], k1 = (float)c.k[1], k2 = (float)c.k[2], k3 = (float)c.k[3];
   const float tdf = (float)thd;
@@ -39,10 +40,11 @@ __device__ inline double kb_solve(const DevCamera& c, double thd) {
   for (int it = 0; it < 32; ++it) {
     const float t2 = tf * tf;
     const float f = tf * (1.f + t2 * (k0 + t2 * (k1 + t2 * (k2 + t2 * k3)))) - tdf;
+    if (f == 0.f) break;
     const float sl = 1.f + t2 * (3.f * k0 + t2 * (5.f * k1 + t2 * (7.f * k2 + t2 * 9.f * k3)));
     if (f > 0.f) hif = tf; else lof = tf;
     float nt = tf - f * __builtin_amdgcn_rcpf(sl);
-    if (!(nt > lof && nt < hif)) nt = 0.5f * (lof + hif);
+    if (!(nt >= lof && nt <= hif)) nt = 0.5f * (lof + hif);
     const bool conv = fabsf(nt - tf) < 1e-6f || hif - lof < 1e-6f;
     tf = nt;
     if (conv) break;
@@ -51,9 +53,10 @@ __device__ inline double kb_solve(const DevCamera& c, double thd) {
   double th = fmin(fmax((double)tf, 0.0), hi);
   for (int it = 0; it < 64; ++it) {
     const double f = kb_theta_d(c, th) - thd;
+    if (f == 0.0) break;
     if (f > 0.0) hi = th; else lo = th;
     double nt = th - f * (double)__builtin_amdgcn_rcpf((float)kb_slope(c, th));
-    if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
+    if (!(nt >= lo && nt <= hi)) nt = 0.5 * (lo + hi);
     const bool conv = fabs(nt - th) < 1e-15 || hi - lo < 1e-15;
     th = nt;
     if (conv) break;
