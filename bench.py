@@ -42,8 +42,8 @@ RENDER_SOURCES = ["paper_2609_13397_amd/csrc/render_fwd.hip", "paper_2609_13397_
                   "paper_2609_13397_amd/csrc/cg_common.hpp", "paper_2609_13397_amd/csrc/preprocess.hip",
                   "paper_2609_13397_amd/csrc/pixel_buf.hpp", "paper_2609_13397_amd/csrc/wave_ops.hpp",
                   "paper_2609_13397_amd/csrc/camera.hip"]
-# the anisotropic, marginal-floor, max-response variant the bench times
-TRAFFIC_KERNEL = "cg::k_render<1, true, false, false>"
+# the anisotropic, marginal-floor, max-response, inference variant the bench times
+TRAFFIC_KERNEL = "cg::k_render<1, true, false, false, false>"
 
 
 def render_source_hash() -> str:
