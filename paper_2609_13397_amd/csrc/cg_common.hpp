@@ -78,6 +78,7 @@ static_assert(sizeof(Record) == 128, "Record layout");
 // Hardware square root, reciprocal square root and reciprocal (about 1 ulp, no
 // correctly-rounded expansion): for per-pair arithmetic whose tolerance is far above
 // float32 rounding, and for conservative bounds that carry relative margins.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 

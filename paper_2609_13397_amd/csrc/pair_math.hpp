@@ -47,7 +47,6 @@ __device__ __forceinline__ PairPixel make_pair_pixel(const PixelRay& r) {
 
 __device__ __forceinline__ Origin make_origin(const DevCamera& c) { return Origin{c.o[0], c.o[1], c.o[2]}; }
 
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Intermediate quantities shared by the forward response and its derivative.
 struct PairGeom {

@@ -7,7 +7,8 @@
 namespace cg {
 
 // Tangent-cone test bounded over the cone |d - a| <= rad (a unit, rad a chord length):
-// with n = v x d, |n|_S >= |v x a|_S - sqrt(tr S) |v| rad (lambda_max(S) <= tr S) and
+// with n = v x d, |n|_S >= |v x a|_S - sqrt(lambda_max(S)) |v| rad, where S is a
+// multiple of R diag(s'^2) R^T, so lambda_max(S) = tr S max(s'^2) / sum(s'^2); and
 // |W d| <= |W a| + rad / s'_min.  False means no ray of the cone passes the per-pixel
 // test n^T S n <= |W d|^2 (and so none passes the pre-rejection it bounds).
 __device__ __forceinline__ bool tangent_cone_reaches(const Record& R, float ax, float ay, float az, float rad) {
@@ -20,7 +21,9 @@ __device__ __forceinline__ bool tangent_cone_reaches(const Record& R, float ax, 
   const float wx = W[0] * ax + W[1] * ay + W[2] * az;
   const float wy = W[3] * ax + W[4] * ay + W[5] * az;
   const float wz = W[6] * ax + W[7] * ay + W[8] * az;
-  const float lo = fast_sqrt(fmaxf(nsn, 0.f)) * 0.9999f - fast_sqrt(S[0] + S[3] + S[5]) * fast_sqrt(vv) * rad;
+  const float smax = fmaxf(R.sp2[0], fmaxf(R.sp2[1], R.sp2[2]));
+  const float lmax = (S[0] + S[3] + S[5]) * smax * fast_rcp(R.sp2[0] + R.sp2[1] + R.sp2[2]) * 1.0001f;
+  const float lo = fast_sqrt(fmaxf(nsn, 0.f)) * 0.9999f - fast_sqrt(lmax) * fast_sqrt(vv) * rad;
   const float hi = fast_sqrt(wx * wx + wy * wy + wz * wz) * 1.0001f + fast_sqrt(R.kg) * rad * 1.0001f;
   return lo <= hi;
 }
