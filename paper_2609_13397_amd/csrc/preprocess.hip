@@ -22,13 +22,19 @@ __device__ __noinline__ float depth_key_f32(float mx, float my, float mz, float 
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera* __restrict__ cams,
+// Block order: workgroup b runs on XCD b % 8.  The views of one 256-Gaussian chunk are
+// given to workgroups b, b + 8, b + 16, ... (same XCD, consecutive in dispatch order),
+// so the views after the first read the chunk's parameters (48 SH coefficients each)
+// from that XCD's L2 instead of HBM.
+__global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera* __restrict__ cams, int n_views,
                                                     const float* __restrict__ view_cmax, Opts o,
                                                     Record* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     float4* __restrict__ cone) {
-  const int v = blockIdx.y;
+  const int q8 = (int)(blockIdx.x >> 3);
+  const int v = q8 % n_views;
+  const int64_t chunk = (int64_t)(q8 / n_views) * 8 + (blockIdx.x & 7);
   const int64_t n = g.n;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = chunk * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const DevCamera& c = cams[v];
   const int64_t out = (int64_t)v * n + i;
@@ -191,8 +197,9 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
 hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,
                              const Opts& o, Record* rec, uint32_t* depth_key, float4* cone, hipStream_t s) {
   if (g.n == 0 || n_views == 0) return hipSuccess;
-  const dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)n_views);
-  k_preprocess<<<grid, dim3(256), 0, s>>>(g, cams, view_cmax, o, rec, depth_key, cone);
+  const int64_t chunks8 = (g.n + 8 * 256 - 1) / (8 * 256);  // groups of 8 chunks of 256 Gaussians
+  const dim3 grid((unsigned)(chunks8 * 8 * n_views));
+  k_preprocess<<<grid, dim3(256), 0, s>>>(g, cams, n_views, view_cmax, o, rec, depth_key, cone);
   return hipGetLastError();
 }
 
