@@ -16,6 +16,7 @@
 namespace cg {
 
 constexpr int kMaxGroupHits = 16;
+constexpr int kPhase1Unroll = 8;
 
 __device__ __forceinline__ float readlane_f(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -42,10 +43,29 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
   const int ng = c.groups_x * c.groups_y;
   const float4* __restrict__ vgroups = groups + c.group_offset;
 
-  // phase 1: overlapping groups of this lane's Gaussian
+  // phase 1: overlapping groups of this lane's Gaussian.  The group cones are loaded
+  // kPhase1Unroll at a time before any is tested: the LDS writes of the hits share the
+  // scalar loads' wait counter, so loads interleaved with them would be waited for one
+  // at a time.
   int nh = 0;
   if (__ballot(cn.w >= 0.f) != 0) {
-    for (int gi = 0; gi < ng; ++gi) {
+    int gi = 0;
+    for (; gi + kPhase1Unroll <= ng; gi += kPhase1Unroll) {
+      float4 G[kPhase1Unroll];
+#pragma unroll
+      for (int u = 0; u < kPhase1Unroll; ++u) G[u] = vgroups[gi + u];
+      bool h[kPhase1Unroll];
+#pragma unroll
+      for (int u = 0; u < kPhase1Unroll; ++u) h[u] = chords_overlap(G[u], cn.x, cn.y, cn.z, cn.w);
+#pragma unroll
+      for (int u = 0; u < kPhase1Unroll; ++u) {
+        if (h[u]) {
+          if (nh < kMaxGroupHits) hits[wave][lane][nh] = (uint16_t)(gi + u);
+          ++nh;
+        }
+      }
+    }
+    for (; gi < ng; ++gi) {
       if (chords_overlap(vgroups[gi], cn.x, cn.y, cn.z, cn.w)) {
         if (nh < kMaxGroupHits) hits[wave][lane][nh] = (uint16_t)gi;
         ++nh;
@@ -65,17 +85,10 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
     const float cw = readlane_f(cn.w, l);
     const uint32_t base = EMIT ? readlane_u(my_base, l) : 0u;
     const bool ovf = nh_l > kMaxGroupHits;
-    const int n_iter = ovf ? ng : nh_l;
     uint32_t cnt = 0;
-    for (int h = 0; h < n_iter; ++h) {
-      int gi;
-      if (ovf) {
-        gi = h;
-        if (!chords_overlap(vgroups[gi], cx, cy, cz, cw)) continue;
-      } else {
-        gi = __builtin_amdgcn_readfirstlane((int)hits[wave][l][h]);
-      }
-      const bool hit = chords_overlap(vmem[gi * kGroupTiles], cx, cy, cz, cw);
+    // one hit group: the ballot of its member-tile tests gives the pairs and their positions
+    auto group = [&](int gi, const float4& T) {
+      const bool hit = chords_overlap(T, cx, cy, cz, cw);
       const uint64_t m = __ballot(hit);
       if (EMIT && hit) {
         const uint32_t pos = base + cnt + (uint32_t)__popcll(m & __lanemask_lt());
@@ -89,6 +102,23 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
         }
       }
       cnt += (uint32_t)__popcll(m);
+    };
+    if (!ovf) {
+      // software-pipelined: the next hit group's member cones load while this one is tested
+      int gi_next = __builtin_amdgcn_readfirstlane((int)hits[wave][l][0]);
+      float4 T_next = vmem[gi_next * kGroupTiles];
+      for (int h = 0; h < nh_l; ++h) {
+        const int gi = gi_next;
+        const float4 T = T_next;
+        if (h + 1 < nh_l) {
+          gi_next = __builtin_amdgcn_readfirstlane((int)hits[wave][l][h + 1]);
+          T_next = vmem[gi_next * kGroupTiles];
+        }
+        group(gi, T);
+      }
+    } else {
+      for (int gi = 0; gi < ng; ++gi)
+        if (chords_overlap(vgroups[gi], cx, cy, cz, cw)) group(gi, vmem[gi * kGroupTiles]);
     }
     if (lane == l) my_count = cnt;
   }
