@@ -258,6 +258,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     uint32_t* offs_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
     void* dsort_tmp = sc.get(radix_temp_bytes(nv));
     uint32_t host_last[2] = {0, 0};
+    const uint32_t* sorted_items = items;
     if (nv > 0) {
       int d_alt = 0;
       {
@@ -272,7 +273,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
           CG_HIP(launch_radix_sort(dkeys, items, dkeys_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
         }
       }
-      const uint32_t* sorted_items = d_alt ? items_alt : items;
+      sorted_items = d_alt ? items_alt : items;
       {
         ProfScope ps(ST_SCAN, s);
         CG_HIP(launch_gather_u32(counts, sorted_items, nv, counts_sorted, s));
@@ -376,8 +377,9 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       st->total_px = total_px;
       st->P = P;
       st->rec = rec;
-      st->counts = counts;
-      st->offsets = offsets;
+      st->counts = counts_sorted;
+      st->offsets = offs_sorted;
+      st->sorted_items = sorted_items;
       st->sorted_slots = sslots;
       st->sorted_gid = sorted_gid;
       st->ranges = ranges;

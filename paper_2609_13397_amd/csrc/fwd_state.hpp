@@ -13,8 +13,9 @@ struct cg_fwd_state {
   cg::DevCamera* dcams = nullptr;
   int64_t total_tiles = 0, total_px = 0, P = 0;
   cg::Record* rec = nullptr;          // [views][n]
-  uint32_t* counts = nullptr;         // pairs per (view, Gaussian)
-  uint32_t* offsets = nullptr;        // first emission slot per (view, Gaussian)
+  const uint32_t* sorted_items = nullptr;  // (view, Gaussian) item at each position of the compositing order
+  uint32_t* counts = nullptr;         // pairs per position of the compositing order
+  uint32_t* offsets = nullptr;        // first emission slot per position of the compositing order
   uint32_t* sorted_slots = nullptr;   // emission slot of each sorted pair
   uint32_t* sorted_gid = nullptr;     // Gaussian of each sorted pair
   uint2* ranges = nullptr;            // per tile [start, end)

@@ -165,7 +165,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt),
-// added in slot order.  20 lanes per item, one gradient component each, 3 items per
+// added in slot order.  The items are taken in compositing order (counts, offsets
+// and items per position), whose slot ranges follow each other, so the partials are
+// read front to back.  20 lanes per item, one gradient component each, 3 items per
 // wave step: a wave waits on the largest of 3 slot counts instead of 64, and each
 // slot's row is read as one contiguous 80-byte segment.  The waves stride over the
 // item triples and load the next step's count and offset while the current step's
@@ -174,7 +176,8 @@ constexpr int kReduceItemsPerWave = 64 / kGradLen;
 constexpr int kReduceBlocks = 16384;
 
 __global__ __launch_bounds__(256) void k_reduce_items(const uint32_t* __restrict__ counts,
-                                                      const uint32_t* __restrict__ offsets, int64_t nv,
+                                                      const uint32_t* __restrict__ offsets,
+                                                      const uint32_t* __restrict__ items, int64_t nv,
                                                       const float* __restrict__ partial,
                                                       float* __restrict__ item_grad) {
   const int lane = threadIdx.x & 63;
@@ -197,9 +200,9 @@ __global__ __launch_bounds__(256) void k_reduce_items(const uint32_t* __restrict
     }
     const float* src = partial + (int64_t)off * kGradLen + q;
     float acc = 0.f;
-#pragma unroll 4
+#pragma unroll 8
     for (uint32_t k = 0; k < cnt; ++k) acc += src[(int64_t)k * kGradLen];
-    item_grad[it * kGradLen + q] = acc;
+    item_grad[(int64_t)items[it] * kGradLen + q] = acc;
     it = next;
     cnt = ncnt;
     off = noff;
@@ -401,7 +404,8 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
     ProfScope ps(ST_BWD_REDUCE, s);
     const int64_t waves = (nv + kReduceItemsPerWave - 1) / kReduceItemsPerWave;
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, kReduceBlocks);
-    k_reduce_items<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(st->counts, st->offsets, nv, partial, item_grad);
+    k_reduce_items<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(st->counts, st->offsets, st->sorted_items, nv,
+                                                                partial, item_grad);
     CG_HIP(hipGetLastError());
   }
   {
