@@ -163,7 +163,8 @@ typedef struct {
   int64_t n_pixels;         /* pixels over all views                                 */
   int64_t n_gaussian_views; /* n * n_views                                           */
   int32_t sort_bits;        /* radix-sort key width                                  */
-  int32_t reserved;
+  int32_t n_segments;       /* work items of the split tile render (see
+                               cg_set_tile_split); 0: one workgroup per tile         */
   /* filled only with opts.count_pairs (else -1):                                    */
   int64_t n_evaluated;      /* (pixel, Gaussian) pairs a pixel walked through        */
   int64_t n_full;           /* ... that passed the cheap rejection (full Eq. 9 work) */
@@ -294,6 +295,21 @@ void cg_profile_enable(int on);
 void cg_profile_enable_stages(uint32_t mask);
 cg_status cg_profile_collect(void);
 void cg_profile_read(double* total_ms /* host */, int64_t* launches /* host */);
+
+/* Split tile render.  A forward call without training state, pair counting or per-ray
+ * order whose launch has fewer than max_tiles tiles (over all views) and more than
+ * min_avg_pairs pairs per tile on average (a small view of a large scene) would leave
+ * most compute units idle while each tile's workgroup walks a long list.  Each tile's
+ * depth-ordered list is then cut into segments of seg_len pairs (0: about 4096
+ * segments in all, at least 1024 pairs each), each rendered by its own workgroup:
+ * one pass takes every segment's per-pixel transmittance product (Eq. 4's factors
+ * 1 - alpha, ending with the one that takes it below T_min), a second composites each
+ * segment from the product of the segments in front of it, and a last step sums the
+ * segments up to the one where the pixel terminated.  The image equals the
+ * one-workgroup-per-tile render up to the rounding order of those products.
+ * Arguments <= 0 restore the defaults (2048 tiles, 2048 pairs, seg_len 0).
+ * Process-wide; calls already enqueued keep the values they were issued with. */
+void cg_set_tile_split(int64_t max_tiles, int64_t min_avg_pairs, int64_t seg_len);
 
 /* Returns the library's cached scratch memory to the device. */
 cg_status cg_release_cached_memory(void);

@@ -58,7 +58,7 @@ class CgAllocator(C.Structure):
 
 class CgStats(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("n_tiles", C.c_int64), ("n_pixels", C.c_int64),
-                ("n_gaussian_views", C.c_int64), ("sort_bits", C.c_int32), ("reserved", C.c_int32),
+                ("n_gaussian_views", C.c_int64), ("sort_bits", C.c_int32), ("n_segments", C.c_int32),
                 ("n_evaluated", C.c_int64), ("n_full", C.c_int64), ("n_contrib", C.c_int64),
                 ("n_order_overflow", C.c_int64)]
 
@@ -79,6 +79,7 @@ SIGNATURES = {
     "cg_profile_stage_name": (C.c_char_p, [C.c_int]),
     "cg_profile_enable": (None, [C.c_int]),
     "cg_profile_enable_stages": (None, [C.c_uint32]),
+    "cg_set_tile_split": (None, [C.c_int64, C.c_int64, C.c_int64]),
     "cg_profile_collect": (C.c_int, []),
     "cg_profile_read": (None, [_vp, _vp]),
     "cg_release_cached_memory": (C.c_int, []),

@@ -343,11 +343,32 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       tlo_suffix = sc.get_n<float>(P);
       CG_HIP(launch_order_bounds(dcams, n_views, (int)total_tiles, rec, n, ranges, sorted_gid, tlo_suffix, s));
     }
+    // long lists on a launch with few tiles: segments of the lists on separate workgroups
+    const SplitPolicy pol = split_policy();
+    const bool split = !st && !opts_in->count_pairs && !ray_order && P > 0 && total_tiles < pol.max_tiles &&
+                       P > total_tiles * pol.min_avg_pairs;
+    SegPlan sp{};
+    if (split) {
+      int64_t L = pol.seg_len > 0 ? pol.seg_len : std::max<int64_t>(1024, (P + 4095) / 4096);
+      L = std::min<int64_t>(L, int64_t(1) << 30);
+      sp.seg_len = (uint32_t)L;
+      sp.max_segs = total_tiles + (P + L - 1) / L;
+      CG_CHECK_ARG(sp.max_segs < (int64_t(1) << 31), "too many tile segments");
+      sp.nseg = sc.get_n<uint32_t>(total_tiles);
+      sp.seg_off = sc.get_n<uint32_t>(total_tiles);
+      sp.seg_tile = sc.get_n<uint32_t>(sp.max_segs);
+      sp.seg_prod = sc.get_n<float>(sp.max_segs * kTilePx);
+      sp.seg_out = sc.get_n<float4>(sp.max_segs * kTilePx);
+      sp.scan_tmp = sc.get(scan_temp_bytes(total_tiles));
+    }
     {
       ProfScope ps(ST_RENDER, s);
       if (wmask) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(wmask), 0u, 8 * mask_words, s));
-      CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, tile_order, sorted_gid, pix,
-                               tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, s));
+      if (split)
+        CG_HIP(launch_render_fwd_split(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sp, sorted_gid, pix, s));
+      else
+        CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, tile_order, sorted_gid, pix,
+                                 tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, s));
     }
     unsigned long long host_counters[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (counters && (opts_in->count_pairs || stats)) {
@@ -365,7 +386,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       stats->n_pixels = total_px;
       stats->n_gaussian_views = nv;
       stats->sort_bits = end_bit;
-      stats->reserved = 0;
+      stats->n_segments = split ? (int32_t)sp.max_segs : 0;
     }
     if (st) {
       st->g = g;

@@ -171,6 +171,29 @@ hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles
                              float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
                              unsigned long long* counters, hipStream_t s);
 
+// Split tile render (long lists on launches with few tiles; render_fwd.hip).  Buffers:
+// nseg, seg_off: total_tiles entries; seg_tile: max_segs; seg_prod: max_segs * 256
+// floats; seg_out: max_segs * 256 float4; scan_tmp: scan_temp_bytes(total_tiles).
+// max_segs must be at least total_tiles + P / seg_len (P: pairs of the launch).
+struct SegPlan {
+  uint32_t seg_len;
+  int64_t max_segs;
+  uint32_t* nseg;
+  uint32_t* seg_off;
+  uint32_t* seg_tile;
+  float* seg_prod;
+  float4* seg_out;
+  void* scan_tmp;
+};
+hipError_t launch_render_fwd_split(const DevCamera* cams, int n_views, int total_tiles, const Opts& o,
+                                   const Record* rec, int64_t n_gauss, const uint2* ranges, const SegPlan& sp,
+                                   const uint32_t* sorted_gid, const float4* pix, hipStream_t s);
+// The thresholds of the split render (cg_set_tile_split; runtime.cpp).
+struct SplitPolicy {
+  int64_t max_tiles, min_avg_pairs, seg_len;
+};
+SplitPolicy split_policy();
+
 // bake.hip
 hipError_t launch_bake_rho2(const GaussPtrs& g, const DevCamera* cams, int n_views, float t_near, float* rho2,
                             hipStream_t s);

@@ -331,6 +331,202 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   if (threadIdx.x < 4 && scount[threadIdx.x]) atomicAdd(&counters[threadIdx.x], (unsigned long long)scount[threadIdx.x]);
 }
 
+// ---------------------------------------------------------------------------- split tiles
+// A launch with few tiles and long lists (a small view of a large scene) leaves most of
+// the GPU idle while each workgroup walks its list alone.  The lists are then cut into
+// segments of L pairs, each rendered by its own workgroup (k_seg_plan lists them:
+// nseg[t] segments per tile from seg_off[t], seg_tile[b] the tile of segment b).
+// Pass 1 takes, per pixel, the transmittance product of each segment but the last:
+// the factors (1 - alpha) of its pairs with alpha >= alpha_min, from T = 1, ending
+// with the first factor that takes the product below T_min.  Pass 2 composites each
+// segment front to back from T_in = the product of the earlier segments' factors; a
+// pixel whose T_in is below T_min terminated in an earlier segment (the product of
+// every factor before a pair is below T_min exactly when the walk terminated before
+// it).  k_seg_combine sums the segments' colours up to the one where the pixel
+// terminated.  Up to the order of the products, this is the walk of k_render.
+__global__ void k_seg_count(const uint2* __restrict__ ranges, int total_tiles, uint32_t L, uint32_t* __restrict__ nseg) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total_tiles) return;
+  const uint32_t len = ranges[t].y - ranges[t].x;
+  nseg[t] = len > L ? (len + L - 1) / L : 1u;
+}
+
+__global__ void k_seg_fill(const uint32_t* __restrict__ nseg, const uint32_t* __restrict__ seg_off, int total_tiles,
+                           uint32_t* __restrict__ seg_tile) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total_tiles) return;
+  for (uint32_t q = 0; q < nseg[t]; ++q) seg_tile[seg_off[t] + q] = (uint32_t)t;
+}
+
+template <int FILTER, bool MARGINAL, bool GEER, int PASS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render_seg(
+    const DevCamera* __restrict__ cams, int n_views, int total_tiles, Opts o, const Record* __restrict__ rec,
+    int64_t n_gauss, const uint2* __restrict__ ranges, const uint32_t* __restrict__ nseg,
+    const uint32_t* __restrict__ seg_off, const uint32_t* __restrict__ seg_tile, uint32_t L,
+    const uint32_t* __restrict__ sorted_gid, const float4* __restrict__ pix, float* __restrict__ seg_prod,
+    float4* __restrict__ seg_out) {
+  __shared__ Record srec[kFwdBatch];
+  const uint32_t n_segs = seg_off[total_tiles - 1] + nseg[total_tiles - 1];
+  const uint32_t b = blockIdx.x;
+  if (b >= n_segs) return;
+  const int t = (int)seg_tile[b];
+  const uint32_t ns = nseg[t], q = b - seg_off[t];
+  if (PASS == 1 && q + 1 == ns) return;  // no segment follows the last one
+  const int v = view_of_tile(cams, n_views, t);
+  const DevCamera& c = cams[v];
+  const int lane = threadIdx.x & 63;
+  int i, j;
+  tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
+  const bool inside = i < c.crop_w && j < c.crop_h;
+  const PairPixel px = load_pair_pixel(pix, (int64_t)total_tiles * kTilePx, (int64_t)t * kTilePx + threadIdx.x);
+  const bool valid = pixel_valid(px);
+  const Origin org = make_origin(c);
+  const WaveCone wc = wave_cone(px, valid);
+  const uint2 rg = ranges[t];
+  const uint32_t s0 = rg.x + q * L, s1 = min(s0 + L, rg.y);
+  float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !valid;
+  if (PASS == 2) {
+    for (uint32_t e = 0; e < q; ++e) Ttr *= seg_prod[(int64_t)(seg_off[t] + e) * kTilePx + threadIdx.x];
+    if (Ttr < o.T_min) done = true;  // terminated in an earlier segment
+  }
+  const Record* vrec = rec + (int64_t)v * n_gauss;
+  for (uint32_t base = s0; base < s1; base += kFwdBatch) {
+    if (__syncthreads_count(!done) == 0) break;
+    const uint32_t idx = base + threadIdx.x;
+    if ((int)threadIdx.x < kFwdBatch && idx < s1) srec[threadIdx.x] = vrec[sorted_gid[idx]];
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)kFwdBatch, s1 - base);
+    if (wc.live && __ballot(!done) != 0) {
+      for (int sub = 0; sub < cnt; sub += 64) {
+        bool rel = false;
+        if (sub + lane < cnt) rel = record_reaches_cone(srec[sub + lane], wc.ax, wc.ay, wc.az, wc.rad);
+        uint64_t m = __ballot(rel);
+        while (m) {
+          const int k = sub + (int)__builtin_ctzll(m);
+          m &= m - 1;
+          if (!done) {
+            float T;
+            if (pair_response<FILTER, MARGINAL, GEER>(srec[k], px, org, o, T)) {
+              const float alpha = fminf(T, o.alpha_max);
+              if (alpha >= o.alpha_min) {
+                const float test = Ttr * (1.f - alpha);
+                if (test < o.T_min) {
+                  done = true;
+                  if (PASS == 1) Ttr = test;  // the product includes the factor that ends it
+                } else {
+                  if (PASS == 2) {
+                    const float w = Ttr * alpha;
+                    C0 = fmaf(w, srec[k].rgb[0], C0);
+                    C1 = fmaf(w, srec[k].rgb[1], C1);
+                    C2 = fmaf(w, srec[k].rgb[2], C2);
+                  }
+                  Ttr = test;
+                }
+              }
+            }
+          }
+          if (__ballot(!done) == 0) break;
+        }
+        if (__ballot(!done) == 0) break;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t slot = (int64_t)b * kTilePx + threadIdx.x;
+  if (PASS == 1) {
+    seg_prod[slot] = Ttr;
+  } else if (ns > 1) {
+    // colour, and the transmittance at the end of the segment (or where the pixel
+    // terminated: stored as -(1 + T))
+    seg_out[slot] = make_float4(C0, C1, C2, done ? -(1.f + Ttr) : Ttr);
+  } else if (inside) {
+    float4 out;
+    out.x = C0 + Ttr * o.bg[0];
+    out.y = C1 + Ttr * o.bg[1];
+    out.z = C2 + Ttr * o.bg[2];
+    out.w = 1.f - Ttr;
+    reinterpret_cast<float4*>(c.out)[(int64_t)j * c.crop_w + i] = out;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_seg_combine(const DevCamera* __restrict__ cams, int n_views, Opts o,
+                                                     const uint32_t* __restrict__ nseg,
+                                                     const uint32_t* __restrict__ seg_off,
+                                                     const float4* __restrict__ seg_out) {
+  const int t = blockIdx.x;
+  const uint32_t ns = nseg[t];
+  if (ns <= 1) return;
+  const int v = view_of_tile(cams, n_views, t);
+  const DevCamera& c = cams[v];
+  int i, j;
+  tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
+  if (i >= c.crop_w || j >= c.crop_h) return;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+  for (uint32_t q = 0; q < ns; ++q) {
+    const float4 r = seg_out[(int64_t)(seg_off[t] + q) * kTilePx + threadIdx.x];
+    C0 += r.x;
+    C1 += r.y;
+    C2 += r.z;
+    if (r.w < 0.f) {
+      T = -r.w - 1.f;
+      break;
+    }
+    T = r.w;
+  }
+  float4 out;
+  out.x = C0 + T * o.bg[0];
+  out.y = C1 + T * o.bg[1];
+  out.z = C2 + T * o.bg[2];
+  out.w = 1.f - T;
+  reinterpret_cast<float4*>(c.out)[(int64_t)j * c.crop_w + i] = out;
+}
+
+template <int FILTER, bool MARGINAL, bool GEER>
+static void launch_seg_passes(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
+                              int64_t n_gauss, const uint2* ranges, const SegPlan& sp, const uint32_t* sorted_gid,
+                              const float4* pix, hipStream_t s) {
+  const dim3 grid((unsigned)sp.max_segs), block(256);
+  k_render_seg<FILTER, MARGINAL, GEER, 1><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss, ranges,
+                                                                 sp.nseg, sp.seg_off, sp.seg_tile, sp.seg_len,
+                                                                 sorted_gid, pix, sp.seg_prod, sp.seg_out);
+  k_render_seg<FILTER, MARGINAL, GEER, 2><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss, ranges,
+                                                                 sp.nseg, sp.seg_off, sp.seg_tile, sp.seg_len,
+                                                                 sorted_gid, pix, sp.seg_prod, sp.seg_out);
+}
+
+hipError_t launch_render_fwd_split(const DevCamera* cams, int n_views, int total_tiles, const Opts& o,
+                                   const Record* rec, int64_t n_gauss, const uint2* ranges, const SegPlan& sp,
+                                   const uint32_t* sorted_gid, const float4* pix, hipStream_t s) {
+  if (total_tiles == 0) return hipSuccess;
+  const unsigned tb = (unsigned)((total_tiles + 255) / 256);
+  k_seg_count<<<dim3(tb), dim3(256), 0, s>>>(ranges, total_tiles, sp.seg_len, sp.nseg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_exclusive_scan(sp.nseg, sp.seg_off, total_tiles, sp.scan_tmp, s);
+  if (e != hipSuccess) return e;
+  k_seg_fill<<<dim3(tb), dim3(256), 0, s>>>(sp.nseg, sp.seg_off, total_tiles, sp.seg_tile);
+  const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
+  const bool geer = o.backbone == CG_BACKBONE_RAY_INTEGRAL;
+#define CG_SEG(F, M)                                                                                               \
+  (geer ? launch_seg_passes<F, M, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sp, sorted_gid, pix, s) \
+        : launch_seg_passes<F, M, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, sp, sorted_gid, pix, s))
+  switch (o.filter_mode) {
+    case CG_FILTER_CENTER_RAY:
+      CG_SEG(0, false);
+      break;
+    case CG_FILTER_ISOTROPIC:
+      if (marginal) CG_SEG(2, true); else CG_SEG(2, false);
+      break;
+    default:
+      if (marginal) CG_SEG(1, true); else CG_SEG(1, false);
+      break;
+  }
+#undef CG_SEG
+  k_seg_combine<<<dim3((unsigned)total_tiles), dim3(256), 0, s>>>(cams, n_views, o, sp.nseg, sp.seg_off, sp.seg_out);
+  return hipGetLastError();
+}
+
 template <int FILTER, bool MARGINAL, bool GEER, bool COUNT>
 static void launch_key(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
                        int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid,

@@ -180,6 +180,34 @@ def test_empty_and_degenerate_inputs():
     check_view(imgs[1], scene, cam, O.Opts())
 
 
+def test_large_gaussians_cover_many_tile_groups():
+    """Gaussians close to the camera whose influence cones reach more than 16 of a
+    view's 8x8-tile groups: the binning lists at most 16 group hits per Gaussian and
+    tests every group of the view again for these, in the count and the emit pass.
+    A 640x480 pinhole (20 tile groups), a 533x533 KB fisheye (25) and a 683x341
+    equirect (18), floor off."""
+    torch, R = _gpu()
+    cam = synth.camera(synth.PINHOLE, 640, 480, fx=500.0, fy=500.0, cx=320.0, cy=240.0,
+                       R_c2w=np.eye(3), origin=(0.0, 0.0, -3.0))
+    scene = synth.make_scene(12, seed=71, layout="uniform", color="rgb", log_scale_mean=-1.2, log_scale_std=0.4)
+    scene["means"][:, 0] = 0.0        # 3 m in front of the pinhole
+    scene["log_scales"][:, 0] = 0.0   # 1 m: its cone covers the whole pinhole view
+    scene["opacity_logits"][0] = -1.0
+    _say("large Gaussians")
+    # a Gaussian with more pairs than 16 groups of 64 tiles hold overlaps more than 16 groups
+    _, info = gpu_render(synth.subset_scene(scene, np.arange(1)), [cam], R.RenderOpts())
+    _say(f"   one large Gaussian: {info['n_pairs']} pairs")
+    assert info["n_pairs"] > 16 * 64
+    kb, eq = synth.fisheye_cameras()
+    cams = [cam, synth.scale_camera(kb, 1 / 3), synth.scale_camera(eq, 1 / 3)]
+    for c in cams[1:]:
+        c["origin"] = (0.0, 0.0, -3.0)
+    imgs, info = gpu_render(scene, cams, R.RenderOpts())
+    _say(f"   pairs {info['n_pairs']}")
+    for img, c in zip(imgs, cams):
+        check_view(img, scene, c, O.Opts())
+
+
 def test_multiview_batch_equals_single_views():
     """A batched call renders each view exactly as a call with that view alone."""
     torch, R = _gpu()

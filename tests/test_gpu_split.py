@@ -1,0 +1,130 @@
+"""GPU parity of the split tile render: launches with few tiles and long lists cut each
+tile's depth-ordered list into segments rendered by separate workgroups, composited
+from the transmittance product of the segments in front (Eq. 4 regrouped).  The image
+must equal the one-workgroup-per-tile render up to the rounding order of those
+products, and match the FP64 oracle like any forward image."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_13397_amd import synth
+from parity import TOL_IMAGE, compare_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _render(scene, cams, opts, split):
+    """split: (max_tiles, min_avg_pairs, seg_len) for cg_set_tile_split, or None for
+    a render that never splits."""
+    import torch
+    from paper_2609_13397_amd import render as R
+    assert torch.cuda.is_available(), "no GPU"
+    if split is None:
+        R.set_tile_split(1, 1 << 40, 0)  # no launch has fewer than 1 tile: never split
+    else:
+        R.set_tile_split(*split)
+    try:
+        sc = R.Scene.from_numpy(scene)
+        rgba, info, _ = R.render_forward(sc, cams, opts)
+        torch.cuda.synchronize()
+    finally:
+        R.set_tile_split(0, 0, 0)
+    return [v.cpu().numpy().astype(np.float64) for v in R.split_views(rgba, cams)], info
+
+
+def _small_wide_scene():
+    scene = synth.make_scene(2000, seed=22, layout="clusters", color="sh3", log_scale_mean=-3.0, log_scale_std=0.6)
+    scene["means"] *= 0.3
+    kb, eq = synth.fisheye_cameras()
+    cams = [synth.scale_camera(kb, 1 / 16), synth.scale_camera(eq, 1 / 16)]
+    for c in cams:
+        c["origin"] = (0.0, -1.0, 0.3)
+    scene["rho2"] = O.bake_rho2(scene, [synth.scale_camera(c, 2.0) for c in cams]).astype(np.float32)
+    return scene, cams
+
+
+@pytest.mark.parametrize("seg_len", [64, 200, 1024])
+def test_split_render_equals_unsplit_and_oracle(seg_len):
+    from paper_2609_13397_amd import render as R
+    scene, cams = _small_wide_scene()
+    opts = R.RenderOpts(use_floor=True)
+    _say(f"split render, segments of {seg_len} pairs")
+    ref, info0 = _render(scene, cams, opts, None)
+    got, info1 = _render(scene, cams, opts, (1 << 20, 1, seg_len))
+    _say(f"   pairs {info1['n_pairs']} segments {info1['n_segments']} tiles {info1['n_tiles']}")
+    assert info0["n_segments"] == 0
+    assert info1["n_segments"] > info1["n_tiles"]  # some tile has more than one segment
+    assert info1["n_pairs"] == info0["n_pairs"]
+    oopts = O.Opts(use_floor=1)
+    for a, b, c in zip(ref, got, cams):
+        diff = np.abs(a - b)
+        _say(f"   max |split - unsplit| {diff.max():.3e}, pixels above 1e-5: {(diff.max(axis=-1) > 1e-5).sum()}")
+        # the same pairs and arithmetic; only the products of the transmittance factors
+        # are grouped per segment (pixels at a near-threshold decision may differ more)
+        assert (diff.max(axis=-1) > 1e-5).mean() < 0.002
+        refo = O.render(scene, c, oopts, mode="brute", with_alt=True)
+        nfail, worst, det = compare_image(b, refo, TOL_IMAGE)
+        _say(f"   oracle parity: fail={nfail} worst={worst:.3e} {det}")
+        assert nfail == 0, (worst, det)
+
+
+def test_split_render_options_and_batches():
+    """Every filter mode, the additive composition, the ray-integral backbone and a
+    multi-view batch take the split path and agree with the unsplit render."""
+    from paper_2609_13397_amd import render as R
+    scene, cams = _small_wide_scene()
+    cams = cams + [synth.scale_camera(cams[0], 0.5)]
+    for kw in (dict(filter_mode=0), dict(filter_mode=2, use_floor=True), dict(use_floor=True, composition=1),
+               dict(use_floor=True, backbone=1), dict(bg=(0.2, 0.3, 0.4))):
+        opts = R.RenderOpts(**kw)
+        ref, _ = _render(scene, cams, opts, None)
+        got, info = _render(scene, cams, opts, (1 << 20, 1, 128))
+        worst = max(float(np.abs(a - b).max()) for a, b in zip(ref, got))
+        frac = max(float((np.abs(a - b).max(axis=-1) > 1e-5).mean()) for a, b in zip(ref, got))
+        _say(f"   {kw}: segments {info['n_segments']} max diff {worst:.2e} frac>1e-5 {frac:.4f}")
+        assert info["n_segments"] > info["n_tiles"]
+        assert frac < 0.002 and worst < 0.05
+
+
+def test_small_view_of_large_scene_splits_by_default():
+    """A 240x135 view of the 100k-Gaussian pinhole scene has few tiles and long lists:
+    the default thresholds take the split path; its image matches the oracle."""
+    from paper_2609_13397_amd import render as R
+    scene, views = synth.pinhole_config()
+    scene["rho2"] = O.bake_rho2(scene, views).astype(np.float32)
+    cam = synth.scale_camera(views[2], 0.125)
+    opts = R.RenderOpts(use_floor=True)
+    _say("small view of the pinhole scene")
+    got, info = _render(scene, [cam], opts, (0, 0, 0))
+    _say(f"   pairs {info['n_pairs']} tiles {info['n_tiles']} segments {info['n_segments']}")
+    if info["n_pairs"] > info["n_tiles"] * 2048:
+        assert info["n_segments"] > 0
+    ref, _ = _render(scene, [cam], opts, None)
+    assert (np.abs(ref[0] - got[0]).max(axis=-1) > 1e-5).mean() < 0.002
+    refo = O.render(scene, cam, O.Opts(use_floor=1), mode="culled", with_alt=True)
+    nfail, worst, det = compare_image(got[0], refo, TOL_IMAGE)
+    _say(f"   oracle parity: fail={nfail} worst={worst:.3e} {det}")
+    assert nfail == 0, (worst, det)
+
+
+def test_training_and_counting_calls_never_split():
+    import torch
+    from paper_2609_13397_amd import render as R
+    scene, cams = _small_wide_scene()
+    R.set_tile_split(1 << 20, 1, 64)
+    try:
+        sc = R.Scene.from_numpy(scene)
+        _, info, fs = R.render_forward(sc, cams, R.RenderOpts(use_floor=True), need_state=True)
+        assert info["n_segments"] == 0
+        _, info, _ = R.render_forward(sc, cams, R.RenderOpts(use_floor=True, count_pairs=True))
+        assert info["n_segments"] == 0
+        torch.cuda.synchronize()
+    finally:
+        R.set_tile_split(0, 0, 0)
