@@ -300,8 +300,8 @@ void cg_profile_read(double* total_ms /* host */, int64_t* launches /* host */);
  * order whose launch has fewer than max_tiles tiles (over all views) and more than
  * min_avg_pairs pairs per tile on average (a small view of a large scene) would leave
  * most compute units idle while each tile's workgroup walks a long list.  Each tile's
- * depth-ordered list is then cut into segments of seg_len pairs (0: about 4096
- * segments in all, at least 1024 pairs each), each rendered by its own workgroup:
+ * depth-ordered list is then cut into segments of seg_len pairs (0: about 16384
+ * segments in all, at least 384 pairs each), each rendered by its own workgroup:
  * one pass takes every segment's per-pixel transmittance product (Eq. 4's factors
  * 1 - alpha, ending with the one that takes it below T_min), a second composites each
  * segment from the product of the segments in front of it, and a last step sums the

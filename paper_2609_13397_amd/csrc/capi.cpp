@@ -349,7 +349,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
                        P > total_tiles * pol.min_avg_pairs;
     SegPlan sp{};
     if (split) {
-      int64_t L = pol.seg_len > 0 ? pol.seg_len : std::max<int64_t>(1024, (P + 4095) / 4096);
+      int64_t L = pol.seg_len > 0 ? pol.seg_len : std::max<int64_t>(384, (P + 16383) / 16384);
       L = std::min<int64_t>(L, int64_t(1) << 30);
       sp.seg_len = (uint32_t)L;
       sp.max_segs = total_tiles + (P + L - 1) / L;

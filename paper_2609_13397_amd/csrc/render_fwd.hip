@@ -338,8 +338,9 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
 // nseg[t] segments per tile from seg_off[t], seg_tile[b] the tile of segment b).
 // Pass 1 takes, per pixel, the transmittance product of each segment but the last:
 // the factors (1 - alpha) of its pairs with alpha >= alpha_min, from T = 1, ending
-// with the first factor that takes the product below T_min.  Pass 2 composites each
-// segment front to back from T_in = the product of the earlier segments' factors; a
+// with the first factor that takes the product below T_min.  k_seg_prefix replaces
+// them, in place, by T_in = the product of the earlier segments' factors (taken left
+// to right).  Pass 2 composites each segment front to back from its T_in; a
 // pixel whose T_in is below T_min terminated in an earlier segment (the product of
 // every factor before a pair is below T_min exactly when the walk terminated before
 // it).  k_seg_combine sums the segments' colours up to the one where the pixel
@@ -386,9 +387,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const uint32_t s0 = rg.x + q * L, s1 = min(s0 + L, rg.y);
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool done = !valid;
-  if (PASS == 2) {
-    for (uint32_t e = 0; e < q; ++e) Ttr *= seg_prod[(int64_t)(seg_off[t] + e) * kTilePx + threadIdx.x];
-    if (Ttr < o.T_min) done = true;  // terminated in an earlier segment
+  if (PASS == 2 && q > 0) {
+    Ttr = seg_prod[(int64_t)b * kTilePx + threadIdx.x];  // T_in, from k_seg_prefix
+    if (Ttr < o.T_min) done = true;                       // terminated in an earlier segment
   }
   const Record* vrec = rec + (int64_t)v * n_gauss;
   for (uint32_t base = s0; base < s1; base += kFwdBatch) {
@@ -450,6 +451,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
 }
 
+// Per multi-segment tile and pixel: seg_prod[segment q] <- product of the factors of
+// segments 0 .. q - 1 (segment 0 keeps its own product, which no pass reads).
+__global__ __launch_bounds__(256) void k_seg_prefix(const uint32_t* __restrict__ nseg,
+                                                    const uint32_t* __restrict__ seg_off, float* __restrict__ seg_prod) {
+  const int t = blockIdx.x;
+  const uint32_t ns = nseg[t];
+  if (ns <= 1) return;
+  float* p = seg_prod + (int64_t)seg_off[t] * kTilePx + threadIdx.x;
+  float T = p[0];
+  for (uint32_t q = 1; q < ns; ++q) {
+    const float f = p[(int64_t)q * kTilePx];
+    p[(int64_t)q * kTilePx] = T;
+    T *= f;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_seg_combine(const DevCamera* __restrict__ cams, int n_views, Opts o,
                                                      const uint32_t* __restrict__ nseg,
                                                      const uint32_t* __restrict__ seg_off,
@@ -490,6 +507,7 @@ static void launch_seg_passes(const DevCamera* cams, int n_views, int total_tile
   k_render_seg<FILTER, MARGINAL, GEER, 1><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss, ranges,
                                                                  sp.nseg, sp.seg_off, sp.seg_tile, sp.seg_len,
                                                                  sorted_gid, pix, sp.seg_prod, sp.seg_out);
+  k_seg_prefix<<<dim3((unsigned)total_tiles), block, 0, s>>>(sp.nseg, sp.seg_off, sp.seg_prod);
   k_render_seg<FILTER, MARGINAL, GEER, 2><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss, ranges,
                                                                  sp.nseg, sp.seg_off, sp.seg_tile, sp.seg_len,
                                                                  sorted_gid, pix, sp.seg_prod, sp.seg_out);
