@@ -6,9 +6,7 @@
 // next to the requests already running (or if nothing else is running, so one
 // oversized request still makes progress), then fuses further queued requests for
 // the same scene into the same render call while they fit the view, pixel and memory
-// caps.  A request whose view alone would take the split tile render (a small view of
-// a large scene, by the scene's running pairs-per-pixel estimate) is neither fused
-// nor fused into.  Requests that arrive while others are on the device are admitted as soon as
+// caps.  Requests that arrive while others are on the device are admitted as soon as
 // a worker and memory free up; the calls of different workers overlap on the GPU.
 // The per-view-launch baseline is the same server with one worker and one view per
 // call.  The scheduler is independent of the executor, so a CPU stand-in executor
@@ -40,7 +38,6 @@ struct Request {
   double t_submit, t_admit;
   size_t est;
   int64_t px;
-  bool solo;  // its launch alone would take the split tile render: never fused
 };
 
 struct SceneEntry {
@@ -70,23 +67,14 @@ struct cg_server {
   // staging; when the estimated pairs would take the split tile render, its
   // per-segment state (tiles + pairs / 384 segments, at most tiles + 16384, of 256
   // pixels, 20 bytes each).  pairs_per_px is refreshed from completed calls.
-  // Whether a view alone would take the split tile render (few tiles, long lists), by
-  // the same pair estimate.  Such a request runs alone: fused with larger views, its
-  // launch would have too many tiles to split, and its long tile lists would hold up
-  // every view of the call.
-  bool splits_alone(const SceneEntry& sc, const cg_camera& cam) const {
-    const int64_t px = (int64_t)cam.crop_w * cam.crop_h;
-    const int64_t tiles = (int64_t)((cam.crop_w + 15) / 16) * ((cam.crop_h + 15) / 16);
-    const double pairs = sc.pairs_per_px * (double)px + 64.0 * (double)tiles;
-    const SplitPolicy pol = split_policy();
-    return tiles < pol.max_tiles && pairs > (double)tiles * (double)pol.min_avg_pairs;
-  }
-
   size_t estimate(const SceneEntry& sc, const cg_camera& cam) const {
     const int64_t px = (int64_t)cam.crop_w * cam.crop_h;
     const int64_t tiles = (int64_t)((cam.crop_w + 15) / 16) * ((cam.crop_h + 15) / 16);
     const double pairs = sc.pairs_per_px * (double)px + 64.0 * (double)tiles;
-    const double segs = splits_alone(sc, cam) ? (double)tiles + std::min(16384.0, pairs / 384.0) : 0.0;
+    const SplitPolicy pol = split_policy();
+    const double segs = (tiles < pol.max_tiles && pairs > (double)tiles * (double)pol.min_avg_pairs)
+                            ? (double)tiles + std::min(16384.0, pairs / 384.0)
+                            : 0.0;
     return (size_t)(sc.g.n * 192 + pairs * 24.0 + (double)tiles * (48.0 + 256.0 * 64.0) + (double)px * 8.0 + (1 << 20) +
                     segs * 256.0 * 20.0);
   }
@@ -144,8 +132,8 @@ struct cg_server {
         batch.push_back(head);
         est_total = head.est;
         px_total = head.px;
-        for (auto it = queue.begin(); !head.solo && it != queue.end() && (int)batch.size() < cfg.max_batch_views;) {
-          if (it->scene == head.scene && !it->solo && px_total + it->px <= cfg.max_batch_pixels &&
+        for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < cfg.max_batch_views;) {
+          if (it->scene == head.scene && px_total + it->px <= cfg.max_batch_pixels &&
               reserved + est_total + it->est <= cfg.hbm_budget_bytes) {
             est_total += it->est;
             px_total += it->px;
@@ -261,7 +249,6 @@ cg_status cg_server_submit(cg_server* s, int32_t scene, const cg_camera* cam, fl
       r.t_admit = 0.0;
       r.px = px;
       r.est = s->estimate(s->scenes[scene], *cam);
-      r.solo = s->splits_alone(s->scenes[scene], *cam);
       s->queue.push_back(r);
       if (request_id) *request_id = r.id;
     }

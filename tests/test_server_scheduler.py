@@ -73,25 +73,6 @@ def test_requests_queued_behind_a_running_call_are_fused():
     s.close()
 
 
-def test_views_that_split_alone_are_never_fused():
-    """A view whose launch alone would take the split tile render (few tiles and long
-    lists by the scene's pair estimate) runs alone: fused with others, the launch
-    could have too many tiles to split.  Thresholds forced so that every view splits."""
-    s = _server(n_workers=1, max_batch_views=4)
-    g, o, keep = _fake_scene()
-    sid = s.add_scene(g, o, keep)
-    _lib.lib().cg_set_tile_split(1 << 20, 1, 0)
-    try:
-        for _ in range(9):
-            s.submit(sid, _cam(), 1)
-        done = _collect(s, 9)
-    finally:
-        _lib.lib().cg_set_tile_split(0, 0, 0)
-    assert all(c.batch_views == 1 and c.status == 0 for c in done)
-    assert s.stats()["batches"] == 9
-    s.close()
-
-
 def test_batches_never_mix_scenes_and_respect_pixel_cap():
     s = _server(n_workers=1, max_batch_views=8, max_batch_pixels=64 * 48 * 3)
     g, o, keep = _fake_scene()
