@@ -24,12 +24,13 @@ def _say(*a):
 
 
 def _bench_scene(torch, R):
+    """fisheye_1M with rho^2 baked by the oracle from the 8 orbit views (Eq. 11), so
+    that every input the oracle sees comes from the generator or the oracle."""
     scene_np, cams = synth.fisheye_config()
-    scene = R.Scene.from_numpy(scene_np)
-    scene.rho2 = R.bake_rho2(scene, synth.orbit_views(), 0.2)
-    torch.cuda.synchronize()
     scene_np = dict(scene_np)
-    scene_np["rho2"] = scene.rho2.cpu().numpy()
+    scene_np["rho2"] = O.bake_rho2(scene_np, synth.orbit_views(), 0.2).astype(np.float32)
+    scene = R.Scene.from_numpy(scene_np)
+    torch.cuda.synchronize()
     return scene_np, scene, cams
 
 
@@ -59,11 +60,10 @@ def test_pinhole_config_full_resolution_sampled_rows():
     import torch
     from paper_2609_13397_amd import render as R
     scene_np, views_cams = synth.pinhole_config()
-    scene = R.Scene.from_numpy(scene_np)
-    scene.rho2 = R.bake_rho2(scene, views_cams, 0.2)
-    torch.cuda.synchronize()
     scene_np = dict(scene_np)
-    scene_np["rho2"] = scene.rho2.cpu().numpy()
+    scene_np["rho2"] = O.bake_rho2(scene_np, views_cams, 0.2).astype(np.float32)
+    scene = R.Scene.from_numpy(scene_np)
+    torch.cuda.synchronize()
     _say("pinhole 1080p x 8 views")
     rgba, info, _ = R.render_forward(scene, views_cams, R.RenderOpts(use_floor=True))
     torch.cuda.synchronize()

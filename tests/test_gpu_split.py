@@ -114,6 +114,32 @@ def test_small_view_of_large_scene_splits_by_default():
     assert nfail == 0, (worst, det)
 
 
+def test_small_view_of_serving_scene_split_sampled_rows():
+    """The 500k-Gaussian serving scene in a 256x128 equirect view (1/8 scale): about 1.7M
+    pairs over 128 tiles, so the default thresholds split the lists into segments and
+    pixels terminate across segment boundaries.  Sampled rows (crops of the same
+    camera) match the oracle, with rho^2 baked by the oracle."""
+    import torch
+    from paper_2609_13397_amd import render as R
+    scene = synth.make_scene(500_000, seed=51, layout="clusters", color="sh3", log_scale_mean=-4.0,
+                             log_scale_std=0.7)
+    scene["rho2"] = O.bake_rho2(scene, synth.orbit_views(), 0.2).astype(np.float32)
+    cam = synth.scale_camera(synth.serving_base_cameras()[2], 0.125)
+    opts = R.RenderOpts(use_floor=True)
+    _say("serving scene, 1/8 equirect")
+    got, info = _render(scene, [cam], opts, (0, 0, 0))
+    _say(f"   pairs {info['n_pairs']} tiles {info['n_tiles']} segments {info['n_segments']}")
+    assert info["n_segments"] > info["n_tiles"]
+    w = cam["crop"][2]
+    for row in (10, 64, 100):
+        c = synth.with_crop(cam, 0, row, w, 1)
+        ref = O.render(scene, c, O.Opts(use_floor=1), mode="culled", with_alt=True)
+        nfail, worst, det = compare_image(got[0][row:row + 1], ref, TOL_IMAGE)
+        _say(f"   row {row}: fail={nfail} worst={worst:.2e} amb={det['n_ambiguous']}")
+        assert nfail == 0, det
+    torch.cuda.synchronize()
+
+
 def test_training_and_counting_calls_never_split():
     import torch
     from paper_2609_13397_amd import render as R
