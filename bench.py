@@ -206,16 +206,17 @@ def serving_bench(torch, R, synth, device, n_requests=200, levels=(0.25, 0.5, 0.
     return out
 
 
-def cpu_baseline(scene_np, scene_rho2, cams, opts_kw, rows=16):
+def cpu_baseline(scene_np, bake_cams, cams, opts_kw, rows=16):
     """The FP64 oracle (culled mode) on a band of `rows` rows through the middle of each
-    view, all host threads."""
+    view, all host threads.  rho^2 is baked by the oracle (Eq. 11) from `bake_cams`, the
+    views the GPU bake uses, before the timed region."""
     import numpy as np
 
     from oracle import oracle as O
     from paper_2609_13397_amd import synth
 
     sc = dict(scene_np)
-    sc["rho2"] = scene_rho2.astype(np.float32)
+    sc["rho2"] = O.bake_rho2(sc, bake_cams, 0.2).astype(np.float32)
     opts = O.Opts(**opts_kw)
     threads = os.cpu_count() or 1
     px = 0
@@ -471,7 +472,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(scene_np, scene.rho2.cpu().numpy(), cams,
+        cpu = cpu_baseline(scene_np, synth.orbit_views(), cams,
                            dict(filter_mode=1, use_floor=1), rows=args.cpu_rows)
 
     line = {
