@@ -203,6 +203,29 @@ def serving_bench(torch, R, synth, device, n_requests=200, levels=(0.25, 0.5, 0.
     srv.close()
     out["batched_saturation_rps"] = len(trace) / bsat.wall_s
     out["batched_saturation_mpix_per_s"] = bsat.summary()["mpix_per_s"]
+    # a small view of the largest scene, whole forward call: the split tile render
+    # against one workgroup per tile (cg_set_tile_split forcing the latter)
+    small_cam = synth.scale_camera(synth.serving_base_cameras()[2], 0.125)
+    ropts = R.RenderOpts(use_floor=True)
+    small = {"workload": "3M-Gaussian serving scene, equirect 256x128 (1/8 scale)"}
+    for name, thresholds in (("split", (0, 0, 0)), ("one_workgroup_per_tile", (1, 1 << 40, 0))):
+        R.set_tile_split(*thresholds)
+        try:
+            for _ in range(2):
+                R.render_forward(scenes[2], [small_cam], ropts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                _, sinfo, _ = R.render_forward(scenes[2], [small_cam], ropts)
+            torch.cuda.synchronize()
+            small[name + "_ms"] = (time.perf_counter() - t0) / 5 * 1e3
+            small[name + "_segments"] = sinfo["n_segments"]
+        finally:
+            R.set_tile_split(0, 0, 0)
+    small["pairs"] = sinfo["n_pairs"]
+    print(f"bench: small view of the 3M scene: split {small['split_ms']:.2f} ms, one workgroup per tile "
+          f"{small['one_workgroup_per_tile_ms']:.2f} ms", file=sys.stderr, flush=True)
+    out["small_view"] = small
     return out
 
 

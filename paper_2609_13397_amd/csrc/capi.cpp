@@ -174,40 +174,6 @@ int bits_for(int64_t v) {
   return b;
 }
 
-// A second stream of the calling thread (default priority) with two events, for work
-// of a forward call that can overlap its main stream: created on first use per device,
-// kept until the process ends.  Null (no overlap) if creation fails.
-struct AuxStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  int device = -1;
-};
-
-AuxStream* aux_stream() {
-  thread_local AuxStream a;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  if (a.s && a.device == dev) return &a;
-  AuxStream b;
-  if (hipStreamCreateWithFlags(&b.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-  if (hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b.join, hipEventDisableTiming) != hipSuccess)
-    return nullptr;
-  b.device = dev;
-  a = b;  // a stream of a previous device is left to the process's end
-  return &a;
-}
-
-// Until the main stream has been made to wait for the second stream's work, unwinding
-// (a failed launch) waits for that work before the scratch blocks it uses are freed.
-struct AuxJoin {
-  AuxStream* aux = nullptr;
-  bool joined = false;
-  ~AuxJoin() {
-    if (aux && !joined) (void)hipStreamSynchronize(aux->s);
-  }
-};
-
 }  // namespace
 
 // ---------------------------------------------------------------------------- forward
@@ -278,9 +244,11 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       ProfScope ps(ST_PREPROCESS, s);
       CG_HIP(launch_preprocess(g, dcams, n_views, view_cmax, o, rec, depth_key, cone, s));
     }
-    // compositing order of the (view, Gaussian) items (a second stream: the depth sort's
-    // short passes leave most of the GPU to the bin count, which needs only the cones),
-    // then pair offsets in that order
+    {
+      ProfScope ps(ST_BIN_COUNT, s);
+      CG_HIP(launch_bin_count(n, n_views, dcams, cone, groups, members, counts, s));
+    }
+    // compositing order of the (view, Gaussian) items, then pair offsets in that order
     const int view_bits = bits_for(std::max(n_views - 1, 1));
     uint64_t* dkeys = sc.get_n<uint64_t>(std::max<int64_t>(nv, 1));
     uint64_t* dkeys_alt = sc.get_n<uint64_t>(std::max<int64_t>(nv, 1));
@@ -289,39 +257,22 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     uint32_t* counts_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
     uint32_t* offs_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
     void* dsort_tmp = sc.get(radix_temp_bytes(nv));
-    int d_alt = 0;
-    AuxStream* aux = nv > 0 ? aux_stream() : nullptr;
-    const hipStream_t s_sort = aux ? aux->s : s;
-    AuxJoin aux_join;
-    if (aux) {
-      CG_HIP(hipEventRecord(aux->fork, s));
-      aux_join.aux = aux;
-      CG_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
-    }
-    if (nv > 0) {
-      ProfScope ps(ST_DEPTH_SORT, s_sort);
-      if (31 + view_bits <= 32) {  // one or two views: 32-bit keys
-        uint32_t* k32 = reinterpret_cast<uint32_t*>(dkeys);
-        uint32_t* k32_alt = reinterpret_cast<uint32_t*>(dkeys_alt);
-        CG_HIP(launch_depth_items32(depth_key, n, nv, k32, items, s_sort));
-        CG_HIP(launch_radix_sort32(k32, items, k32_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s_sort));
-      } else {
-        CG_HIP(launch_depth_items(depth_key, n, nv, dkeys, items, s_sort));
-        CG_HIP(launch_radix_sort(dkeys, items, dkeys_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s_sort));
-      }
-    }
-    if (aux) CG_HIP(hipEventRecord(aux->join, aux->s));
-    {
-      ProfScope ps(ST_BIN_COUNT, s);
-      CG_HIP(launch_bin_count(n, n_views, dcams, cone, groups, members, counts, s));
-    }
-    if (aux) {
-      CG_HIP(hipStreamWaitEvent(s, aux->join, 0));
-      aux_join.joined = true;
-    }
     uint32_t host_last[2] = {0, 0};
     const uint32_t* sorted_items = items;
     if (nv > 0) {
+      int d_alt = 0;
+      {
+        ProfScope ps(ST_DEPTH_SORT, s);
+        if (31 + view_bits <= 32) {  // one or two views: 32-bit keys
+          uint32_t* k32 = reinterpret_cast<uint32_t*>(dkeys);
+          uint32_t* k32_alt = reinterpret_cast<uint32_t*>(dkeys_alt);
+          CG_HIP(launch_depth_items32(depth_key, n, nv, k32, items, s));
+          CG_HIP(launch_radix_sort32(k32, items, k32_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
+        } else {
+          CG_HIP(launch_depth_items(depth_key, n, nv, dkeys, items, s));
+          CG_HIP(launch_radix_sort(dkeys, items, dkeys_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
+        }
+      }
       sorted_items = d_alt ? items_alt : items;
       {
         ProfScope ps(ST_SCAN, s);
