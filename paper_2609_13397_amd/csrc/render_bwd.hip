@@ -56,19 +56,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int red_idx = wave_sum20_index(lane);  // which gradient component this lane's wave sum holds
 
   // upstream gradient and forward result of this pixel
-  float G0 = 0.f, G1 = 0.f, G2 = 0.f, Ga = 0.f, Tfin = 1.f, Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f;
+  // Fo: the forward output, C_fin + T_fin bg, which is all dL/dalpha needs of C_fin and
+  // the background (S_k + T_fin bg = Fo - C_{<=k})
+  // GaT: the upstream alpha gradient times T_fin, the only form dL/dalpha uses
+  float G0 = 0.f, G1 = 0.f, G2 = 0.f, GaT = 0.f, Tfin = 1.f, Fo0 = 0.f, Fo1 = 0.f, Fo2 = 0.f;
   int64_t p = 0;
   if (inside) {
     p = c.px_offset + (int64_t)j * c.crop_w + i;
     const float4 gr = reinterpret_cast<const float4*>(grad_rgba)[p];
     const float4 fo = reinterpret_cast<const float4*>(c.out)[(int64_t)j * c.crop_w + i];
-    G0 = gr.x; G1 = gr.y; G2 = gr.z; Ga = gr.w;
+    G0 = gr.x; G1 = gr.y; G2 = gr.z;
     Tfin = final_T[p];
-    Cf0 = fo.x - Tfin * o.bg[0];
-    Cf1 = fo.y - Tfin * o.bg[1];
-    Cf2 = fo.z - Tfin * o.bg[2];
+    GaT = gr.w * Tfin;
+    Fo0 = fo.x;
+    Fo1 = fo.y;
+    Fo2 = fo.z;
   }
-  const float back0 = Tfin * o.bg[0], back1 = Tfin * o.bg[1], back2 = Tfin * o.bg[2];
 
   const uint2 rg = ranges[t];
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -118,12 +121,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 C1 = fmaf(w, R.rgb[1], C1);
                 C2 = fmaf(w, R.rgb[2], C2);
                 const float inv1 = fast_rcp(1.f - alpha);
-                // colour behind this pair (excluding the background term)
-                const float S0 = Cf0 - C0, S1 = Cf1 - C1, S2 = Cf2 - C2;
-                float dalpha = Ga * Tfin * inv1;
-                dalpha += G0 * (R.rgb[0] * Ttr - (S0 + back0) * inv1);
-                dalpha += G1 * (R.rgb[1] * Ttr - (S1 + back1) * inv1);
-                dalpha += G2 * (R.rgb[2] * Ttr - (S2 + back2) * inv1);
+                // colour behind this pair plus the background it lets through
+                const float B0 = Fo0 - C0, B1 = Fo1 - C1, B2 = Fo2 - C2;
+                float dalpha = GaT * inv1;
+                dalpha += G0 * (R.rgb[0] * Ttr - B0 * inv1);
+                dalpha += G1 * (R.rgb[1] * Ttr - B1 * inv1);
+                dalpha += G2 * (R.rgb[2] * Ttr - B2 * inv1);
                 gv[16] = G0 * w;
                 gv[17] = G1 * w;
                 gv[18] = G2 * w;
