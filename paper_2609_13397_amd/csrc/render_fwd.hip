@@ -10,10 +10,12 @@
 namespace cg {
 
 // Records staged per batch (128 B each, loaded by the first kFwdBatch threads).  With
-// 16 KiB of LDS per workgroup and at most 64 VGPRs (amdgpu_waves_per_eu(8) on the
+// 8 KiB of LDS per workgroup and at most 64 VGPRs (amdgpu_waves_per_eu(8) on the
 // kernel), eight waves per SIMD stay resident: the loop is VALU-bound with long LDS
-// and FP64 latencies, which more resident waves hide.
-constexpr int kFwdBatch = 128;
+// and FP64 latencies, which more resident waves hide.  One wave's worth of records per
+// batch: the workgroup checks for termination and waits for its staging once per
+// batch, so short batches stop sooner after the last pixel terminates.
+constexpr int kFwdBatch = 64;
 static_assert(kFwdBatch % 64 == 0 && kFwdBatch <= 256, "one record per thread, whole waves");
 
 // COUNT: also count, per pixel, the pairs that reached the per-pixel tests, those that
