@@ -75,6 +75,20 @@ struct alignas(16) Record {
 };
 static_assert(sizeof(Record) == 128, "Record layout");
 
+// Stages the records of pairs first .. first + count - 1 of a sorted tile list into
+// srec[0 .. count) with four threads of a 256-thread workgroup per record, 32 bytes
+// each (count <= 64): a wave's loads then cover 16 whole records at once.
+__device__ __forceinline__ void stage_records(Record* srec, const Record* __restrict__ vrec,
+                                              const uint32_t* __restrict__ sorted_gid, uint32_t first, int count) {
+  const int r = (int)(threadIdx.x >> 2), part = (int)(threadIdx.x & 3u);
+  if (r < count) {
+    const float4* src = reinterpret_cast<const float4*>(vrec + sorted_gid[first + (uint32_t)r]) + 2 * part;
+    float4* dst = reinterpret_cast<float4*>(srec + r) + 2 * part;
+    dst[0] = src[0];
+    dst[1] = src[1];
+  }
+}
+
 // Hardware square root, reciprocal square root and reciprocal (about 1 ulp, no
 // correctly-rounded expansion): for per-pair arithmetic whose tolerance is far above
 // float32 rounding, and for conservative bounds that carry relative margins.

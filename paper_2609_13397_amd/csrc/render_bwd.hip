@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       break;
     }
     const int cnt = (int)min(64u, rg.y - base);
-    if (threadIdx.x < 64 && (int)threadIdx.x < cnt) srec[threadIdx.x] = vrec[sorted_gid[base + threadIdx.x]];
+    stage_records(srec, vrec, sorted_gid, base, cnt);
     for (int k = lane; k < 64 * (kGradLen + 1); k += 64) (&gacc[wave][0][0])[k] = 0.f;
     __syncthreads();
     if (__ballot(!done) != 0) {

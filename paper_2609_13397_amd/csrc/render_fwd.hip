@@ -16,7 +16,7 @@ namespace cg {
 // batch: the workgroup checks for termination and waits for its staging once per
 // batch, so short batches stop sooner after the last pixel terminates.
 constexpr int kFwdBatch = 64;
-static_assert(kFwdBatch % 64 == 0 && kFwdBatch <= 256, "one record per thread, whole waves");
+static_assert(kFwdBatch == 64, "one wave of records per batch, staged by stage_records (at most 64)");
 
 // COUNT: also count, per pixel, the pairs that reached the per-pixel tests, those that
 // needed the full footprint arithmetic and those composited, into counters[0..2].
@@ -56,10 +56,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const Record* vrec = rec + (int64_t)v * n_gauss;
   for (uint32_t base = rg.x; base < rg.y; base += kFwdBatch) {
     if (__syncthreads_count(!done) == 0) break;
-    const uint32_t idx = base + threadIdx.x;
-    if ((int)threadIdx.x < kFwdBatch && idx < rg.y) srec[threadIdx.x] = vrec[sorted_gid[idx]];
-    __syncthreads();
     const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - base);
+    stage_records(srec, vrec, sorted_gid, base, cnt);
+    __syncthreads();
     if (wc.live && __ballot(!done) != 0) {
       for (int sub = 0; sub < cnt; sub += 64) {
         bool rel = false;
@@ -262,7 +261,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t idx = base + threadIdx.x;
     const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - base);
-    if ((int)threadIdx.x < kFwdBatch && idx < rg.y) srec[threadIdx.x] = vrec[sorted_gid[idx]];
+    stage_records(srec, vrec, sorted_gid, base, cnt);
     if ((int)threadIdx.x <= cnt) slo[threadIdx.x] = idx < rg.y ? tlo_suffix[idx] : INFINITY;
     __syncthreads();
     if (wc.live && __ballot(!done) != 0) {
@@ -396,10 +395,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const Record* vrec = rec + (int64_t)v * n_gauss;
   for (uint32_t base = s0; base < s1; base += kFwdBatch) {
     if (__syncthreads_count(!done) == 0) break;
-    const uint32_t idx = base + threadIdx.x;
-    if ((int)threadIdx.x < kFwdBatch && idx < s1) srec[threadIdx.x] = vrec[sorted_gid[idx]];
-    __syncthreads();
     const int cnt = (int)min((uint32_t)kFwdBatch, s1 - base);
+    stage_records(srec, vrec, sorted_gid, base, cnt);
+    __syncthreads();
     if (wc.live && __ballot(!done) != 0) {
       for (int sub = 0; sub < cnt; sub += 64) {
         bool rel = false;
