@@ -76,16 +76,19 @@ struct alignas(16) Record {
 static_assert(sizeof(Record) == 128, "Record layout");
 
 // Stages the records of pairs first .. first + count - 1 of a sorted tile list into
-// srec[0 .. count) with four threads of a 256-thread workgroup per record, 32 bytes
-// each (count <= 64): a wave's loads then cover 16 whole records at once.
+// srec[0 .. count) with TPR threads of a 256-thread workgroup per record, 128 / TPR
+// bytes each (count <= 256 / TPR): a wave's loads cover 64 / TPR whole records at once.
+template <int TPR = 4>
 __device__ __forceinline__ void stage_records(Record* srec, const Record* __restrict__ vrec,
                                               const uint32_t* __restrict__ sorted_gid, uint32_t first, int count) {
-  const int r = (int)(threadIdx.x >> 2), part = (int)(threadIdx.x & 3u);
+  static_assert(TPR == 2 || TPR == 4, "8 or 4 float4 per record and thread");
+  constexpr int kVec = 8 / TPR;
+  const int r = (int)(threadIdx.x / TPR), part = (int)(threadIdx.x % TPR);
   if (r < count) {
-    const float4* src = reinterpret_cast<const float4*>(vrec + sorted_gid[first + (uint32_t)r]) + 2 * part;
-    float4* dst = reinterpret_cast<float4*>(srec + r) + 2 * part;
-    dst[0] = src[0];
-    dst[1] = src[1];
+    const float4* src = reinterpret_cast<const float4*>(vrec + sorted_gid[first + (uint32_t)r]) + kVec * part;
+    float4* dst = reinterpret_cast<float4*>(srec + r) + kVec * part;
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) dst[k] = src[k];
   }
 }
 

@@ -139,6 +139,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // wait in a per-pixel buffer in registers; when it is full, its smallest t* is
 // composited early (counted: the order is exact when no pixel overflowed).
 constexpr int kRayBuf = 16;
+// Records staged per batch of the per-ray-order kernel (one thread per record).
+constexpr int kRayBatch = 128;
 
 // Lower bound of t* over the pairs record R can form: pair_cheap admits only D <=
 // D_max (the tangent-cone test; D_max^2 = sum s'^2 / (tr S prod s'^2) from S =
@@ -196,8 +198,8 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
                                                     const float4* __restrict__ pix,
                                                     const float* __restrict__ tlo_suffix,
                                                     unsigned long long* __restrict__ counters) {
-  __shared__ Record srec[kFwdBatch];
-  __shared__ float slo[kFwdBatch + 1];
+  __shared__ Record srec[kRayBatch];
+  __shared__ float slo[kRayBatch + 1];
   __shared__ unsigned int scount[4];
   uint32_t c_eval = 0, c_full = 0, c_contrib = 0, c_over = 0;
   const int t = (int)tile_order[blockIdx.x];
@@ -257,11 +259,13 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   };
 
   const uint2 rg = ranges[t];
-  for (uint32_t base = rg.x; base < rg.y; base += kFwdBatch) {
+  for (uint32_t base = rg.x; base < rg.y; base += kRayBatch) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t idx = base + threadIdx.x;
-    const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - base);
-    stage_records(srec, vrec, sorted_gid, base, cnt);
+    const int cnt = (int)min((uint32_t)kRayBatch, rg.y - base);
+    // one thread per record: this kernel's pending buffers leave no registers for the
+    // wider copies of stage_records (it would drop from 3 to 2 waves per SIMD)
+    if ((int)threadIdx.x < cnt) srec[threadIdx.x] = vrec[sorted_gid[idx]];
     if ((int)threadIdx.x <= cnt) slo[threadIdx.x] = idx < rg.y ? tlo_suffix[idx] : INFINITY;
     __syncthreads();
     if (wc.live && __ballot(!done) != 0) {
