@@ -42,6 +42,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                     unsigned int* __restrict__ mismatch) {
   __shared__ Record srec[64];
   __shared__ float gacc[4][64][kGradLen + 1];
+  // per-pixel constants read only where a pair contributes, kept in LDS (each thread its
+  // own slot) instead of registers: at the 128-VGPR cap they would otherwise spill
+  __shared__ float4 s_up[256], s_fo[256];
   const int t = (int)tile_order[blockIdx.x];
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
@@ -59,18 +62,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // Fo: the forward output, C_fin + T_fin bg, which is all dL/dalpha needs of C_fin and
   // the background (S_k + T_fin bg = Fo - C_{<=k})
   // GaT: the upstream alpha gradient times T_fin, the only form dL/dalpha uses
-  float G0 = 0.f, G1 = 0.f, G2 = 0.f, GaT = 0.f, Tfin = 1.f, Fo0 = 0.f, Fo1 = 0.f, Fo2 = 0.f;
+  // s_up: (G_r, G_g, G_b, G_a T_fin), s_fo: (Fo_r, Fo_g, Fo_b, unused)
   int64_t p = 0;
-  if (inside) {
-    p = c.px_offset + (int64_t)j * c.crop_w + i;
-    const float4 gr = reinterpret_cast<const float4*>(grad_rgba)[p];
-    const float4 fo = reinterpret_cast<const float4*>(c.out)[(int64_t)j * c.crop_w + i];
-    G0 = gr.x; G1 = gr.y; G2 = gr.z;
-    Tfin = final_T[p];
-    GaT = gr.w * Tfin;
-    Fo0 = fo.x;
-    Fo1 = fo.y;
-    Fo2 = fo.z;
+  {
+    float4 up = make_float4(0.f, 0.f, 0.f, 0.f), fo = up;
+    if (inside) {
+      p = c.px_offset + (int64_t)j * c.crop_w + i;
+      up = reinterpret_cast<const float4*>(grad_rgba)[p];
+      fo = reinterpret_cast<const float4*>(c.out)[(int64_t)j * c.crop_w + i];
+      up.w *= final_T[p];
+    }
+    s_up[threadIdx.x] = up;
+    s_fo[threadIdx.x] = fo;
   }
 
   const uint2 rg = ranges[t];
@@ -122,8 +125,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 C2 = fmaf(w, R.rgb[2], C2);
                 const float inv1 = fast_rcp(1.f - alpha);
                 // colour behind this pair plus the background it lets through
-                const float B0 = Fo0 - C0, B1 = Fo1 - C1, B2 = Fo2 - C2;
-                float dalpha = GaT * inv1;
+                const float4 up = s_up[threadIdx.x], fo = s_fo[threadIdx.x];
+                const float G0 = up.x, G1 = up.y, G2 = up.z;
+                const float B0 = fo.x - C0, B1 = fo.y - C1, B2 = fo.z - C2;
+                float dalpha = up.w * inv1;
                 dalpha += G0 * (R.rgb[0] * Ttr - B0 * inv1);
                 dalpha += G1 * (R.rgb[1] * Ttr - B1 * inv1);
                 dalpha += G2 * (R.rgb[2] * Ttr - B2 * inv1);
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (int64_t e = threadIdx.x; e < (int64_t)(rg.y - stop_at) * kGradLen; e += 256)
     partial[(int64_t)sorted_slots[stop_at + e / kGradLen] * kGradLen + e % kGradLen] = 0.f;
   // pixels that ran to the end of their list must have reached the stored transmittance
-  if (valid && !done && Ttr != Tfin) atomicAdd(mismatch, 1u);
+  if (valid && !done && Ttr != (inside ? final_T[p] : 1.f)) atomicAdd(mismatch, 1u);
 }
 
 // Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt),
