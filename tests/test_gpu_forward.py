@@ -160,6 +160,36 @@ def test_fisheye_and_equirect_small_parity(backbone):
         check_view(img, scene, c, oopts)
 
 
+def test_more_than_65536_tiles_three_sort_passes():
+    """Three 4096x2048 equirect views in one call: 98,304 tiles, so the tile ids need
+    17 bits and the tile sort a third 8-bit pass, and more than two views take the
+    64-bit depth keys.  Three rows of every view (near the top, the middle, the last)
+    are checked against the oracle."""
+    torch, R = _gpu()
+    scene = synth.make_scene(2000, seed=23, layout="clusters", color="sh3", log_scale_mean=-3.0, log_scale_std=0.6)
+    scene["means"] *= 0.3
+    _, eq = synth.fisheye_cameras()
+    eq = synth.scale_camera(eq, 2.0)
+    cams = []
+    for o in ((0.0, -1.0, 0.3), (0.8, 0.2, -0.2), (-0.5, 0.6, 0.1)):
+        c = dict(eq)
+        c["origin"] = o
+        cams.append(c)
+    w, h = cams[0]["crop"][2], cams[0]["crop"][3]
+    assert (w, h) == (4096, 2048)
+    _say("3 x equirect 4096x2048")
+    rgba, info, _ = R.render_forward(R.Scene.from_numpy(scene), cams, R.RenderOpts())
+    torch.cuda.synchronize()
+    _say(f"   tiles {info['n_tiles']} sort bits {info['sort_bits']} pairs {info['n_pairs']}")
+    assert info["n_tiles"] == 3 * (w // 16) * (h // 16)
+    assert info["sort_bits"] == 17
+    views = R.split_views(rgba, cams)
+    for v, c in enumerate(cams):
+        for row in (5, 1000, h - 1):
+            img = views[v][row:row + 1].cpu().numpy().astype(np.float64)
+            check_view(img, scene, synth.with_crop(c, 0, row, w, 1), O.Opts())
+
+
 def test_empty_and_degenerate_inputs():
     torch, R = _gpu()
     _say("empty inputs")
