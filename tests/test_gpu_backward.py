@@ -83,18 +83,21 @@ def upstream(cams, refs, seed=7):
 
 
 @pytest.mark.parametrize("case", ["floor_marginal", "no_floor", "centre_ray", "isotropic_floor", "rgb_additive",
-                                  "ray_integral_floor"])
+                                  "ray_integral_floor", "ragged_tiles"])
 def test_backward_matches_oracle_gradient(case):
     from paper_2609_13397_amd import render as R
     color = "rgb" if case == "rgb_additive" else "sh3"
     scene = grad_scene(color=color)
-    cams = grad_cameras()
+    # ragged_tiles: 115x86 pinholes and 101x101 fisheyes, whose last tile row and
+    # column hold pixels outside the image
+    cams = grad_cameras(0.9 if case == "ragged_tiles" else 1.0)
     kw = {"floor_marginal": dict(use_floor=True),
           "no_floor": dict(),
           "centre_ray": dict(filter_mode=0, use_floor=True),
           "isotropic_floor": dict(filter_mode=2, use_floor=True),
           "rgb_additive": dict(use_floor=True, composition=1),
-          "ray_integral_floor": dict(use_floor=True, backbone=1)}[case]
+          "ray_integral_floor": dict(use_floor=True, backbone=1),
+          "ragged_tiles": dict(use_floor=True)}[case]
     if kw.get("use_floor"):
         scene["rho2"] = O.bake_rho2(scene, [synth.scale_camera(c, 2.0) for c in cams]).astype(np.float32)
     oopts = O.Opts(**{k: (int(v) if isinstance(v, bool) else v) for k, v in kw.items()})
