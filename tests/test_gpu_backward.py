@@ -161,3 +161,33 @@ def test_training_forward_image_equals_inference(kw):
     _say(f"   pairs {ia['n_pairs']} / {ib['n_pairs']}")
     assert ia["n_pairs"] == ib["n_pairs"] and ia["n_pairs"] > 0
     assert torch.equal(a, b)
+
+
+def test_backward_degenerate_inputs():
+    """No pairs (one Gaussian behind the camera) gives zero gradients and an exact
+    replay; an empty scene gives empty gradients; a zero-sized crop beside a normal
+    view leaves that view's gradient unchanged."""
+    from paper_2609_13397_amd import render as R
+    scene, cam = synth.tiny_config()
+    scene = dict(scene)
+    w, h = cam["crop"][2], cam["crop"][3]
+    G = [synth.seeded_image((h, w, 4), seed=3)]
+    _say("backward with no pairs")
+    behind = synth.subset_scene(scene, np.arange(1))
+    behind["means"] = np.array([[0.0], [0.0], [-5.0]], np.float32)
+    g, _, info, mism = run_gpu(behind, [cam], R.RenderOpts(), G)
+    assert info["n_pairs"] == 0 and mism == 0
+    for k in GROUPS:
+        assert g[k].size > 0 and np.all(g[k] == 0.0), k
+    _say("backward of an empty scene")
+    g, _, info, mism = run_gpu(synth.subset_scene(scene, np.arange(0)), [cam], R.RenderOpts(), G)
+    assert info["n_pairs"] == 0
+    for k in GROUPS:
+        assert g[k].size == 0, k
+    _say("backward with a zero-sized crop beside a normal view")
+    g1, _, _, m1 = run_gpu(scene, [cam], R.RenderOpts(), G)
+    g2, _, _, m2 = run_gpu(scene, [synth.with_crop(cam, 0, 0, 0, 0), cam], R.RenderOpts(),
+                           [np.zeros((0, 0, 4), np.float32)] + G)
+    assert m1 == 0 and m2 == 0
+    for k in GROUPS:
+        np.testing.assert_allclose(g2[k], g1[k], rtol=1e-6, atol=1e-9, err_msg=k)
