@@ -15,9 +15,11 @@
 //   * neighbour rays use the forward half-pixel offsets of Sec. 4.1, falling back
 //     to the backward offset when the forward one leaves the camera's valid domain;
 //   * backbone factor C[w] = 1 (max-response instance of Eq. 3);
-//   * compositing order (Eq. 4): one key per Gaussian and view, the squared
-//     distance |mu - o|^2 evaluated in IEEE float32 (the precision the GPU sorts
-//     in), ties broken by index;
+//   * compositing order (Eq. 4): one key per Gaussian and view, the distance
+//     |mu - o| (compared as its square) in double precision, ties broken by index.
+//     Two composited Gaussians whose keys agree to within float rounding are an
+//     order decision: a renderer that sorts a rounded key may take them the other
+//     way round, and the result with the two swapped is kept as an alternative;
 //   * cut-offs: alpha = min(T, alpha_max); skip if alpha < alpha_min; stop before
 //     the Gaussian that would take transmittance below T_min; T = 0 if t* <= t_near.
 //
@@ -510,27 +512,24 @@ PairResult pair_response(const GaussPre& G, const double o[3], const double d[3]
 }
 
 // ----------------------------------------------------------------------------- depth order
-// One compositing key per Gaussian and view: |mu - o|^2 in IEEE float32 with the
-// operation order ((vx*vx + vy*vy) + vz*vz) and no fused multiply-add.
+// Eq. 4 composites front to back.  One key per Gaussian and view: the squared distance
+// |mu - o|^2 of the mean from the camera centre, in double precision from the float32
+// inputs (the differences and squares of float32 values are exact in double up to the
+// last rounding).  Equal keys keep the index order.
 
-float depth_key(const orc_gaussians& g, int64_t i, const float o[3]) {
+double depth_key(const orc_gaussians& g, int64_t i, const float o[3]) {
   const int64_t n = g.n;
-  volatile float vx = g.means[i] - o[0];
-  volatile float vy = g.means[n + i] - o[1];
-  volatile float vz = g.means[2 * n + i] - o[2];
-  volatile float sx = vx * vx;
-  volatile float sy = vy * vy;
-  volatile float sz = vz * vz;
-  volatile float s = sx + sy;
-  s = s + sz;
+  double s = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double v = (double)g.means[k * n + i] - (double)o[k];
+    s += v * v;
+  }
   return s;
 }
 
-std::vector<int64_t> depth_order(const orc_gaussians& g, const float o[3]) {
-  std::vector<float> key(g.n);
-  for (int64_t i = 0; i < g.n; ++i) key[i] = depth_key(g, i, o);
-  std::vector<int64_t> idx(g.n);
-  for (int64_t i = 0; i < g.n; ++i) idx[i] = i;
+std::vector<int64_t> depth_order(const std::vector<double>& key) {
+  std::vector<int64_t> idx(key.size());
+  for (size_t i = 0; i < key.size(); ++i) idx[i] = (int64_t)i;
   std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
   return idx;
 }
@@ -540,6 +539,7 @@ std::vector<int64_t> depth_order(const orc_gaussians& g, const float o[3]) {
 struct ViewGauss {
   std::vector<GaussPre> pre;   // by Gaussian index
   std::vector<double> col;     // [n][3]
+  std::vector<double> key;     // depth key |mu - o|^2 by Gaussian index
   std::vector<int64_t> order;  // compositing order
 };
 
@@ -553,7 +553,9 @@ ViewGauss setup_view(const orc_gaussians& g, const orc_camera& c, const orc_opts
     v.pre[i] = preprocess(raw_of(g, i), rho2, op.use_floor != 0);
     gauss_color(g, i, v.pre[i].mu, o, &v.col[3 * i]);
   }
-  v.order = depth_order(g, c.origin);
+  v.key.resize(g.n);
+  for (int64_t i = 0; i < g.n; ++i) v.key[i] = depth_key(g, i, c.origin);
+  v.order = depth_order(v.key);
   return v;
 }
 
@@ -562,14 +564,22 @@ ViewGauss setup_view(const orc_gaussians& g, const orc_camera& c, const orc_opts
 // between this FP64 evaluation and an FP32 one because its operands are within a
 // small relative band of the threshold.  The first few such decisions are recorded;
 // `flip` forces the opposite outcome of one of them, giving the alternative result
-// an FP32 renderer may legitimately produce.
+// an FP32 renderer may legitimately produce.  With `key` given (the per-Gaussian
+// order), two consecutive composited Gaussians whose keys lie within the band that
+// float32 rounding of |mu - o|^2 can cross are an order decision too: their
+// alternative is the composite with the two swapped in `cand`.
 
 constexpr double kBandAlpha = 2e-4;  // relative band around alpha_min
 constexpr double kBandTmin = 2e-4;   // relative band around T_min for T*(1 - alpha)
 constexpr double kBandNear = 1e-5;   // relative band around t_near for t*
+// relative band of the depth key: a float32 |mu - o|^2 (three rounded differences,
+// three squares, two sums) is within about 5 units of 2^-24 of the exact value, so
+// two keys can swap order only when they differ by less than about 6e-7 relative
+constexpr double kBandKey = 1e-6;
 constexpr int kMaxDecisions = 4;
 
-struct Decision { int64_t k; int kind; };  // kind: 0 near, 1 alpha_min, 2 T_min
+// kind: 0 t_near, 1 alpha_min, 2 T_min, 3 key order (pa, pb: positions in cand)
+struct Decision { int64_t k; int kind; int64_t pa, pb; };
 
 struct CompositeOut {
   double rgba[4];
@@ -580,7 +590,7 @@ struct CompositeOut {
 
 template <class PairFn>
 CompositeOut composite(const std::vector<int64_t>& cand, const ViewGauss& vg, const orc_opts& op, PairFn pair,
-                       int flip /* -1 none */) {
+                       const double* key, int flip /* -1 none */) {
   CompositeOut out;
   out.n_dec = 0;
   out.n_contrib = 0;
@@ -589,13 +599,15 @@ CompositeOut composite(const std::vector<int64_t>& cand, const ViewGauss& vg, co
   auto decide = [&](bool outcome, bool near, int64_t k, int kind) {
     if (near) {
       const int id = dec_counter++;
-      if (out.n_dec < kMaxDecisions) out.dec[out.n_dec++] = Decision{k, kind};
+      if (out.n_dec < kMaxDecisions) out.dec[out.n_dec++] = Decision{k, kind, -1, -1};
       if (id == flip) return !outcome;
     }
     return outcome;
   };
   const double amin = op.alpha_min, amax = op.alpha_max, tmin = op.T_min, tnear = op.t_near;
-  for (int64_t k : cand) {
+  int64_t prev = -1;  // position of the last composited pair
+  for (int64_t pos = 0; pos < (int64_t)cand.size(); ++pos) {
+    const int64_t k = cand[pos];
     const PairResult pr = pair(k);
     double T = pr.T_raw;
     // t_near cut: only a decision that matters when the uncut pair would contribute.
@@ -607,6 +619,14 @@ CompositeOut composite(const std::vector<int64_t>& cand, const ViewGauss& vg, co
     const bool skip = alpha < amin;
     const bool near_skip = std::fabs(alpha - amin) <= kBandAlpha * amin;
     if (decide(skip, near_skip, k, 1)) continue;
+    if (key && prev >= 0) {
+      const double ka = key[cand[prev]], kb = key[k];
+      if (kb - ka <= kBandKey * std::max(ka, kb)) {
+        const int id = dec_counter++;
+        if (out.n_dec < kMaxDecisions) out.dec[out.n_dec++] = Decision{k, 3, prev, pos};
+        (void)id;
+      }
+    }
     const double test = Ttr * (1.0 - alpha);
     const bool stop = test < tmin;
     const bool near_stop = std::fabs(test - tmin) <= kBandTmin * tmin;
@@ -614,6 +634,7 @@ CompositeOut composite(const std::vector<int64_t>& cand, const ViewGauss& vg, co
     const double* col = &vg.col[3 * k];
     for (int c = 0; c < 3; ++c) C[c] += Ttr * alpha * col[c];
     Ttr = test;
+    prev = pos;
     out.n_contrib++;
   }
   for (int c = 0; c < 3; ++c) out.rgba[c] = C[c] + Ttr * (double)op.bg[c];
@@ -860,7 +881,7 @@ void orc_pixel_rays(const orc_camera* cam, double* out, uint8_t* valid) {
 void orc_sh_basis(const double* dir, double* Y) { sh_basis(dir, Y); }
 
 // Per-Gaussian preprocessing for one camera centre: out [n][8] =
-// (s'_0, s'_1, s'_2, sigma_eff, r, g, b, depth key), W [n][9] row-major.
+// (s'_0, s'_1, s'_2, sigma_eff, r, g, b, depth key |mu - o|^2), W [n][9] row-major.
 void orc_preprocess(const orc_gaussians* g, const float* origin, const orc_opts* op, double* out, double* W) {
   const double o[3] = {origin[0], origin[1], origin[2]};
   for (int64_t i = 0; i < g->n; ++i) {
@@ -946,7 +967,8 @@ int orc_render(const orc_gaussians* g, const orc_camera* cam, const orc_opts* op
       ro.n_dec = 0;
       if (op->order_mode == 1) ro = ray_order(keyed, *op, pair);
       const std::vector<int64_t>& cand = (op->order_mode == 1) ? ro.list : keyed;
-      const CompositeOut co = composite(cand, vg, *op, pair, -1);
+      const double* key = (op->order_mode == 0) ? vg.key.data() : nullptr;
+      const CompositeOut co = composite(cand, vg, *op, pair, key, -1);
       const int n_all = std::min(kMaxDecisions, ro.n_dec + co.n_dec);
       for (int k = 0; k < 4; ++k) rgba[4 * p + k] = co.rgba[k];
       if (n_dec) n_dec[p] = n_all;
@@ -957,9 +979,16 @@ int orc_render(const orc_gaussians* g, const orc_camera* cam, const orc_opts* op
           if (f < ro.n_dec) {
             std::vector<int64_t> swapped = ro.list;
             std::swap(swapped[ro.swap_a[f]], swapped[ro.swap_b[f]]);
-            ca = composite(swapped, vg, *op, pair, -1);
+            ca = composite(swapped, vg, *op, pair, nullptr, -1);
           } else if (f < n_all) {
-            ca = composite(cand, vg, *op, pair, f - ro.n_dec);
+            const Decision& dd = co.dec[f - ro.n_dec];
+            if (dd.kind == 3) {
+              std::vector<int64_t> swapped = cand;
+              std::swap(swapped[dd.pa], swapped[dd.pb]);
+              ca = composite(swapped, vg, *op, pair, nullptr, -1);
+            } else {
+              ca = composite(cand, vg, *op, pair, key, f - ro.n_dec);
+            }
           }
           for (int k = 0; k < 4; ++k) alt[(p * kMaxDecisions + f) * 4 + k] = ca.rgba[k];
         }
@@ -994,7 +1023,7 @@ int orc_render_supersampled(const orc_gaussians* g, const orc_camera* cam, const
         }
         auto pair = [&](int64_t k) { return pair_response(vg.pre[k], o, d, d, d, op); };
         const CompositeOut co =
-            composite(op.order_mode == 1 ? ray_order(vg.order, op, pair).list : vg.order, vg, op, pair, -1);
+            composite(op.order_mode == 1 ? ray_order(vg.order, op, pair).list : vg.order, vg, op, pair, nullptr, -1);
         for (int k = 0; k < 4; ++k) acc[k] += co.rgba[k];
       }
       for (int k = 0; k < 4; ++k) rgba[4 * p + k] = acc[k] / (double)n_sub;

@@ -80,6 +80,27 @@ def test_camera_unproject_matches_oracle(which):
     assert err < 1e-6  # float32 rounding of a unit vector
 
 
+def test_camera_unproject_equirect_known_pixels():
+    """The GPU's equirect inverse at pixels whose directions are known without the
+    formula (the optical axis at the centre, +x three quarters across, -x a quarter
+    across, behind the camera at the left edge, 45 degrees up a quarter down)."""
+    from test_oracle_pins import EQUIRECT_KNOWN
+    torch, R = _gpu()
+    Rw = synth.look_at((0, 0, 0), (0.3, 1, 0.2))
+    cam = synth.camera(synth.EQUIRECT, 512, 256, R_c2w=Rw, origin=(1.0, -2.0, 0.5))
+    R32 = np.array(cam["R_c2w"], np.float32).astype(np.float64)
+    px = np.array([f[0] * 512 for f, _ in EQUIRECT_KNOWN], np.float32)
+    py = np.array([f[1] * 256 for f, _ in EQUIRECT_KNOWN], np.float32)
+    _say("unproject equirect known pixels")
+    dirs, valid = R.camera_unproject(cam, torch.from_numpy(np.stack([px, py])).cuda())
+    dirs = dirs.cpu().numpy().T.astype(np.float64)
+    assert valid.cpu().numpy().all()
+    expect = np.array([R32 @ np.array(dc) for _, dc in EQUIRECT_KNOWN])
+    err = np.max(np.abs(dirs - expect))
+    _say(f"   max dir err {err:.3e}")
+    assert err < 1e-6
+
+
 # --------------------------------------------------------------------------- floor bake
 
 def test_bake_rho2_matches_oracle():

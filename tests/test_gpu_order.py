@@ -151,3 +151,25 @@ def test_buffer_overflow_is_counted_and_bounded():
     a = img[..., 3]
     assert np.all(a >= 0) and np.all(a <= 1 + 1e-6)
     assert np.all(img[..., :3] <= a[..., None] + 1e-5)
+
+
+@pytest.mark.parametrize("case", ["camera_away_from_origin", "near_tied_keys", "separated_keys"])
+@pytest.mark.parametrize("filter_mode", [0, 1])
+def test_key_order_two_gaussians_against_oracle(case, filter_mode):
+    """The per-Gaussian key order (order_mode KEY) on the two-Gaussian scenes of the
+    oracle's order pins: a turned camera away from the world origin (the key is |mu - o|,
+    not |mu|), two Gaussians whose keys agree within float32 rounding (either order is
+    accepted; the oracle offers the swapped composite), and the same pair well apart."""
+    from test_oracle_order import _two_gaussian_frame
+    if case == "camera_away_from_origin":
+        R = synth.look_at((0, 0, 0), (0.3, -1.0, 0.4))
+        o = -10.0 * R[:, 0] + np.array([0.7, -0.4, 1.1])
+        b_cam = (0.25, 0, 4.995)
+    else:
+        R = synth.look_at((0, 0, 0), (-0.6, 0.2, 1.0))
+        o = np.array([1.25, -3.5, 2.0])
+        b_cam = (3.2e-3 if case == "near_tied_keys" else 0.05, 0, 5.0)
+    scene, cam, *_ = _two_gaussian_frame(o, R, (0, 0, 5.0), b_cam, 0.4, 1.4)
+    _say(f"two-Gaussian key order {case} filter {filter_mode}")
+    imgs, _ = _render(scene, [cam], order_mode=0, filter_mode=filter_mode)
+    _check(imgs[0], scene, cam, order_mode=0, filter_mode=filter_mode)

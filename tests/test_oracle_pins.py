@@ -436,6 +436,43 @@ def test_equirect_rows_constant_latitude():
     np.testing.assert_allclose(lat[:, 0], math.pi * (0.5 - (np.arange(32) + 0.5) / 32), atol=1e-14)
 
 
+# Equirect pixels whose directions follow from the longitude/latitude reading alone:
+# (pixel as a fraction of (W, H), camera-frame direction).  Longitude runs from -pi at
+# the left edge to +pi at the right, zero (the optical axis +z) at the centre, +x (right)
+# at three quarters; latitude is +pi/2 at the top row, and up is -y (OpenCV).
+EQUIRECT_KNOWN = [
+    ((0.5, 0.5), (0.0, 0.0, 1.0)),
+    ((0.75, 0.5), (1.0, 0.0, 0.0)),
+    ((0.25, 0.5), (-1.0, 0.0, 0.0)),
+    ((0.0, 0.5), (0.0, 0.0, -1.0)),
+    ((0.625, 0.5), (math.sqrt(0.5), 0.0, math.sqrt(0.5))),
+    ((0.5, 0.25), (0.0, -math.sqrt(0.5), math.sqrt(0.5))),
+    ((0.75, 0.75), (math.sqrt(0.5), math.sqrt(0.5), 0.0)),
+]
+
+
+def test_equirect_longitude_and_latitude_at_known_pixels():
+    """The equirect reading at pixels whose directions are known without the formula:
+    the image centre is the optical axis, three quarters across is +x, a quarter is -x,
+    the left edge is behind the camera, and a quarter down is 45 degrees up.  A mirrored
+    or quarter-turned longitude fails.  World directions are R_c2w times these (the
+    stored float32 rotation, read exactly)."""
+    R = synth.look_at((0, 0, 0), (0.3, 1, 0.2))
+    cam = synth.camera(synth.EQUIRECT, 512, 256, R_c2w=R, origin=(1.0, -2.0, 0.5))
+    R32 = np.array(cam["R_c2w"], np.float32).astype(np.float64)
+    px = np.array([f[0] * 512 for f, _ in EQUIRECT_KNOWN])
+    py = np.array([f[1] * 256 for f, _ in EQUIRECT_KNOWN])
+    d, v = O.unproject(cam, px, py)
+    assert v.all()
+    expect = np.array([R32 @ np.array(dc) for _, dc in EQUIRECT_KNOWN])
+    np.testing.assert_allclose(d, expect, rtol=0, atol=1e-15)
+    # and back: Pi of those directions gives the pixels (the left edge wraps to x = 0 or W)
+    x, y, v2 = O.project(cam, expect)
+    assert v2.all()
+    np.testing.assert_allclose(np.where(np.abs(x - 512) < 1e-6, 0.0, x), px, atol=1e-9)
+    np.testing.assert_allclose(y, py, atol=1e-9)
+
+
 def test_pinhole_vs_zero_distortion_fisheye_paraxial():
     """North-star check (c): a pinhole and a zero-distortion fisheye with the same focal
     length see the same rays near the axis (they differ by f |tan(theta) - theta| pixels),
@@ -668,6 +705,71 @@ def test_oracle_gradient_matches_finite_differences():
         fd = (loss(sp) - loss(sm)) / (np.float64(xp) - np.float64(xm))
         an = g[name][idx]
         assert an == pytest.approx(fd, rel=2e-4, abs=1e-6), (name, idx, an, fd)
+
+
+def _cutoff_fd_scene():
+    """Ten SH Gaussians in front of a 24x18 pinhole; Gaussian 0 sits near the camera and
+    is clamped at alpha_max on the central pixels, Gaussian 1 behind it is opaque enough
+    that pixels which saw Gaussian 0 at alpha_max stop before it (T_min)."""
+    sc = synth.make_scene(10, seed=23, layout="uniform", color="sh3", log_scale_mean=-2.0, log_scale_std=0.3)
+    sc["means"] *= 0.6
+    sc["means"][:, 0] = (0.02, -0.03, -1.8)
+    sc["log_scales"][:, 0] = np.log([0.3, 0.25, 0.2])
+    sc["opacity_logits"][0] = 9.0
+    sc["means"][:, 1] = (0.1, 0.05, 0.9)
+    sc["log_scales"][:, 1] = np.log([0.6, 0.5, 0.55])
+    sc["opacity_logits"][1] = 6.0
+    sc["rho2"] = np.full(10, 4e-4, np.float32)
+    return sc
+
+
+def test_oracle_gradient_with_cutoffs_matches_finite_differences():
+    """The oracle's gradient with the cut-offs on: pairs clamped at alpha_max pass no
+    gradient through T, pixels stop before the pair that would take transmittance below
+    T_min, and pairs below alpha_min are skipped.  Away from the thresholds the render is
+    a smooth function of the parameters, so central differences of whole renders pin
+    those branches.  The scene has clamped pairs and stopped pixels, and every
+    perturbation leaves each pixel's set of composited pairs unchanged (checked); the
+    gradient differs clearly from the cut-off-free one, so a branch taken wrongly fails."""
+    sc = _cutoff_fd_scene()
+    cam = pinhole(24, 18, 20.0, origin=(0.0, 0.0, -3.0))
+    opts = O.Opts(use_floor=1, alpha_max=0.95, T_min=3e-3)
+    G = synth.seeded_image((18, 24, 4), seed=9)
+    base = O.render(sc, cam, opts, with_alt=True)
+    assert (base["n_dec"] == 0).all()
+    # the branches are exercised: clamped pairs and stopped pixels
+    rays, _ = O.pixel_rays(cam)
+    T = np.stack([O.pair_batch(sc, i, np.array(cam["origin"]), rays.reshape(-1, 9), opts)[:, 0]
+                  for i in range(sc["n"])])
+    assert (T[0] >= opts.alpha_max).sum() >= 3 and (T[1] >= opts.alpha_max).sum() >= 1
+    assert np.abs(T - opts.alpha_max).min() > 2e-3
+    live = (T >= opts.alpha_min).sum(0).reshape(18, 24)
+    assert (base["n_contrib"] < live).sum() >= 2
+    g = O.grad(sc, cam, G, opts)
+    g_smooth = O.grad(sc, cam, G, O.Opts.smooth(use_floor=1))
+
+    def render(s):
+        return O.render(s, cam, opts)
+
+    checks = [("means", (2, 0)), ("log_scales", (0, 0)), ("quats", (1, 0)), ("opacity_logits", (0,)),
+              ("color", (0, 0)), ("means", (0, 1)), ("log_scales", (2, 1)), ("opacity_logits", (1,)),
+              ("color", (5, 1)), ("means", (1, 4)), ("log_scales", (1, 6))]
+    for name, idx in checks:
+        h = 2e-5
+        sp = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+        sm = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+        x = np.float64(sc[name][idx])
+        xp, xm = np.float32(x + h), np.float32(x - h)
+        sp[name][idx] = xp
+        sm[name][idx] = xm
+        rp, rm = render(sp), render(sm)
+        assert np.array_equal(rp["n_contrib"], base["n_contrib"]) and np.array_equal(rm["n_contrib"], base["n_contrib"])
+        fd = (np.sum(rp["rgba"] * G) - np.sum(rm["rgba"] * G)) / (np.float64(xp) - np.float64(xm))
+        an = g[name][idx]
+        assert an == pytest.approx(fd, rel=1e-4, abs=1e-6), (name, idx, an, fd)
+        if idx[-1] in (0, 1) and name != "color":
+            # the cut-offs change this gradient by ten times the tolerance or more
+            assert abs(g_smooth[name][idx] - an) > 1e-3 * max(abs(an), 1e-3), (name, idx)
 
 
 # ----------------------------------------------------------------------------- ray-integral backbone
