@@ -183,6 +183,35 @@ __global__ void k_scatter_u32(const uint32_t* __restrict__ src, const uint32_t* 
   if (k < m) dst[idx[k]] = src[k];
 }
 
+// dst[k] = src[idx[k]], and *total += sum of the gathered values in 64 bits (one
+// atomic per workgroup).  The grid strides over m with at most kGatherBlocks groups.
+constexpr int kGatherBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_gather_total(const uint32_t* __restrict__ src,
+                                                      const uint32_t* __restrict__ idx, int64_t m,
+                                                      uint32_t* __restrict__ dst,
+                                                      unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long wsum[4];
+  unsigned long long acc = 0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < m; k += (int64_t)gridDim.x * 256) {
+    const uint32_t v = src[idx[k]];
+    dst[k] = v;
+    acc += v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(total, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+}
+
+hipError_t launch_gather_total(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst,
+                               unsigned long long* total, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((m + 255) / 256, kGatherBlocks);
+  k_gather_total<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(src, idx, m, dst, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s) {
   if (m == 0) return hipSuccess;
   k_gather_u32<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s>>>(src, idx, m, dst);

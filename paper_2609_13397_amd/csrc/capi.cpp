@@ -180,6 +180,11 @@ int bits_for(int64_t v) {
 
 namespace cg {
 
+// Pair indices, offsets and the radix sort's element counts are 32-bit.
+void check_pair_total(uint64_t total) {
+  CG_CHECK_ARG(total < kMaxPairs, "too many (tile, Gaussian) pairs for 32-bit indices: " + std::to_string(total));
+}
+
 void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, const cg_render_opts* opts_in,
                  const cg_allocator* alloc, float* out_rgba, float* const* view_out, cg_fwd_state** state_out,
                  cg_fwd_stats* stats, hipStream_t s) {
@@ -225,6 +230,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     float4* members = sc.get_n<float4>(total_groups * kGroupTiles);
     uint32_t* member_tile = sc.get_n<uint32_t>(total_groups * kGroupTiles);
     float* view_cmax = sc.get_n<float>(n_views);
+    unsigned long long* pair_total = sc.get_n<unsigned long long>(1);
     float4* pix = sc.get_n<float4>(std::max<int64_t>(total_tiles, 1) * kTilePx * 4);
     Record* rec = sc.get_n<Record>(std::max<int64_t>(nv, 1));
     uint32_t* depth_key = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
@@ -236,6 +242,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     {
       ProfScope ps(ST_CAMERA, s);
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(view_cmax), 0u, n_views, s));
+      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(pair_total), 0u, 2, s));
       CG_HIP(launch_tile_cones(dcams, n_views, (int)total_tiles, o.fs, tiles, pix, s));
       CG_HIP(launch_group_cones(dcams, n_views, (int)total_groups, tiles, groups, members, member_tile,
                                 view_cmax, s));
@@ -257,7 +264,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     uint32_t* counts_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
     uint32_t* offs_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
     void* dsort_tmp = sc.get(radix_temp_bytes(nv));
-    uint32_t host_last[2] = {0, 0};
+    unsigned long long host_total = 0;
     const uint32_t* sorted_items = items;
     if (nv > 0) {
       int d_alt = 0;
@@ -276,17 +283,16 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       sorted_items = d_alt ? items_alt : items;
       {
         ProfScope ps(ST_SCAN, s);
-        CG_HIP(launch_gather_u32(counts, sorted_items, nv, counts_sorted, s));
+        CG_HIP(launch_gather_total(counts, sorted_items, nv, counts_sorted, pair_total, s));
         CG_HIP(launch_exclusive_scan(counts_sorted, offs_sorted, nv, scan_tmp, s));
         CG_HIP(launch_scatter_u32(offs_sorted, sorted_items, nv, offsets, s));
       }
-      CG_HIP(hipMemcpyAsync(&host_last[0], offs_sorted + (nv - 1), 4, hipMemcpyDeviceToHost, s));
-      CG_HIP(hipMemcpyAsync(&host_last[1], counts_sorted + (nv - 1), 4, hipMemcpyDeviceToHost, s));
+      CG_HIP(hipMemcpyAsync(&host_total, pair_total, sizeof(host_total), hipMemcpyDeviceToHost, s));
     }
     CG_HIP(hipStreamSynchronize(s));
-    const uint64_t P64 = (uint64_t)host_last[0] + host_last[1];
-    CG_CHECK_ARG(P64 < 0xF0000000ull, "too many (tile, Gaussian) pairs for 32-bit indices");
-    const int64_t P = (int64_t)P64;
+    // the exact 64-bit total: below the limit, the 32-bit offsets of the scan did not wrap
+    check_pair_total(host_total);
+    const int64_t P = (int64_t)host_total;
 
     // pairs emitted in compositing order, then sorted stably by tile
     uint32_t* keys = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));

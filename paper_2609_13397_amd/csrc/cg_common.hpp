@@ -15,6 +15,10 @@ constexpr int kTilePx = kTile * kTile;
 constexpr int kGroup = 8;             // tile group edge in tiles (64 tiles = one wave64)
 constexpr int kGroupTiles = kGroup * kGroup;
 
+// Pair indices, per-item offsets and sort element counts are 32-bit; a forward call's
+// (tile, Gaussian) pairs must stay below this (an argument error otherwise).
+constexpr uint64_t kMaxPairs = 0xF0000000ull;
+
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -156,6 +160,10 @@ hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, 
 hipError_t launch_depth_items32(const uint32_t* depth_key, int64_t n, int64_t nv, uint32_t* keys, uint32_t* items,
                                 hipStream_t s);
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
+// The gather above that also adds the sum of the gathered values to *total (64 bits,
+// zeroed beforehand): the exact pair count, which 32-bit offsets cannot hold.
+hipError_t launch_gather_total(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst,
+                               unsigned long long* total, hipStream_t s);
 hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const uint32_t* slot_gid, int64_t n,
                               uint2* ranges, uint32_t* sorted_gid, hipStream_t s);

@@ -202,8 +202,16 @@ def split_views(rgba: torch.Tensor, cams: Sequence[dict]) -> List[torch.Tensor]:
 
 
 def render_backward(state: ForwardState, grad_rgba: torch.Tensor, scene: Scene) -> Dict[str, torch.Tensor]:
-    """Gradients of sum(grad_rgba * rgba) w.r.t. the raw parameters of ``scene``."""
+    """Gradients of sum(grad_rgba * rgba) w.r.t. the raw parameters of ``scene``.
+    grad_rgba: float32 tensor of the forward output's shape, on the scene's device."""
     L = _lib.lib()
+    if not state.handle:
+        raise ValueError("the forward state was already released")
+    out = state.keep[1]
+    if (tuple(grad_rgba.shape) != tuple(out.shape) or grad_rgba.dtype != torch.float32
+            or grad_rgba.device != out.device):
+        raise ValueError(f"grad_rgba: expected float32 {tuple(out.shape)} on {out.device}, got "
+                         f"{grad_rgba.dtype} {tuple(grad_rgba.shape)} on {grad_rgba.device}")
     grads = {k: torch.empty_like(getattr(scene, k)) for k in PARAM_NAMES}
     g = grad_rgba.contiguous()
     st = L.cg_render_backward(state.handle, C.c_void_p(g.data_ptr()),
@@ -255,10 +263,15 @@ class ConeGaussRender(torch.autograd.Function):
         rgba, _, state = render_forward(scene, cams, opts, need_state=True)
         ctx.state = state
         ctx.scene = scene
+        # The backward reads the forward image (the colour behind each pair comes from it)
+        # and the parameters: saved here, autograd refuses a backward after any of them
+        # was modified in place.
+        ctx.save_for_backward(means, log_scales, quats, opacity_logits, color, rho2, rgba)
         return rgba
 
     @staticmethod
     def backward(ctx, grad_rgba):
+        ctx.saved_tensors  # raises if a saved tensor was modified in place since the forward
         grads = render_backward(ctx.state, grad_rgba, ctx.scene)
         ctx.state.release()
         return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["color"],

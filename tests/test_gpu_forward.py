@@ -211,6 +211,35 @@ def test_more_than_65536_tiles_three_sort_passes():
             check_view(img, scene, synth.with_crop(c, 0, row, w, 1), O.Opts())
 
 
+def test_pair_total_beyond_32_bits_is_an_argument_error():
+    """50,000 Gaussians of 1.6 m around three 4096x2048 equirect centres: every Gaussian
+    reaches every one of the 98,304 tiles, about 4.9e9 (tile, Gaussian) pairs, more than
+    32-bit pair indices hold.  The forward counts the pairs in 64 bits and returns
+    CG_ERR_INVALID_ARG before anything is emitted; the next call renders normally."""
+    torch, R = _gpu()
+    from paper_2609_13397_amd import _lib
+    n = 50_000
+    scene = synth.make_scene(n, seed=29, layout="uniform", color="rgb", log_scale_mean=0.5, log_scale_std=0.01)
+    scene["means"] *= 0.5
+    scene["opacity_logits"][:] = 3.0
+    _, eq = synth.fisheye_cameras()
+    eq = synth.scale_camera(eq, 2.0)
+    cams = []
+    for o in ((0.0, 0.0, 0.0), (0.1, 0.0, 0.0), (0.0, 0.1, 0.0)):
+        c = dict(eq)
+        c["origin"] = o
+        cams.append(c)
+    _say("pair total beyond 32 bits: 50k Gaussians x 3 x equirect 4096x2048")
+    with pytest.raises(_lib.CgError) as ei:
+        R.render_forward(R.Scene.from_numpy(scene), cams, R.RenderOpts())
+    torch.cuda.synchronize()
+    _say(f"   {ei.value}")
+    assert ei.value.status == -1 and "too many" in str(ei.value)  # CG_ERR_INVALID_ARG
+    tiny, cam = synth.tiny_config()
+    imgs, _ = gpu_render(tiny, [cam], R.RenderOpts())
+    check_view(imgs[0], tiny, cam, O.Opts())
+
+
 def test_empty_and_degenerate_inputs():
     torch, R = _gpu()
     _say("empty inputs")
