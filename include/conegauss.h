@@ -143,7 +143,11 @@ typedef struct {
 } cg_render_opts;
 
 /* Scratch allocator.  alloc returns device memory usable in stream order on `stream`
- * (NULL on failure -> CG_ERR_OUT_OF_MEMORY); free releases it in stream order. */
+ * (NULL on failure -> CG_ERR_OUT_OF_MEMORY); free releases it in stream order.
+ * cg_render_forward makes two allocations (the buffers whose sizes are known up front,
+ * then those sized by the pair count), cg_render_backward one.  On a failure the call
+ * frees every block it already holds before it returns; the blocks of a training
+ * state are freed by cg_fwd_state_release, with the allocator the forward was given. */
 typedef struct {
   void* ctx;
   void* (*alloc)(void* ctx, size_t bytes, hipStream_t stream);

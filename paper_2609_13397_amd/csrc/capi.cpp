@@ -223,21 +223,43 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     st->stream = s;
   }
   try {
-    DevCamera* dcams = sc.get_n<DevCamera>(n_views);
+    // phase 1 (sizes known up front): per view, tile, pixel and (view, Gaussian) item
+    const int64_t nv1 = std::max<int64_t>(nv, 1);
+    DevCamera* dcams;
+    TileCone* tiles;
+    float4 *groups, *members, *pix, *cone;
+    uint32_t *member_tile, *depth_key, *counts, *offsets, *items, *items_alt, *counts_sorted, *offs_sorted;
+    float* view_cmax;
+    unsigned long long* pair_total;
+    Record* rec;
+    uint64_t *dkeys, *dkeys_alt;
+    void *scan_tmp, *dsort_tmp;
+    {
+      Carve c;
+      c.add(&dcams, n_views);
+      c.add(&tiles, total_tiles);
+      c.add(&groups, total_groups);
+      c.add(&members, total_groups * kGroupTiles);
+      c.add(&member_tile, total_groups * kGroupTiles);
+      c.add(&view_cmax, n_views);
+      c.add(&pair_total, 1);
+      c.add(&pix, std::max<int64_t>(total_tiles, 1) * kTilePx * 4);
+      c.add(&rec, nv1);
+      c.add(&depth_key, nv1);
+      c.add(&cone, nv1);
+      c.add(&counts, nv1);
+      c.add(&offsets, nv1);
+      c.add_bytes(&scan_tmp, scan_temp_bytes(nv));
+      c.add(&dkeys, nv1);
+      c.add(&dkeys_alt, nv1);
+      c.add(&items, nv1);
+      c.add(&items_alt, nv1);
+      c.add(&counts_sorted, nv1);
+      c.add(&offs_sorted, nv1);
+      c.add_bytes(&dsort_tmp, radix_temp_bytes(nv));
+      sc.get(c);
+    }
     CG_HIP(hipMemcpyAsync(dcams, hc.data(), sizeof(DevCamera) * n_views, hipMemcpyHostToDevice, s));
-    TileCone* tiles = sc.get_n<TileCone>(total_tiles);
-    float4* groups = sc.get_n<float4>(total_groups);
-    float4* members = sc.get_n<float4>(total_groups * kGroupTiles);
-    uint32_t* member_tile = sc.get_n<uint32_t>(total_groups * kGroupTiles);
-    float* view_cmax = sc.get_n<float>(n_views);
-    unsigned long long* pair_total = sc.get_n<unsigned long long>(1);
-    float4* pix = sc.get_n<float4>(std::max<int64_t>(total_tiles, 1) * kTilePx * 4);
-    Record* rec = sc.get_n<Record>(std::max<int64_t>(nv, 1));
-    uint32_t* depth_key = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
-    float4* cone = sc.get_n<float4>(std::max<int64_t>(nv, 1));
-    uint32_t* counts = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
-    uint32_t* offsets = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
-    void* scan_tmp = sc.get(scan_temp_bytes(nv));
 
     {
       ProfScope ps(ST_CAMERA, s);
@@ -257,13 +279,6 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     }
     // compositing order of the (view, Gaussian) items, then pair offsets in that order
     const int view_bits = bits_for(std::max(n_views - 1, 1));
-    uint64_t* dkeys = sc.get_n<uint64_t>(std::max<int64_t>(nv, 1));
-    uint64_t* dkeys_alt = sc.get_n<uint64_t>(std::max<int64_t>(nv, 1));
-    uint32_t* items = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
-    uint32_t* items_alt = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
-    uint32_t* counts_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
-    uint32_t* offs_sorted = sc.get_n<uint32_t>(std::max<int64_t>(nv, 1));
-    void* dsort_tmp = sc.get(radix_temp_bytes(nv));
     unsigned long long host_total = 0;
     const uint32_t* sorted_items = items;
     if (nv > 0) {
@@ -294,22 +309,60 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     check_pair_total(host_total);
     const int64_t P = (int64_t)host_total;
 
-    // pairs emitted in compositing order, then sorted stably by tile
-    uint32_t* keys = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
-    uint32_t* vals = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
-    uint32_t* keys_alt = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
-    uint32_t* vals_alt = sc.get_n<uint32_t>(std::max<int64_t>(P, 1));
-    uint32_t* slot_gid = st ? sc.get_n<uint32_t>(std::max<int64_t>(P, 1)) : nullptr;
-    uint32_t* sorted_gid_buf = st ? sc.get_n<uint32_t>(std::max<int64_t>(P, 1)) : nullptr;
-    uint2* ranges = sc.get_n<uint2>(std::max<int64_t>(total_tiles, 1));
-    uint32_t* tile_order = sc.get_n<uint32_t>(std::max<int64_t>(total_tiles, 1));
-    void* sort_tmp = sc.get(radix_temp_bytes(P));
+    // phase 2 (sizes from the pair count): pairs emitted in compositing order, then
+    // sorted stably by tile, per-tile ranges and the render's state
+    const int64_t P1 = std::max<int64_t>(P, 1);
+    const bool ray_order = o.order_mode == CG_ORDER_RAY;
+    // long lists on a launch with few tiles: segments of the lists on separate workgroups
+    const SplitPolicy pol = split_policy();
+    const bool split = !st && !opts_in->count_pairs && !ray_order && P > 0 && total_tiles < pol.max_tiles &&
+                       P > total_tiles * pol.min_avg_pairs;
+    SegPlan sp{};
+    if (split) {
+      int64_t L = pol.seg_len > 0 ? pol.seg_len : std::max<int64_t>(384, (P + 16383) / 16384);
+      L = std::min<int64_t>(L, int64_t(1) << 30);
+      sp.seg_len = (uint32_t)L;
+      sp.max_segs = total_tiles + (P + L - 1) / L;
+      CG_CHECK_ARG(sp.max_segs < (int64_t(1) << 31), "too many tile segments");
+    }
     // training: per wave, the pairs at which some pixel had alpha >= alpha_min (4 waves
     // per tile; two words of slack so the backward can read the word after a batch)
     const int64_t mask_words = P / 64 + 2;
-    unsigned long long* wmask = st ? sc.get_n<unsigned long long>(4 * mask_words) : nullptr;
-    float* final_T = st ? sc.get_n<float>(std::max<int64_t>(total_px, 1)) : nullptr;
-    uint32_t* n_last = st ? sc.get_n<uint32_t>(std::max<int64_t>(total_px, 1)) : nullptr;
+    uint32_t *keys, *vals, *keys_alt, *vals_alt, *tile_order;
+    uint32_t *slot_gid = nullptr, *sorted_gid_buf = nullptr, *n_last = nullptr;
+    uint2* ranges;
+    void* sort_tmp;
+    unsigned long long *wmask = nullptr, *counters = nullptr;
+    float *final_T = nullptr, *tlo_suffix = nullptr;
+    {
+      Carve c;
+      c.add(&keys, P1);
+      c.add(&vals, P1);
+      c.add(&keys_alt, P1);
+      c.add(&vals_alt, P1);
+      c.add(&ranges, std::max<int64_t>(total_tiles, 1));
+      c.add(&tile_order, std::max<int64_t>(total_tiles, 1));
+      c.add_bytes(&sort_tmp, radix_temp_bytes(P));
+      if (st) {
+        c.add(&slot_gid, P1);
+        c.add(&sorted_gid_buf, P1);
+        c.add(&wmask, 4 * mask_words);
+        c.add(&final_T, std::max<int64_t>(total_px, 1));
+        c.add(&n_last, std::max<int64_t>(total_px, 1));
+      }
+      // counters [0..2]: pair counts (count_pairs); [3]: early composites (order_mode RAY)
+      if (opts_in->count_pairs || ray_order) c.add(&counters, 4);
+      if (ray_order) c.add(&tlo_suffix, P1);
+      if (split) {
+        c.add(&sp.nseg, total_tiles);
+        c.add(&sp.seg_off, total_tiles);
+        c.add(&sp.seg_tile, sp.max_segs);
+        c.add(&sp.seg_prod, sp.max_segs * kTilePx);
+        c.add(&sp.seg_out, sp.max_segs * kTilePx);
+        c.add_bytes(&sp.scan_tmp, scan_temp_bytes(total_tiles));
+      }
+      sc.get(c);
+    }
 
     const int tile_bits = bits_for(std::max<int64_t>(total_tiles - 1, 1));
     int in_alt = 0;
@@ -336,36 +389,10 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       CG_HIP(launch_tile_ranges(skeys, svals, slot_gid, P, ranges, st ? sorted_gid : nullptr, s));
       CG_HIP(launch_tile_order(ranges, (int)total_tiles, tile_order, s));
     }
-    // counters [0..2]: pair counts (count_pairs); [3]: early composites (order_mode RAY)
-    const bool ray_order = o.order_mode == CG_ORDER_RAY;
-    unsigned long long* counters = nullptr;
-    if (opts_in->count_pairs || ray_order) {
-      counters = sc.get_n<unsigned long long>(4);
-      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, s));
-    }
-    float* tlo_suffix = nullptr;
+    if (counters) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, s));
     if (ray_order && P > 0) {
       ProfScope ps(ST_RANGES, s);
-      tlo_suffix = sc.get_n<float>(P);
       CG_HIP(launch_order_bounds(dcams, n_views, (int)total_tiles, rec, n, ranges, sorted_gid, tlo_suffix, s));
-    }
-    // long lists on a launch with few tiles: segments of the lists on separate workgroups
-    const SplitPolicy pol = split_policy();
-    const bool split = !st && !opts_in->count_pairs && !ray_order && P > 0 && total_tiles < pol.max_tiles &&
-                       P > total_tiles * pol.min_avg_pairs;
-    SegPlan sp{};
-    if (split) {
-      int64_t L = pol.seg_len > 0 ? pol.seg_len : std::max<int64_t>(384, (P + 16383) / 16384);
-      L = std::min<int64_t>(L, int64_t(1) << 30);
-      sp.seg_len = (uint32_t)L;
-      sp.max_segs = total_tiles + (P + L - 1) / L;
-      CG_CHECK_ARG(sp.max_segs < (int64_t(1) << 31), "too many tile segments");
-      sp.nseg = sc.get_n<uint32_t>(total_tiles);
-      sp.seg_off = sc.get_n<uint32_t>(total_tiles);
-      sp.seg_tile = sc.get_n<uint32_t>(sp.max_segs);
-      sp.seg_prod = sc.get_n<float>(sp.max_segs * kTilePx);
-      sp.seg_out = sc.get_n<float4>(sp.max_segs * kTilePx);
-      sp.scan_tmp = sc.get(scan_temp_bytes(total_tiles));
     }
     {
       ProfScope ps(ST_RENDER, s);

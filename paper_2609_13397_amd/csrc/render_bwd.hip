@@ -388,9 +388,15 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
   CG_CHECK_ARG(grad_rgba || st->total_px == 0, "null grad_rgba");
   const int64_t nv = n * st->n_views;
   Scratch sc(&st->alloc, s);
-  float* partial = sc.get_n<float>((size_t)std::max<int64_t>(st->P, 1) * kGradLen);
-  float* item_grad = sc.get_n<float>((size_t)nv * kGradLen);
-  unsigned int* mismatch = sc.get_n<unsigned int>(4);
+  float *partial, *item_grad;
+  unsigned int* mismatch;
+  {
+    Carve c;
+    c.add(&partial, (size_t)std::max<int64_t>(st->P, 1) * kGradLen);
+    c.add(&item_grad, (size_t)nv * kGradLen);
+    c.add(&mismatch, 4);
+    sc.get(c);
+  }
   CG_HIP(launch_fill_u32(mismatch, 0u, 1, s));
   if (st->P > 0) {
     ProfScope ps(ST_BWD_RENDER, s);

@@ -36,6 +36,33 @@ void* pool_alloc(size_t bytes, hipStream_t s);
 void pool_free(void* p, hipStream_t s);
 void pool_release_all();
 
+// The buffers of one allocation phase, laid out back to back in one block: each
+// starts on a 256-byte boundary and has 16 bytes of slack after it.  add() records
+// where to store a buffer's address; place() stores them all once the block exists.
+class Carve {
+ public:
+  template <class T>
+  void add(T** out, size_t n) {
+    add_bytes(reinterpret_cast<void**>(out), n * sizeof(T));
+  }
+  void add_bytes(void** out, size_t bytes) {
+    items_.push_back(Item{out, offset_});
+    offset_ += (bytes + 16 + 255) / 256 * 256;
+  }
+  size_t bytes() const { return offset_ == 0 ? 256 : offset_; }
+  void place(void* base) const {
+    for (const Item& it : items_) *it.out = static_cast<char*>(base) + it.offset;
+  }
+
+ private:
+  struct Item {
+    void** out;
+    size_t offset;
+  };
+  std::vector<Item> items_;
+  size_t offset_ = 0;
+};
+
 // Scratch allocations of one call, from the caller's cg_allocator or the pool.
 class Scratch {
  public:
@@ -49,6 +76,8 @@ class Scratch {
   T* get_n(size_t n) {
     return static_cast<T*>(get(n * sizeof(T) + 16));
   }
+  // One block for every buffer of `c` (one allocator call per phase).
+  void get(const Carve& c) { c.place(get(c.bytes())); }
   // Hands ownership of every block allocated so far to `out` (which releases them
   // later with the same allocator and stream).
   void transfer(std::vector<void*>& out) {

@@ -85,6 +85,44 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+class TorchAllocator:
+    """A cg_allocator whose scratch comes from PyTorch's caching allocator, on the
+    stream the library passes (the call's stream), so scratch memory is counted and
+    reused by torch like any tensor's.  A failed allocation returns NULL, which the
+    library turns into CG_ERR_OUT_OF_MEMORY after freeing what the call already held."""
+
+    def __init__(self):
+        self._alloc = _lib.ALLOC_FN(self._on_alloc)
+        self._free = _lib.FREE_FN(self._on_free)
+        self.struct = _lib.CgAllocator(None, self._alloc, self._free)
+
+    def allocate(self, nbytes: int, stream: int) -> int:
+        return torch._C._cuda_cudaCachingAllocator_raw_alloc(int(nbytes), int(stream))
+
+    def release(self, ptr: int) -> None:
+        torch._C._cuda_cudaCachingAllocator_raw_delete(int(ptr))
+
+    def _on_alloc(self, ctx, nbytes, stream):
+        try:
+            return self.allocate(nbytes, stream or 0)
+        except Exception:  # out of memory (or any failure): NULL
+            return None
+
+    def _on_free(self, ctx, ptr, stream):
+        if ptr:
+            self.release(ptr)
+
+
+_TORCH_ALLOCATOR: Optional[TorchAllocator] = None
+
+
+def torch_allocator() -> TorchAllocator:
+    global _TORCH_ALLOCATOR
+    if _TORCH_ALLOCATOR is None:
+        _TORCH_ALLOCATOR = TorchAllocator()
+    return _TORCH_ALLOCATOR
+
+
 @dataclass
 class Scene:
     """Gaussian parameters as float32 device tensors, component-major ([C][N])."""
@@ -142,7 +180,7 @@ class ForwardState:
 
     def __init__(self, handle: C.c_void_p, keep: tuple):
         self.handle = handle
-        self.keep = keep  # tensors the state points into
+        self.keep = keep  # tensors the state points into, and the allocator of its scratch
 
     def release(self):
         if self.handle:
@@ -157,10 +195,12 @@ class ForwardState:
 
 
 def render_forward(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None, need_state: bool = False,
-                   out: Optional[torch.Tensor] = None):
+                   out: Optional[torch.Tensor] = None, allocator: Optional[TorchAllocator] = None):
     """Renders ``cams`` (one batched call).  Returns (rgba [sum px, 4] float32 tensor,
-    stats dict, ForwardState or None)."""
+    stats dict, ForwardState or None).  Scratch memory comes from ``allocator``
+    (default: PyTorch's caching allocator on the current stream)."""
     opts = opts or RenderOpts()
+    allocator = allocator or torch_allocator()
     L = _lib.lib()
     device = scene.means.device
     npx = sum(view_pixels(cams))
@@ -173,11 +213,12 @@ def render_forward(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None, 
     o = opts.to_c()
     stats = _lib.CgStats()
     state = C.c_void_p(0)
-    st = L.cg_render_forward(_lib.byref(g), C.cast(carr, C.c_void_p), len(cams), _lib.byref(o), None,
-                             C.c_void_p(out.data_ptr()), C.byref(state) if need_state else None,
-                             _lib.byref(stats), _stream_handle(device))
+    with torch.cuda.device(device):
+        st = L.cg_render_forward(_lib.byref(g), C.cast(carr, C.c_void_p), len(cams), _lib.byref(o),
+                                 _lib.byref(allocator.struct), C.c_void_p(out.data_ptr()),
+                                 C.byref(state) if need_state else None, _lib.byref(stats), _stream_handle(device))
     _lib.check(st)
-    fs = ForwardState(state, (scene, out)) if need_state else None
+    fs = ForwardState(state, (scene, out, allocator)) if need_state else None
     info = {"n_pairs": stats.n_pairs, "n_tiles": stats.n_tiles, "n_pixels": stats.n_pixels,
             "sort_bits": stats.sort_bits, "n_evaluated": stats.n_evaluated, "n_full": stats.n_full,
             "n_contrib": stats.n_contrib, "n_order_overflow": stats.n_order_overflow,
@@ -214,9 +255,10 @@ def render_backward(state: ForwardState, grad_rgba: torch.Tensor, scene: Scene) 
                          f"{grad_rgba.dtype} {tuple(grad_rgba.shape)} on {grad_rgba.device}")
     grads = {k: torch.empty_like(getattr(scene, k)) for k in PARAM_NAMES}
     g = grad_rgba.contiguous()
-    st = L.cg_render_backward(state.handle, C.c_void_p(g.data_ptr()),
-                              *[C.c_void_p(grads[k].data_ptr()) for k in PARAM_NAMES],
-                              _stream_handle(scene.means.device))
+    with torch.cuda.device(scene.means.device):
+        st = L.cg_render_backward(state.handle, C.c_void_p(g.data_ptr()),
+                                  *[C.c_void_p(grads[k].data_ptr()) for k in PARAM_NAMES],
+                                  _stream_handle(scene.means.device))
     _lib.check(st)
     return grads
 

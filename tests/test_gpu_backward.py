@@ -139,6 +139,38 @@ def test_backward_deterministic_and_autograd():
         assert np.array_equal(p.grad.cpu().numpy().astype(np.float64), g1[k]), k
 
 
+def test_autograd_refuses_inputs_changed_in_place():
+    """The backward reads the forward image and the parameters: changing either in
+    place between the forward and the backward makes autograd raise instead of giving
+    wrong gradients; an upstream gradient of the wrong shape or dtype is refused."""
+    import torch
+    from paper_2609_13397_amd import render as R
+    scene, cam = synth.tiny_config()
+    sc = R.Scene.from_numpy(scene)
+    _say("autograd in-place checks")
+    for which in ("image", "means"):
+        params = [getattr(sc, k).clone().requires_grad_(True) for k in GROUPS]
+        rgba = R.ConeGaussRender.apply(*params, sc.rho2, [cam], R.RenderOpts(), sc.color_mode)
+        loss = rgba.sum()
+        if which == "image":
+            rgba.clamp_(0.0, 0.5)  # an in-place op on the saved output
+        else:
+            with torch.no_grad():
+                params[0].add_(0.01)
+        with pytest.raises(RuntimeError, match="inplace"):
+            loss.backward()
+    _, _, st = R.render_forward(sc, [cam], R.RenderOpts(), need_state=True)
+    npx = cam["crop"][2] * cam["crop"][3]
+    for bad in (torch.zeros((npx, 3), device="cuda"), torch.zeros((npx, 4), device="cuda", dtype=torch.float64),
+                torch.zeros((npx, 4))):
+        with pytest.raises(ValueError, match="grad_rgba"):
+            R.render_backward(st, bad, sc)
+    grads = R.render_backward(st, torch.zeros((npx, 4), device="cuda"), sc)
+    torch.cuda.synchronize()
+    st.release()
+    assert all(float(v.abs().max()) == 0.0 for v in grads.values())
+
+
 @pytest.mark.parametrize("kw", [dict(use_floor=True), dict(use_floor=True, count_pairs=True),
                                 dict(filter_mode=2, use_floor=True), dict(filter_mode=0)],
                          ids=["floor", "floor_counting", "iso_floor", "centre"])
