@@ -194,6 +194,28 @@ cg_status cg_render_forward(const cg_gaussians* g /* host struct, device arrays 
                             float* out_rgba, cg_fwd_state** state_out, cg_fwd_stats* stats_out,
                             hipStream_t stream);
 
+/* cg_render_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * inference forward, same kernels and same result, with every scratch buffer carved
+ * from a 64 MiB file-scope device array instead of an allocator.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the caller still
+ * passes its inputs and out_rgba.  Each GPU holds its own copy of the array from the
+ * library's load until the process ends; its device address is looked up on the first
+ * call on that device.
+ *   A call whose scratch would exceed 64 MiB returns CG_ERR_INVALID_ARG (found before
+ *   anything is written for the buffers sized up front; after the pair count for the
+ *   pair lists), and the next call is unaffected.  As a guide, a call needs about
+ *   190 B per (view, Gaussian), 64 B per pixel (rounded up to 16x16 tiles) and 16 B per
+ *   (tile, Gaussian) pair, plus sort buffers.
+ *   Every call on one GPU uses that GPU's one array, which keeps the last call's
+ *   contents (every buffer that must start at zero is cleared by the call): calls that
+ *   overlap on one GPU, for instance on two streams, race and give wrong images.
+ *   Calls in stream order on one stream are safe.  No training state (no state_out). */
+cg_status cg_render_forward_noalloc(const cg_gaussians* g /* host struct, device arrays */,
+                                    const cg_camera* cams /* host */, int32_t n_views,
+                                    const cg_render_opts* opts /* host */, float* out_rgba,
+                                    cg_fwd_stats* stats_out /* host, may be NULL */, hipStream_t stream);
+
 /* Gradients of L = sum(grad_rgba * out_rgba) with respect to the raw Gaussian
  * parameters of the forward call that produced `st` (summed over its views).  The
  * outputs have the shapes of the inputs and are OVERWRITTEN; rho2 gets no gradient.

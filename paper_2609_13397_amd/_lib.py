@@ -70,6 +70,7 @@ SIGNATURES = {
     "cg_last_error": (C.c_char_p, []),
     "cg_default_opts": (None, [_vp]),
     "cg_render_forward": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cg_render_forward_noalloc": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "cg_render_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cg_fwd_state_release": (None, [_vp]),
     "cg_bwd_replay_mismatches": (C.c_int64, [_vp]),

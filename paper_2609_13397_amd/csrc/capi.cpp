@@ -187,8 +187,9 @@ void check_pair_total(uint64_t total) {
 
 void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, const cg_render_opts* opts_in,
                  const cg_allocator* alloc, float* out_rgba, float* const* view_out, cg_fwd_state** state_out,
-                 cg_fwd_stats* stats, hipStream_t s) {
+                 cg_fwd_stats* stats, hipStream_t s, const FixedRegion* fixed) {
   CG_CHECK_ARG(g_in && cams && opts_in, "null argument");
+  CG_CHECK_ARG(!(fixed && state_out), "a fixed scratch region serves inference calls only");
   CG_CHECK_ARG(n_views >= 1 && n_views <= 4096, "n_views must be in [1, 4096]");
   const GaussPtrs g = make_gauss(*g_in);
   const Opts o = make_opts(*opts_in);
@@ -215,7 +216,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
   const int64_t nv = n * n_views;
   CG_CHECK_ARG(nv < (int64_t(1) << 31), "n * n_views must be below 2^31");
 
-  Scratch sc(alloc, s);
+  Scratch sc(alloc, s, fixed);
   cg_fwd_state* st = nullptr;
   if (state_out) {
     st = new cg_fwd_state();

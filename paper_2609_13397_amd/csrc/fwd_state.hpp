@@ -34,9 +34,10 @@ struct cg_fwd_state {
 
 namespace cg {
 // view_out: per-view output pointers (NULL: views laid out contiguously in out_rgba).
+// fixed: scratch from that region instead of alloc (inference only: state_out NULL).
 void run_forward(const cg_gaussians* g, const cg_camera* cams, int n_views, const cg_render_opts* opts,
                  const cg_allocator* alloc, float* out_rgba, float* const* view_out, cg_fwd_state** state_out,
-                 cg_fwd_stats* stats, hipStream_t s);
+                 cg_fwd_stats* stats, hipStream_t s, const FixedRegion* fixed = nullptr);
 // Host-side validation and set-up shared by the entry points (capi.cpp).
 void check_camera(const cg_camera& c, int idx);
 DevCamera make_dev_camera(const cg_camera& c);

@@ -104,6 +104,16 @@ void pool_release_all() {
 void* Scratch::get(size_t bytes) {
   if (bytes == 0) bytes = 16;
   void* p = nullptr;
+  if (fixed_.base) {
+    const size_t need = fixed_used_ + (bytes + 255) / 256 * 256;
+    if (need > fixed_.bytes)
+      throw Error(CG_ERR_INVALID_ARG, "the call needs more than the " + std::to_string(fixed_.bytes) +
+                                          " bytes of its fixed scratch region (" + std::to_string(need) +
+                                          " bytes so far)");
+    p = static_cast<char*>(fixed_.base) + fixed_used_;
+    fixed_used_ = need;
+    return p;
+  }
   if (user_.alloc) {
     p = user_.alloc(user_.ctx, bytes, s_);
     if (!p) throw Error(CG_ERR_OUT_OF_MEMORY, "allocator callback failed for " + std::to_string(bytes) + " bytes");

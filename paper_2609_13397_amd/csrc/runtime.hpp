@@ -63,10 +63,19 @@ class Carve {
   size_t offset_ = 0;
 };
 
-// Scratch allocations of one call, from the caller's cg_allocator or the pool.
+// A caller-provided device region that stands in for every allocation of a call.
+struct FixedRegion {
+  void* base;
+  size_t bytes;
+};
+
+// Scratch allocations of one call, from the caller's cg_allocator or the pool, or, with
+// a FixedRegion, consecutive 256-byte aligned pieces of that region (nothing is
+// allocated or freed; asking for more than it holds is an argument error).
 class Scratch {
  public:
-  Scratch(const cg_allocator* a, hipStream_t s) : user_(a ? *a : cg_allocator{nullptr, nullptr, nullptr}), s_(s) {}
+  Scratch(const cg_allocator* a, hipStream_t s, const FixedRegion* fixed = nullptr)
+      : user_(a ? *a : cg_allocator{nullptr, nullptr, nullptr}), s_(s), fixed_(fixed ? *fixed : FixedRegion{}) {}
   Scratch(const Scratch&) = delete;
   Scratch& operator=(const Scratch&) = delete;
   ~Scratch() { release(); }
@@ -91,6 +100,8 @@ class Scratch {
  private:
   cg_allocator user_;
   hipStream_t s_;
+  FixedRegion fixed_;
+  size_t fixed_used_ = 0;
   std::vector<void*> blocks_;
 };
 

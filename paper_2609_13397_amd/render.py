@@ -226,6 +226,30 @@ def render_forward(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None, 
     return out, info, fs
 
 
+def render_forward_noalloc(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None,
+                           out: Optional[torch.Tensor] = None):
+    """cg_render_forward_noalloc: the inference forward with its scratch in the library's
+    fixed per-GPU device array (no allocation inside the call).  ``out`` (or a new tensor)
+    receives rgba [sum px, 4].  Returns (rgba, stats dict)."""
+    opts = opts or RenderOpts()
+    L = _lib.lib()
+    device = scene.means.device
+    npx = sum(view_pixels(cams))
+    if out is None:
+        out = torch.empty((npx, 4), dtype=torch.float32, device=device)
+    elif tuple(out.shape) != (npx, 4) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of shape (pixels, 4)")
+    g = scene.to_c()
+    carr = cameras_array(cams)
+    o = opts.to_c()
+    stats = _lib.CgStats()
+    with torch.cuda.device(device):
+        st = L.cg_render_forward_noalloc(_lib.byref(g), C.cast(carr, C.c_void_p), len(cams), _lib.byref(o),
+                                         C.c_void_p(out.data_ptr()), _lib.byref(stats), _stream_handle(device))
+    _lib.check(st)
+    return out, {"n_pairs": stats.n_pairs, "n_tiles": stats.n_tiles, "n_segments": stats.n_segments}
+
+
 def set_tile_split(max_tiles: int = 0, min_avg_pairs: int = 0, seg_len: int = 0) -> None:
     """Thresholds of the split tile render (cg_set_tile_split); zeros restore the defaults."""
     _lib.lib().cg_set_tile_split(int(max_tiles), int(min_avg_pairs), int(seg_len))
