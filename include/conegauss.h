@@ -117,12 +117,14 @@ enum { CG_BACKBONE_MAX_RESPONSE = 0, CG_BACKBONE_RAY_INTEGRAL = 1 };
  *   order_mode      CG_ORDER_* [KEY]: the front-to-back order of Eq. 4.  KEY: one key
  *                   per view and Gaussian, |mu - o| (ties by Gaussian index).  RAY: each
  *                   pixel's pairs by their own max-response depth t* along its ray
- *                   (Sec. 3).  RAY holds up to 16 pending pairs per pixel and composites
- *                   one as soon as no later Gaussian of the tile's list can have a
- *                   smaller t* (every record bounds its t* from below); a full buffer
- *                   composites its smallest t* early, counted in
- *                   cg_fwd_stats.n_order_overflow.  RAY is forward-only: state_out must
- *                   be NULL (CG_ERR_UNSUPPORTED otherwise).
+ *                   (Sec. 3), ties by list position.  RAY holds up to 16 pending pairs
+ *                   per pixel and composites one as soon as no later Gaussian of the
+ *                   tile's list can have a smaller t* (every record bounds its t* from
+ *                   below).  A full buffer defers the pair with the largest t* to a
+ *                   further walk of the tile list over the deferred depth range, so the
+ *                   order is exact however many pairs a pixel has; deferrals are
+ *                   counted in cg_fwd_stats.n_order_overflow.  RAY is forward-only:
+ *                   state_out must be NULL (CG_ERR_UNSUPPORTED otherwise).
  *   backbone        CG_BACKBONE_* [MAX_RESPONSE]: the longitudinal factor C[w] of the
  *                   weighted ray response (Sec. 3) that multiplies Eq. 9.  MAX_RESPONSE:
  *                   w = delta(t - t*), C = 1.  RAY_INTEGRAL: w = 1, C = sqrt(2 pi) /
@@ -174,8 +176,9 @@ typedef struct {
   int64_t n_full;           /* ... that passed the cheap rejection (full Eq. 9 work) */
   int64_t n_contrib;        /* ... that were composited (alpha >= alpha_min, before
                                termination): the method's unit of work              */
-  int64_t n_order_overflow; /* order_mode RAY: pairs composited early because a
-                               pixel's pending buffer was full (else -1)            */
+  int64_t n_order_overflow; /* order_mode RAY: pairs deferred to a further walk of
+                               their tile list because a pixel's pending buffer was
+                               full; the order stays exact (else -1)                */
 } cg_fwd_stats;
 
 int cg_version(void);

@@ -105,7 +105,8 @@ struct PairFoot {
   float h1, h2;                        // E^T q / sqrt 3
 };
 
-__device__ __forceinline__ void pair_foot(const Record& R, const PairPixel& p, const PairGeom& g, PairFoot& f) {
+// e_x and e_y of Eq. 6 in whitened space.
+__device__ __forceinline__ void pair_edges(const Record& R, const PairPixel& p, const PairGeom& g, PairFoot& f) {
   const float* W = R.W;
   const float bx0 = W[0] * p.x0 + W[1] * p.x1 + W[2] * p.x2;
   const float bx1 = W[3] * p.x0 + W[4] * p.x1 + W[5] * p.x2;
@@ -118,6 +119,10 @@ __device__ __forceinline__ void pair_foot(const Record& R, const PairPixel& p, c
   const float t = g.tstar;
   f.ex0 = t * (bx0 - px * g.ax); f.ex1 = t * (bx1 - px * g.ay); f.ex2 = t * (bx2 - px * g.az);
   f.ey0 = t * (by0 - py * g.ax); f.ey1 = t * (by1 - py * g.ay); f.ey2 = t * (by2 - py * g.az);
+}
+
+__device__ __forceinline__ void pair_foot(const Record& R, const PairPixel& p, const PairGeom& g, PairFoot& f) {
+  pair_edges(R, p, g, f);
   constexpr float third = 1.f / 3.f;
   constexpr float isq3 = 0.57735026918962576f;
   f.K11 = (f.ex0 * f.ex0 + f.ex1 * f.ex1 + f.ex2 * f.ex2) * third;
@@ -166,6 +171,48 @@ __device__ __forceinline__ bool floor_G(const Record& R, const PairFoot& f, Pair
   fl.G11 = gbar + beta * fl.dd;
   fl.G22 = gbar - beta * fl.dd;
   fl.G12 = beta * fl.P12;
+  return true;
+}
+
+// Above this tr K the 2x2 form below loses accuracy: D^2 - h^T G (I + K G)^{-1} h and
+// det(I + K G) cancel (a thin Gaussian seen at a grazing angle can have K ~ 1e4, with
+// D^2 and the subtracted term both ~ 1e8), and foot_stable takes over.  At or below it
+// the absolute error of the exponent stays below about 1e-4 (float32 rounding of terms
+// bounded by the pre-rejection's D^2 <= L (1 + 3 tr K)).
+constexpr float kStableTrace = 16.f;
+
+// det A and q^T A^{-1} q of Eq. 9 without cancellation.  q, e_x and e_y lie in the plane
+// orthogonal to a.  With the orthogonal basis e_x, v = e_y - mu e_x of that plane
+// (mu = K12 / K11, n1 = |e_x|^2 = 3 K11, n2 = |v|^2), write q = c_x e_x + c_y e_y; in the
+// orthonormal basis of (e_x, v) the footprint E G E^T / 3 is M = R G R^T / 3 with
+// E = Q R, so det A = det(I + M) = 1 + tr(G K) + N det(G) / 9 and
+// q^T A^{-1} q = (|q|^2 + N c^T adj(G) c / 3) / det A, sums of non-negative terms, with
+// N = n1 n2 = |e_x x e_y|^2.  N would cancel as 9 (K11 K22 - K12^2); instead, since both
+// edges are orthogonal to a, e_x x e_y = t*^2 det(W) (d . (dx x dy)) a / |a|^2 (from
+// (W x) x (W y) = det(W) W^{-T} (x x y)), so N = (t*^2 tau)^2 / (|a|^2 P^2) with the
+// pixel's triple product tau = d . (dx x dy) and P^2 = s'1^2 s'2^2 s'3^2: products only.
+// c_x = sqrt3 h1 / n1 and c_y = s / n2 with s = q . v = sqrt3 (h2 - mu h1), which loses
+// only about ulp / sin(angle of e_x, e_y).  Returns false for a footprint of rank one
+// (e_y parallel to e_x), which the caller leaves to the 2x2 form.
+template <bool FLOOR>
+__device__ __forceinline__ bool foot_stable(const Record& R, const PairPixel& p, const PairGeom& g,
+                                            const PairFoot& f, const PairFloor& fl, float& det, float& expo) {
+  const float c0 = p.x1 * p.y2 - p.x2 * p.y1, c1 = p.x2 * p.y0 - p.x0 * p.y2, c2 = p.x0 * p.y1 - p.x1 * p.y0;
+  const float tt = g.tstar * g.tstar * (p.a0 * c0 + p.a1 * c1 + p.a2 * c2);
+  const float N = tt * tt * g.rn * fast_rcp(R.sp2[0] * R.sp2[1] * R.sp2[2]);
+  const float n1 = 3.f * f.K11;
+  if (!(N > 1e-14f * n1 * n1)) return false;
+  const float G11 = FLOOR ? fl.G11 : 1.f, G12 = FLOOR ? fl.G12 : 0.f, G22 = FLOOR ? fl.G22 : 1.f;
+  constexpr float sq3 = 1.7320508075688772f;
+  const float i1 = fast_rcp(n1);
+  const float mu = f.K12 * 3.f * i1;
+  const float cx = sq3 * f.h1 * i1;
+  const float s = sq3 * (f.h2 - mu * f.h1);
+  const float z1 = N * i1 * cx - mu * s;  // n2 c_x, with c_y = s / n2
+  const float adjG = G22 * z1 * z1 - 2.f * G12 * z1 * s + G11 * s * s;
+  const float detG = FLOOR ? (fl.lm > R.rho2 ? fl.gp * (1.f - R.rho2 * fast_rcp(fl.lm)) : 0.f) : 1.f;
+  det = 1.f + (G11 * f.K11 + 2.f * G12 * f.K12 + G22 * f.K22) + N * detG * (1.f / 9.f);
+  expo = (g.D2 + n1 * n1 * fast_rcp(N) * adjG * (1.f / 3.f)) * fast_rcp(det);
   return true;
 }
 
@@ -230,6 +277,12 @@ __device__ __forceinline__ float pair_full_keep(const Record& R, const PairPixel
     return C * R.sigma * is * __expf(-0.5f * g.D2 * is);
   }
   float det, quad;
+  if (!(f.K11 + f.K22 <= kStableTrace)) {  // large whitened footprint
+    float expo;
+    const bool ok = (MARGINAL && R.rho2 > 0.f) ? foot_stable<true>(R, p, g, f, fl, det, expo)
+                                               : foot_stable<false>(R, p, g, f, fl, det, expo);
+    if (ok) return C * R.sigma * fast_rsq(det) * __expf(-0.5f * expo);
+  }
   if (MARGINAL && R.rho2 > 0.f) {
     const float M11 = 1.f + f.K11 * G11 + f.K12 * G12, M12 = f.K11 * G12 + f.K12 * G22;
     const float M21 = f.K12 * G11 + f.K22 * G12, M22 = 1.f + f.K12 * G12 + f.K22 * G22;

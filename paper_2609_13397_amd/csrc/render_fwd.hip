@@ -132,12 +132,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 
 // ---------------------------------------------------------------------------- per-ray order
 // order_mode RAY: each pixel composites its pairs in the order of their own t* along
-// its ray (Sec. 3).  The tile list is in key order, and every record bounds from below
-// the t* of any pair it can form (record_tstar_lower); with the suffix minimum of those
-// bounds over the rest of the list, a pending pair whose t* is at most that minimum can
-// no longer be preceded and is composited.  Pending pairs (t*, alpha, record index)
-// wait in a per-pixel buffer in registers; when it is full, its smallest t* is
-// composited early (counted: the order is exact when no pixel overflowed).
+// its ray (Sec. 3), ties broken by list position: the key of a pair is (t*, position).
+// The tile list is in per-Gaussian key order, and every record bounds from below the t*
+// of any pair it can form (record_tstar_lower); with the suffix minimum of those bounds
+// over the rest of the list, a pending pair whose t* is at most that minimum can no
+// longer be preceded and is composited.  Pending pairs (t*, alpha, list position) wait
+// in a per-pixel buffer in registers.  When it is full, the pair with the largest key
+// (the new one or a pending one) is deferred, and the pixel's horizon h becomes the
+// smallest deferred key: from then on this walk composites only keys below h, and
+// every such key is either composited or pending when the walk ends.  A pixel with a
+// horizon walks the list again for the keys from h on, and so on: each walk composites
+// the keys of [lo, h) in order, so the order is exact however many pairs a pixel has.
 constexpr int kRayBuf = 16;
 // Records staged per batch of the per-ray-order kernel (one thread per record).
 constexpr int kRayBatch = 128;
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   __shared__ Record srec[kRayBatch];
   __shared__ float slo[kRayBatch + 1];
   __shared__ unsigned int scount[4];
-  uint32_t c_eval = 0, c_full = 0, c_contrib = 0, c_over = 0;
+  uint32_t c_eval = 0, c_full = 0, c_contrib = 0, c_defer = 0;
   const int t = (int)tile_order[blockIdx.x];
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
@@ -215,42 +220,53 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   const WaveCone wc = wave_cone(px, valid);
 
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  bool done = !valid;
+  bool done = !valid;  // terminated (or no valid ray): nothing more to composite
+  bool idle = done;    // no key left for this pixel in the current walk range
   const Record* vrec = rec + (int64_t)v * n_gauss;
-  // pending pairs: t* (INFINITY = empty slot), alpha, Gaussian index; bmin = smallest t*
+  // pending pairs: t* (INFINITY = empty slot), alpha, list position; bmin = smallest t*
   float bt[kRayBuf], ba[kRayBuf];
-  uint32_t bgid[kRayBuf];
+  uint32_t bpos[kRayBuf];
 #pragma unroll
   for (int q = 0; q < kRayBuf; ++q) {
     bt[q] = INFINITY;
     ba[q] = 0.f;
-    bgid[q] = 0u;
+    bpos[q] = 0u;
   }
   float bmin = INFINITY;
-  // composites the pending pair with the smallest t*; called only with bmin < INFINITY,
+  // keys (t*, position) of this walk: lo <= key < h; h = (INFINITY, ~0) while nothing
+  // has been deferred
+  float lo_t = -INFINITY, h_t = INFINITY;
+  uint32_t lo_p = 0u, h_p = ~0u;
+  // composites the pending pair with the smallest key; called only with bmin < INFINITY,
   // so every call removes one entry and each flush loop ends
   auto pop_min = [&]() {
-    float a = 0.f;
-    uint32_t gi = 0u;
-    bool taken = false;
+    int sel = 0;
+    float st = INFINITY;
+    uint32_t sp = ~0u;
 #pragma unroll
     for (int q = 0; q < kRayBuf; ++q)
-      if (!taken && bt[q] == bmin) {
+      if (bt[q] < st || (bt[q] == st && bt[q] < INFINITY && bpos[q] < sp)) {
+        st = bt[q];
+        sp = bpos[q];
+        sel = q;
+      }
+    float a = 0.f;
+#pragma unroll
+    for (int q = 0; q < kRayBuf; ++q)
+      if (q == sel) {
         a = ba[q];
-        gi = bgid[q];
         bt[q] = INFINITY;
-        taken = true;
       }
     bmin = bt[0];
 #pragma unroll
     for (int q = 1; q < kRayBuf; ++q) bmin = fminf(bmin, bt[q]);
     const float test = Ttr * (1.f - a);
     if (test < o.T_min) {
-      done = true;
+      done = idle = true;
       return;
     }
     if (COUNT) ++c_contrib;
-    const float* rgb = vrec[gi].rgb;
+    const float* rgb = vrec[sorted_gid[sp]].rgb;
     const float w = Ttr * a;
     C0 = fmaf(w, rgb[0], C0);
     C1 = fmaf(w, rgb[1], C1);
@@ -259,63 +275,111 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
   };
 
   const uint2 rg = ranges[t];
-  for (uint32_t base = rg.x; base < rg.y; base += kRayBatch) {
-    if (__syncthreads_count(!done) == 0) break;
-    const uint32_t idx = base + threadIdx.x;
-    const int cnt = (int)min((uint32_t)kRayBatch, rg.y - base);
-    // one thread per record: this kernel's pending buffers leave no registers for the
-    // wider copies of stage_records (it would drop from 3 to 2 waves per SIMD)
-    if ((int)threadIdx.x < cnt) srec[threadIdx.x] = vrec[sorted_gid[idx]];
-    if ((int)threadIdx.x <= cnt) slo[threadIdx.x] = idx < rg.y ? tlo_suffix[idx] : INFINITY;
-    __syncthreads();
-    if (wc.live && __ballot(!done) != 0) {
-      for (int sub = 0; sub < cnt; sub += 64) {
-        bool rel = false;
-        if (sub + lane < cnt) rel = record_reaches_cone(srec[sub + lane], wc.ax, wc.ay, wc.az, wc.rad);
-        uint64_t m = __ballot(rel);
-        while (m) {
-          const int k = sub + (int)__builtin_ctzll(m);
-          m &= m - 1;
-          if (!done) {
-            if (COUNT) ++c_eval;
-            const Record& R = srec[k];
-            PairGeom g;
-            if (pair_cheap<FILTER>(R, px, org, o, g)) {
-              if (COUNT) ++c_full;
-              const float alpha = fminf(pair_full<FILTER, MARGINAL, GEER>(R, px, g), o.alpha_max);
-              if (alpha >= o.alpha_min) {
-                bool full = true;
+  // Every walk in which a pixel defers composites at least the kRayBuf pairs pending at
+  // its end (or ends the pixel), and each pair of the list is composited once, so a list
+  // of L pairs needs at most L / kRayBuf + 1 walks: the loop bound is never reached.
+  const int max_walks = (int)((rg.y - rg.x) / kRayBuf) + 2;
+  for (int walk = 0; walk < max_walks; ++walk) {
+    for (uint32_t base = rg.x; base < rg.y; base += kRayBatch) {
+      if (__syncthreads_count(!idle) == 0) break;
+      const uint32_t idx = base + threadIdx.x;
+      const int cnt = (int)min((uint32_t)kRayBatch, rg.y - base);
+      // one thread per record: this kernel's pending buffers leave no registers for the
+      // wider copies of stage_records
+      if ((int)threadIdx.x < cnt) srec[threadIdx.x] = vrec[sorted_gid[idx]];
+      if ((int)threadIdx.x <= cnt) slo[threadIdx.x] = idx < rg.y ? tlo_suffix[idx] : INFINITY;
+      __syncthreads();
+      if (wc.live && __ballot(!idle) != 0) {
+        for (int sub = 0; sub < cnt; sub += 64) {
+          bool rel = false;
+          if (sub + lane < cnt) rel = record_reaches_cone(srec[sub + lane], wc.ax, wc.ay, wc.az, wc.rad);
+          uint64_t m = __ballot(rel);
+          while (m) {
+            const int k = sub + (int)__builtin_ctzll(m);
+            m &= m - 1;
+            if (!idle) {
+              if (COUNT && walk == 0) ++c_eval;
+              const Record& R = srec[k];
+              const uint32_t pos = base + (uint32_t)k;
+              PairGeom g;
+              if (pair_cheap<FILTER>(R, px, org, o, g)) {
+                const float ts = g.tstar;
+                // inside this walk's key range [lo, h)?
+                const bool above_lo = ts > lo_t || (ts == lo_t && pos >= lo_p);
+                const bool below_h = ts < h_t || (ts == h_t && pos < h_p);
+                if (above_lo && below_h) {
+                  if (COUNT) ++c_full;
+                  const float alpha = fminf(pair_full<FILTER, MARGINAL, GEER>(R, px, g), o.alpha_max);
+                  if (alpha >= o.alpha_min) {
+                    bool full = true;
 #pragma unroll
-                for (int q = 0; q < kRayBuf; ++q) full = full && bt[q] < INFINITY;
-                if (full) {  // composite the smallest t* early: the order may be inexact here
-                  ++c_over;
-                  pop_min();
-                }
-                bool placed = done;
+                    for (int q = 0; q < kRayBuf; ++q) full = full && bt[q] < INFINITY;
+                    float nt = ts, na = alpha;
+                    uint32_t np = pos;
+                    if (full) {
+                      // defer the largest key of the pending pairs and the new one
+                      int sel = -1;
+                      float mt = ts;
+                      uint32_t mp = pos;
 #pragma unroll
-                for (int q = 0; q < kRayBuf; ++q)
-                  if (!placed && !(bt[q] < INFINITY)) {
-                    bt[q] = g.tstar;
-                    ba[q] = alpha;
-                    bgid[q] = sorted_gid[base + k];
-                    placed = true;
+                      for (int q = 0; q < kRayBuf; ++q)
+                        if (bt[q] > mt || (bt[q] == mt && bpos[q] > mp)) {
+                          mt = bt[q];
+                          mp = bpos[q];
+                          sel = q;
+                        }
+                      ++c_defer;
+                      h_t = mt;
+                      h_p = mp;
+#pragma unroll
+                      for (int q = 0; q < kRayBuf; ++q)
+                        if (q == sel) {
+                          bt[q] = nt;
+                          ba[q] = na;
+                          bpos[q] = np;
+                        }
+                      if (sel >= 0) {
+                        bmin = bt[0];
+#pragma unroll
+                        for (int q = 1; q < kRayBuf; ++q) bmin = fminf(bmin, bt[q]);
+                      }
+                    } else {
+                      bool placed = false;
+#pragma unroll
+                      for (int q = 0; q < kRayBuf; ++q)
+                        if (!placed && !(bt[q] < INFINITY)) {
+                          bt[q] = nt;
+                          ba[q] = na;
+                          bpos[q] = np;
+                          placed = true;
+                        }
+                      bmin = fminf(bmin, nt);
+                    }
                   }
-                if (!done) bmin = fminf(bmin, g.tstar);
+                }
               }
+              // no record after k can precede a pending t* at or below this bound
+              const float bound = slo[k + 1];
+              while (!done && bmin < INFINITY && bmin <= bound) pop_min();
             }
-            // no record after k can precede a pending t* at or below this bound
-            const float bound = slo[k + 1];
-            while (!done && bmin < INFINITY && bmin <= bound) pop_min();
+            if (__ballot(!idle) == 0) break;
           }
-          if (__ballot(!done) == 0) break;
+          if (__ballot(!idle) == 0) break;
         }
-        if (__ballot(!done) == 0) break;
       }
+      while (!done && bmin < INFINITY && bmin <= slo[cnt]) pop_min();
+      __syncthreads();
     }
-    while (!done && bmin < INFINITY && bmin <= slo[cnt]) pop_min();
-    __syncthreads();
+    // the list is walked: every pending key is below h and nothing later precedes it
+    while (!done && bmin < INFINITY) pop_min();
+    const bool again = !done && h_t < INFINITY;
+    lo_t = h_t;
+    lo_p = h_p;
+    h_t = INFINITY;
+    h_p = ~0u;
+    idle = !again;
+    if (__syncthreads_count(again) == 0) break;
   }
-  while (!done && bmin < INFINITY) pop_min();
   if (inside) {
     float4 out;
     out.x = C0 + Ttr * o.bg[0];
@@ -331,7 +395,7 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
     atomicAdd(&scount[1], c_full);
     atomicAdd(&scount[2], c_contrib);
   }
-  if (c_over) atomicAdd(&scount[3], c_over);
+  if (c_defer) atomicAdd(&scount[3], c_defer);
   __syncthreads();
   if (threadIdx.x < 4 && scount[threadIdx.x]) atomicAdd(&counters[threadIdx.x], (unsigned long long)scount[threadIdx.x]);
 }

@@ -176,10 +176,9 @@ def test_train_1M_backward_sampled_pixels():
 
 
 def test_fisheye_1M_ray_order_sampled_row():
-    """fisheye_1M in per-ray order (order_mode RAY): the pending buffer overflows in its
-    dense clusters, so the GPU image is an approximation of the exact per-ray order;
-    on a sampled row it must be closer to the oracle's exact per-ray order than the
-    key-order image is."""
+    """fisheye_1M in per-ray order (order_mode RAY), in the launch the bench times: the
+    dense clusters fill many pixels' pending buffers (deferred pairs, further walks),
+    and sampled rows match the oracle's exact per-ray order at the 2e-4 bar."""
     import torch
     from paper_2609_13397_amd import render as R
     scene_np, scene, cams = _bench_scene(torch, R)
@@ -189,11 +188,12 @@ def test_fisheye_1M_ray_order_sampled_row():
     _say(f"   overflow {info['n_order_overflow']}")
     ray_v = [v.cpu().numpy().astype(np.float64) for v in R.split_views(ray, cams)]
     key_v = [v.cpu().numpy().astype(np.float64) for v in R.split_views(key, cams)]
+    assert info["n_order_overflow"] > 0
     for v, row in ((0, 800), (1, 512)):
         w = cams[v]["crop"][2]
         cam = synth.with_crop(cams[v], 0, row, w, 1)
-        ref = O.render(scene_np, cam, O.Opts(use_floor=1, order_mode=1), mode="culled")["rgba"][0]
-        e_ray = float(np.sqrt(np.mean((ray_v[v][row] - ref) ** 2)))
-        e_key = float(np.sqrt(np.mean((key_v[v][row] - ref) ** 2)))
-        _say(f"   view {v} row {row}: rmse vs exact per-ray order: ray {e_ray:.3e} key {e_key:.3e}")
-        assert e_ray < 0.05 * e_key
+        ref = O.render(scene_np, cam, O.Opts(use_floor=1, order_mode=1), mode="culled", with_alt=True)
+        nfail, worst, det = compare_image(ray_v[v][row:row + 1], ref)
+        e_key = float(np.sqrt(np.mean((key_v[v][row] - ref["rgba"][0]) ** 2)))
+        _say(f"   view {v} row {row}: fail={nfail} worst={worst:.3e} (key-order rmse {e_key:.3e}) {det}")
+        assert nfail == 0, (worst, det)

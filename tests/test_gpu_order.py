@@ -1,10 +1,10 @@
 """GPU parity of the per-ray compositing order (order_mode RAY: each pixel composites
 its pairs by their own t* along its ray) against the FP64 oracle's order_mode 1.
 
-Parity is exact as long as no pixel's pending buffer overflowed: the parity cases check
-n_order_overflow == 0 and then hold the images to the 2e-4 bar, with the oracle's
-near-tie order decisions as alternatives.  Dense scenes, where the buffer does
-overflow, are checked through properties.
+The kernel's order is exact whatever the density: a pixel whose pending buffer fills
+defers the pairs with the largest keys and walks its tile list again for them.  Every
+case is held to the 2e-4 bar against the oracle, with its near-tie order decisions as
+alternatives, sparse scenes (nothing deferred) and dense ones (many deferrals) alike.
 """
 import math
 import sys
@@ -85,21 +85,21 @@ def test_fisheye_equirect_ray_order_parity():
         _check(img, scene, c, order_mode=1, use_floor=1)
 
 
-def test_dense_scene_ray_order_moves_toward_exact_order():
-    """Dense clusters (2000 Gaussians in 0.3x the volume) overflow the 16-entry buffer
-    in places, so the order is exact only where no overflow happened: the GPU per-ray
-    image must still be closer to the oracle's exact per-ray order than the key-order
-    image is, and the overflow must be reported."""
+@pytest.mark.parametrize("kw", [dict(use_floor=True), dict(filter_mode=0), dict(filter_mode=2, use_floor=True)],
+                         ids=["aniso_floor", "centre", "iso_floor"])
+def test_dense_scene_ray_order_parity(kw):
+    """Dense clusters (2000 Gaussians in 0.3x the volume) fill the 16-entry pending
+    buffer of many pixels: the deferred pairs are composited by further walks, and the
+    image matches the oracle's exact per-ray order at the 2e-4 bar."""
     scene, cams = _wide_scene(2000, 0.3)
-    ray, info = _render(scene, cams, order_mode=1, use_floor=True)
-    key, _ = _render(scene, cams, order_mode=0, use_floor=True)
-    _say(f"   dense: overflow {info['n_order_overflow']}")
+    ray, info = _render(scene, cams, order_mode=1, **kw)
+    key, _ = _render(scene, cams, order_mode=0, **kw)
+    _say(f"   dense {kw}: deferred {info['n_order_overflow']}")
+    assert info["n_order_overflow"] > 0
+    okw = {k: int(v) if isinstance(v, bool) else v for k, v in kw.items()}
     for r, k, c in zip(ray, key, cams):
-        ref = O.render(scene, c, O.Opts(order_mode=1, use_floor=1))["rgba"]
-        e_ray = float(np.sqrt(np.mean((r - ref) ** 2)))
-        e_key = float(np.sqrt(np.mean((k - ref) ** 2)))
-        _say(f"   rmse vs exact per-ray order: ray {e_ray:.3e} key {e_key:.3e}")
-        assert e_ray < 0.5 * e_key
+        assert np.abs(r - k).max() > 1e-3  # the two orders differ visibly here
+        _check(r, scene, c, order_mode=1, **okw)
 
 
 def test_two_gaussian_closed_form_on_gpu():
@@ -128,10 +128,10 @@ def test_two_gaussian_closed_form_on_gpu():
     np.testing.assert_allclose(ray[24, 32, :3], [aA * (1 - aB), aB, 0.0], atol=2e-6)
 
 
-def test_buffer_overflow_is_counted_and_bounded():
-    """A deep stack of nearly coplanar wide Gaussians on one ray fills the 16-entry
-    pending buffer: the overflow is reported, and the image stays a valid composite
-    (alpha in [0, 1], colour within the colour range times alpha)."""
+def test_deep_stack_defers_and_stays_exact():
+    """A deep stack of 40 nearly coplanar wide Gaussians on one ray fills the 16-entry
+    pending buffer: pairs are deferred (counted) and composited by later walks, and the
+    image equals the oracle's exact per-ray order."""
     n = 40
     rng = np.random.default_rng(3)
     scene = {
@@ -146,11 +146,9 @@ def test_buffer_overflow_is_counted_and_bounded():
     }
     cam = synth.camera(synth.PINHOLE, 32, 32, fx=40.0, fy=40.0, cx=16.0, cy=16.0)
     (img,), info = _render(scene, [cam], filter_mode=1, order_mode=1)
-    _say(f"   overflow {info['n_order_overflow']}")
+    _say(f"   deferred {info['n_order_overflow']}")
     assert info["n_order_overflow"] > 0
-    a = img[..., 3]
-    assert np.all(a >= 0) and np.all(a <= 1 + 1e-6)
-    assert np.all(img[..., :3] <= a[..., None] + 1e-5)
+    _check(img, scene, cam, filter_mode=1, order_mode=1)
 
 
 @pytest.mark.parametrize("case", ["camera_away_from_origin", "near_tied_keys", "separated_keys"])
