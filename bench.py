@@ -25,15 +25,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic work per contributing (pixel, Gaussian) pair: flops of the closed form
-# (FMA = 2), floor on / off, plus transcendentals, frozen before tuning.
+# (FMA = 2), floor on / off, plus transcendentals, frozen before tuning; the backward
+# is three times the forward per pair.
 FLOPS_PER_PAIR = {True: 225, False: 156}
 TRANSC_PER_PAIR = {True: 8, False: 4}
+BWD_FLOPS_FACTOR = 3
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
-# Algorithmic HBM bytes of one render launch: per pair a 4-byte list entry and its
-# 128-byte record; per pixel the 64-byte ray record it reads and the 16-byte RGBA output.
-BYTES_PER_PAIR = 132
-BYTES_PER_PIXEL = 80
+# Algorithmic HBM bytes, frozen before tuning: the render reads per pair a 4-byte
+# Gaussian id and an 80-byte record and writes per pixel 24 bytes (RGBA and state);
+# per Gaussian and view the preprocess reads 240 bytes of raw parameters (SH) and
+# writes 100 bytes of record, key and cone; the sort moves 64 bytes per Gaussian and
+# view plus 24 per pair; the backward writes and reads an 80-byte partial gradient per
+# pair and writes 236 bytes of gradient per Gaussian.
+BYTES_PER_PAIR = 84
+BYTES_PER_PIXEL = 24
+BYTES_RAW_PER_GAUSSIAN = 240
+BYTES_RECORD_PER_ITEM = 100
+BYTES_SORT_PER_ITEM, BYTES_SORT_PER_PAIR = 64, 24
+BYTES_BWD_PARTIAL_PER_PAIR = 160
+BYTES_BWD_GRAD_PER_GAUSSIAN = 236
+# this design's render actually reads a 128-byte record per pair and a 64-byte ray
+# record per pixel (reported beside the frozen figure)
+DESIGN_BYTES_PER_PAIR = 132
+DESIGN_BYTES_PER_PIXEL = 80
+
+
+def frame_roofline_ms(n_gauss, n_views, pairs, pixels, contrib, floor=True, backward=False):
+    """Time the whole step would take at the roofline: the tile render (and backward
+    render) at the FP32 vector peak on their algorithmic flops, plus every algorithmic
+    HBM byte of the step at 8 TB/s (stages bound by memory)."""
+    flops = contrib * FLOPS_PER_PAIR[floor] * (1 + (BWD_FLOPS_FACTOR if backward else 0))
+    items = n_gauss * n_views
+    byts = (n_gauss * BYTES_RAW_PER_GAUSSIAN + items * BYTES_RECORD_PER_ITEM + items * BYTES_SORT_PER_ITEM +
+            pairs * (BYTES_SORT_PER_PAIR + BYTES_PER_PAIR) + pixels * BYTES_PER_PIXEL)
+    if backward:
+        byts += pairs * BYTES_BWD_PARTIAL_PER_PAIR + n_gauss * BYTES_BWD_GRAD_PER_GAUSSIAN
+    return (flops / (PEAK_FP32_VECTOR_TFLOPS * 1e12) + byts / (PEAK_HBM_GBS * 1e9)) * 1e3, flops, byts
 
 # sources whose change invalidates the measured HBM traffic of the render kernel (the
 # kernel itself, the pair arithmetic and culling it inlines, and the records it reads)
@@ -120,25 +148,87 @@ def train_step_bench(torch, R, synth, device, steps, warmup):
         loss.backward()
         return loss
 
+    # contributing pairs of the training forward (counting variant, outside the timed region)
+    copts = R.RenderOpts(filter_mode=R.FILTER_ANISOTROPIC, use_floor=True, count_pairs=True)
+    _, info, _ = R.render_forward(scene, cams, copts)
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    # per-stage breakdown from a separate pass (the timed region records no events)
+    # timed region: HIP events bracket the backward render kernel only, for its roofline
+    bprof = R.Profiler(stages=["bwd_render"])
+    with bprof:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    bwd = bprof.read()["bwd_render"]
+    # per-stage breakdown from a separate pass
     prof = R.Profiler()
     with prof:
         for _ in range(steps):
             step()
         torch.cuda.synchronize()
     stages = prof.read()
-    return {"value": npx * steps / dt / 1e6, "unit": "Mpix/s", "ms_per_step": dt / steps * 1e3, "steps": steps,
+    bwd_ms = bwd["ms"] / max(bwd["launches"], 1)
+    bflops = info["n_contrib"] * FLOPS_PER_PAIR[True] * BWD_FLOPS_FACTOR
+    achieved = bflops / (bwd_ms * 1e-3) / 1e12
+    ms_per_step = dt / steps * 1e3
+    frame_ms, _, frame_bytes = frame_roofline_ms(scene.n, len(cams), info["n_pairs"], npx, info["n_contrib"],
+                                                 backward=True)
+    return {"value": npx * steps / dt / 1e6, "unit": "Mpix/s", "ms_per_step": ms_per_step, "steps": steps,
             "workload": "train_1M: 1M Gaussians, 2 pinhole + 2 KB fisheye 1280x720, L1 vs seeded target",
-            "pixels_per_step": npx,
+            "pixels_per_step": npx, "pairs": info["n_pairs"],
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "kernel": "k_render_bwd (backward tile render)",
+                         "kernel_ms": bwd_ms, "units_per_launch": info["n_contrib"], "unit_name": "contributing pair",
+                         "flops_per_unit": FLOPS_PER_PAIR[True] * BWD_FLOPS_FACTOR},
+            "frame_roofline": {"ms": frame_ms, "frac": frame_ms / ms_per_step, "algorithmic_bytes": frame_bytes},
             "stages_ms_per_step": {k: v["ms"] / steps for k, v in stages.items() if v["launches"]}}
+
+
+def config2_bench(torch, R, synth, device, steps, warmup):
+    """Pinhole workload at four resolutions: 100k clustered Gaussians with SH colour, the
+    8 orbit views at 1920x1080, 1/2, 1/4 and 1/8 (calibration scaled with resolution),
+    each resolution one batched call of its 8 views; rho^2 baked from the full-resolution
+    views.  Per resolution: Mpix/s, the tile render's roofline fraction, and the
+    frame-level roofline fraction."""
+    scene_np, full = synth.pinhole_config()
+    scene = R.Scene.from_numpy(scene_np, device=device)
+    scene.rho2 = R.bake_rho2(scene, full, t_near=0.2)
+    opts = R.RenderOpts(filter_mode=R.FILTER_ANISOTROPIC, use_floor=True)
+    copts = R.RenderOpts(filter_mode=R.FILTER_ANISOTROPIC, use_floor=True, count_pairs=True)
+    res = {"workload": "100k Gaussians, 8 orbit pinhole views, one batched call per resolution",
+           "gaussians": scene.n, "resolutions": {}}
+    for name, s in (("1", 1.0), ("1/2", 0.5), ("1/4", 0.25), ("1/8", 0.125)):
+        cams = full if s == 1.0 else [synth.scale_camera(c, s) for c in full]
+        npx = sum(R.view_pixels(cams))
+        out = torch.empty((npx, 4), dtype=torch.float32, device=device)
+        _, info, _ = R.render_forward(scene, cams, copts, out=out)
+        for _ in range(warmup):
+            R.render_forward(scene, cams, opts, out=out)
+        prof = R.Profiler(stages=["render"])
+        with prof:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                R.render_forward(scene, cams, opts, out=out)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        rk = prof.read()["render"]
+        render_ms = rk["ms"] / max(rk["launches"], 1)
+        ms = dt / steps * 1e3
+        frame_ms, _, _ = frame_roofline_ms(scene.n, len(cams), info["n_pairs"], npx, info["n_contrib"])
+        achieved = info["n_contrib"] * FLOPS_PER_PAIR[True] / (render_ms * 1e-3) / 1e12
+        res["resolutions"][name] = {
+            "view": f"{cams[0]['crop'][2]}x{cams[0]['crop'][3]}", "value": npx * steps / dt / 1e6, "unit": "Mpix/s",
+            "ms_per_step": ms, "pixels_per_step": npx, "pairs": info["n_pairs"], "contrib": info["n_contrib"],
+            "render_ms": render_ms, "render_frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "frame_frac": frame_ms / ms}
+        print(f"bench: config 2 at {name}: {ms:.3f} ms/step, {npx * steps / dt / 1e6:.1f} Mpix/s",
+              file=sys.stderr, flush=True)
+    return res
 
 
 def serving_bench(torch, R, synth, device, n_requests=200, levels=(0.25, 0.5, 0.75, 0.9)):
@@ -373,7 +463,8 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-order", action="store_true", help="skip the per-ray compositing order leg")
-    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--no-config2", action="store_true", help="skip the pinhole workload at four resolutions")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     # offline summaries of rocprofv3 output into profiles/ (no GPU needed)
@@ -467,9 +558,17 @@ def main():
     alg_bytes = info["n_pairs"] * BYTES_PER_PAIR + npx * BYTES_PER_PIXEL
     roofline["algorithmic_bytes"] = alg_bytes
     roofline["achieved_GBps"] = alg_bytes / (render_ms * 1e-3) / 1e9
+    roofline["design_bytes"] = info["n_pairs"] * DESIGN_BYTES_PER_PAIR + npx * DESIGN_BYTES_PER_PIXEL
     tr = load_traffic()
     if tr is not None:
         roofline["traffic"] = tr["bytes_per_launch"]
+    frame_ms, _, frame_bytes = frame_roofline_ms(scene.n, len(cams), info["n_pairs"], npx, info["n_contrib"])
+    frame_roofline = {"ms": frame_ms, "frac": frame_ms / ms_per_step, "algorithmic_bytes": frame_bytes}
+
+    config2 = None
+    if not args.no_config2:
+        print("bench: pinhole workload at four resolutions", file=sys.stderr, flush=True)
+        config2 = config2_bench(torch, R, synth, device, max(3, args.steps // 2), max(1, args.warmup))
 
     order_ray = None
     if not args.no_order:
@@ -508,8 +607,10 @@ def main():
                    "filter": "anisotropic footprint + floor (marginal composition)", "colour": "SH degree 3",
                    "pixels_per_step": npx, "pairs": info["n_pairs"]},
         "roofline": roofline,
+        "frame_roofline": frame_roofline,
         "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd,
+        "config2": config2,
         "order_ray": order_ray,
         "serving": serving_res,
         "stages_ms_per_step": stage_ms,

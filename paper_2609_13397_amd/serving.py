@@ -133,10 +133,14 @@ class TraceResult:
 
     def summary(self) -> dict:
         lat = self.latencies_ms
+        # render calls by the number of views they fused (a call of k views completes k
+        # requests, each reporting k)
+        calls = {int(k): int(round((self.batch_views == k).sum() / k)) for k in np.unique(self.batch_views) if k > 0}
         return {"requests": int(lat.size), "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
                 "mpix_per_s": self.pixels / self.wall_s / 1e6, "wall_s": self.wall_s,
                 "mean_batch_views": float(self.batch_views.mean()),
+                "calls_by_views": calls,
                 "failed": int((self.statuses != 0).sum())}
 
 

@@ -77,6 +77,33 @@ def test_pinhole_config_full_resolution_sampled_rows():
         assert nfail == 0, det
 
 
+@pytest.mark.parametrize("scale", [0.5, 0.25, 0.125], ids=["half", "quarter", "eighth"])
+def test_pinhole_config_reduced_resolution_sampled_rows(scale):
+    """The same scene and 8 orbit views at 1/2, 1/4 and 1/8 of 1080p (calibration scaled
+    with resolution), each as one batched call as the bench times it; rho^2 baked from
+    the full-resolution views.  Three rows per resolution, in different views."""
+    import torch
+    from paper_2609_13397_amd import render as R
+    scene_np, full = synth.pinhole_config()
+    scene_np = dict(scene_np)
+    scene_np["rho2"] = O.bake_rho2(scene_np, full, 0.2).astype(np.float32)
+    scene = R.Scene.from_numpy(scene_np)
+    cams = [synth.scale_camera(c, scale) for c in full]
+    w, h = cams[0]["crop"][2], cams[0]["crop"][3]
+    _say(f"pinhole 8 views at {w}x{h}")
+    rgba, info, _ = R.render_forward(scene, cams, R.RenderOpts(use_floor=True))
+    torch.cuda.synchronize()
+    views = [v.cpu().numpy().astype(np.float64) for v in R.split_views(rgba, cams)]
+    _say(f"   pairs {info['n_pairs']}")
+    for v, frac in ((1, 0.5), (4, 0.2), (7, 0.93)):
+        row = int(frac * h)
+        cam = synth.with_crop(cams[v], 0, row, w, 1)
+        ref = O.render(scene_np, cam, O.Opts(use_floor=1), mode="culled", with_alt=True)
+        nfail, worst, det = compare_image(views[v][row:row + 1], ref)
+        _say(f"   view {v} row {row}: fail={nfail} worst={worst:.2e}")
+        assert nfail == 0, det
+
+
 def test_train_1M_backward_properties():
     """train_1M (1M Gaussians, 4 x 1280x720 mixed views): exact replay, bitwise
     determinism, finite gradients, and d/de L(theta + e g) at e = 0 equal to |g|^2 within
