@@ -188,6 +188,31 @@ def train_step_bench(torch, R, synth, device, steps, warmup):
             "stages_ms_per_step": {k: v["ms"] / steps for k, v in stages.items() if v["launches"]}}
 
 
+def valu_ceiling(torch, R, device, blocks=256 * 8, iters=20000):
+    """The FP32 FMA rate the chip sustains without packed instructions, from the
+    library's calibration kernel (8 independent FMA chains per thread, 8 waves per
+    SIMD): wave instructions per SIMD per clock and TFLOP/s, from HIP events."""
+    from paper_2609_13397_amd import _lib
+    L = _lib.lib()
+    out = torch.zeros(1, dtype=torch.float32, device=device)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    import ctypes as C
+    _lib.check(L.cg_profile_valu_probe(blocks, iters, C.c_void_p(out.data_ptr()), C.c_void_p(stream)))
+    prof = R.Profiler(stages=["valu_probe"])
+    with prof:
+        for _ in range(3):
+            _lib.check(L.cg_profile_valu_probe(blocks, iters, C.c_void_p(out.data_ptr()), C.c_void_p(stream)))
+        torch.cuda.synchronize()
+    p = prof.read()["valu_probe"]
+    ms = p["ms"] / max(p["launches"], 1)
+    waves = blocks * 4
+    insts = waves * iters * 8
+    return {"kernel": "k_valu_probe (8 independent v_fma_f32 chains per thread, 8 waves per SIMD)",
+            "ms": ms, "fma_wave_inst": insts,
+            "inst_per_simd_per_clk": insts / (ms * 1e-3 * CLOCK_GHZ * 1e9 * N_SIMD),
+            "tflops": insts * 64 * 2 / (ms * 1e-3) / 1e12}
+
+
 def config2_bench(torch, R, synth, device, steps, warmup):
     """Pinhole workload at four resolutions: 100k clustered Gaussians with SH colour, the
     8 orbit views at 1920x1080, 1/2, 1/4 and 1/8 (calibration scaled with resolution),
@@ -384,54 +409,80 @@ def summarize_traffic(fetch_csv: str, write_csv: str, commands) -> dict:
     return out
 
 
-SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES",
-               "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU"]
+# Two rocprofv3 --pmc passes (at most 8 SQ counters each):
+SQ_COUNTERS = ["SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_VALU2", "SQ_THREAD_CYCLES_VALU",
+               "SQ_INSTS_VALU_TRANS_F32", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAVES"]
+SQ_COUNTERS_2 = ["SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_SALU", "SQ_WAIT_INST_ANY",
+                 "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INST_LEVEL_LDS"]
 N_SIMD = 256 * 4          # MI355X: 256 CUs x 4 SIMDs
 CLOCK_GHZ = 2.4
 
 
-def summarize_valu(sq_csv: str, trace_csv: str, out_md: str, commands, kernels) -> None:
-    """VALU utilisation of the given kernels from one rocprofv3 --pmc run of SQ_COUNTERS
-    (per-dispatch values) and a --kernel-trace run of the same command (per-dispatch
-    durations, kernel_trace.csv), grouped by kernel and grid size (one row per workload).
-    VALU rate = wave64 VALU instructions per SIMD per cycle (duration x clock x SIMDs);
-    lane utilisation = active-lane VALU cycles / (64 x wave VALU cycles)."""
+def summarize_valu(sq_csv: str, trace_csv: str, out_md: str, commands, kernels, sq2_csv: str = None) -> None:
+    """VALU and LDS utilisation of the given kernels from rocprofv3 --pmc runs of
+    SQ_COUNTERS (and SQ_COUNTERS_2) and a --kernel-trace run of the same command
+    (per-dispatch durations, kernel_trace.csv), grouped by kernel and grid size (one
+    row per workload).  SQ_ACTIVE_INST_VALU counts quad-cycles in which a wave works on
+    a VALU instruction, summed over the SIMDs: VALU busy = 4 x that / (SIMDs x cycles).
+    SQ_ACTIVE_INST_VALU2 counts the quad-cycles in which two VALU instructions issue
+    (gfx950 issues up to two per SIMD and cycle).  A kernel whose VALU is busy most of
+    its cycles is issue-bound; one that is not is latency-bound."""
     import csv
-    with open(sq_csv) as f:
-        rows = list(csv.DictReader(f))
+
+    def load(path, names):
+        with open(path) as f:
+            rows = list(csv.DictReader(f))
+        groups = {}
+        for k in kernels:
+            for r in rows:
+                if k in r["Kernel_Name"] and r["Counter_Name"] in names:
+                    groups.setdefault((k, int(r["Grid_Size"])), {}).setdefault(r["Counter_Name"], []).append(
+                        float(r["Counter_Value"]))
+        return groups
+
+    g1 = load(sq_csv, SQ_COUNTERS)
+    g2 = load(sq2_csv, SQ_COUNTERS_2) if sq2_csv else {}
     with open(trace_csv) as f:
         trace = list(csv.DictReader(f))
-    lines = ["# VALU utilisation: " + ", ".join(kernels), "", "Commands (run from the repository root on the GPU box):", "",
-             "```", *commands, "```", "",
-             f"VALU rate = SQ_INSTS_VALU / (average duration in the kernel trace x {CLOCK_GHZ} GHz x {N_SIMD} SIMDs): "
-             "wave64 VALU instructions issued per SIMD per clock. Lane utilisation = SQ_THREAD_CYCLES_VALU / "
-             "(64 x SQ_ACTIVE_INST_VALU). "
-             "Counters and durations are averaged over the dispatches of each kernel and grid size "
-             "(4657152 threads: fisheye_1M; 3686400: train_1M).", "",
-             "| kernel | grid (threads) | dispatches | avg duration (ms) | waves | VALU inst | SALU inst | LDS inst | "
-             "VALU rate (inst/SIMD/clk) | lane utilisation |",
-             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
-    for k in kernels:
-        groups = {}
-        for r in rows:
-            if k in r["Kernel_Name"] and r["Counter_Name"] in SQ_COUNTERS:
-                groups.setdefault(int(r["Grid_Size"]), {}).setdefault(r["Counter_Name"], []).append(
-                    float(r["Counter_Value"]))
-        if not groups:
-            raise SystemExit(f"no {k} dispatches in {sq_csv}")
-        for grid in sorted(groups, reverse=True):
-            per = groups[grid]
-            avg = {c: sum(v) / len(v) for c, v in per.items()}
-            ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
-                  if k in r["Kernel_Name"] and int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) == grid]
-            if not ns:
-                raise SystemExit(f"no {k} with grid {grid} in {trace_csv}")
-            t = sum(ns) / len(ns) * 1e-9
-            issue = avg["SQ_INSTS_VALU"] / (t * CLOCK_GHZ * 1e9 * N_SIMD)
-            lane = avg["SQ_THREAD_CYCLES_VALU"] / (64.0 * avg["SQ_ACTIVE_INST_VALU"])
-            lines.append(f"| `{k}` | {grid} | {len(per['SQ_INSTS_VALU'])} | {t * 1e3:.3f} | {avg['SQ_WAVES']:.0f} | "
-                         f"{avg['SQ_INSTS_VALU']:.3e} | {avg['SQ_INSTS_SALU']:.3e} | {avg['SQ_INSTS_LDS']:.3e} | "
-                         f"{issue:.2f} | {lane:.2f} |")
+    lines = ["# VALU and LDS utilisation: " + ", ".join(kernels), "",
+             "Commands (run from the repository root on the GPU box):", "", "```", *commands, "```", "",
+             f"Per kernel and grid size (4657152 threads: fisheye_1M; 3686400: train_1M), averaged over its "
+             f"dispatches; cycles = average duration in the kernel trace x {CLOCK_GHZ} GHz.", "",
+             "* VALU inst rate = SQ_INSTS_VALU / (cycles x 1024 SIMDs): wave instructions per SIMD per clock.",
+             "* VALU busy = 4 x SQ_ACTIVE_INST_VALU / (cycles x 1024 SIMDs): share of SIMD cycles with a VALU "
+             "instruction in flight (SQ_ACTIVE_INST_VALU is in quad-cycles, summed over SIMDs).",
+             "* dual issue = SQ_ACTIVE_INST_VALU2 / SQ_ACTIVE_INST_VALU: share of VALU quad-cycles in which two "
+             "VALU instructions issue.",
+             "* lane utilisation = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU) (the profiler's "
+             "VALUUtilization).",
+             "* trans = SQ_INSTS_VALU_TRANS_F32 / SQ_INSTS_VALU.",
+             "* LDS bank conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE (stall cycles per active LDS cycle).",
+             "",
+             "| kernel | grid | dispatches | avg ms | waves | VALU inst | inst/SIMD/clk | VALU busy | dual issue | "
+             "lane util | trans | LDS inst | LDS bank conflict |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for (k, grid) in sorted(g1, key=lambda x: (kernels.index(x[0]), -x[1])):
+        per = g1[(k, grid)]
+        avg = {c: sum(v) / len(v) for c, v in per.items()}
+        avg2 = {c: sum(v) / len(v) for c, v in g2.get((k, grid), {}).items()}
+        ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
+              if k in r["Kernel_Name"] and int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) == grid]
+        if not ns:
+            raise SystemExit(f"no {k} with grid {grid} in {trace_csv}")
+        t = sum(ns) / len(ns) * 1e-9
+        cyc = t * CLOCK_GHZ * 1e9
+        issue = avg["SQ_INSTS_VALU"] / (cyc * N_SIMD)
+        busy = 4.0 * avg["SQ_ACTIVE_INST_VALU"] / (cyc * N_SIMD)
+        dual = avg["SQ_ACTIVE_INST_VALU2"] / max(avg["SQ_ACTIVE_INST_VALU"], 1.0)
+        lane = avg["SQ_THREAD_CYCLES_VALU"] / (64.0 * max(avg["SQ_ACTIVE_INST_VALU"], 1.0))
+        trans = avg["SQ_INSTS_VALU_TRANS_F32"] / max(avg["SQ_INSTS_VALU"], 1.0)
+        lds = avg2.get("SQ_INSTS_LDS")
+        conf = (avg2["SQ_LDS_BANK_CONFLICT"] / max(avg2["SQ_LDS_IDX_ACTIVE"], 1.0)) if "SQ_LDS_BANK_CONFLICT" in avg2 \
+            else None
+        lines.append(f"| `{k}` | {grid} | {len(per['SQ_INSTS_VALU'])} | {t * 1e3:.3f} | {avg['SQ_WAVES']:.0f} | "
+                     f"{avg['SQ_INSTS_VALU']:.3e} | {issue:.3f} | {busy:.2f} | {dual:.2f} | {lane:.2f} | {trans:.3f} | "
+                     + (f"{lds:.3e}" if lds is not None else "-") + " | "
+                     + (f"{conf:.3f}" if conf is not None else "-") + " |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -471,6 +522,7 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT_MD"))
     ap.add_argument("--summarize-valu", nargs=3, metavar=("SQ_COUNTER_CSV", "KERNEL_TRACE_CSV", "OUT_MD"))
+    ap.add_argument("--sq2", default=None, help="second SQ counter CSV (SQ_COUNTERS_2) for --summarize-valu")
     ap.add_argument("--kernel", action="append", default=[], help="kernel name (substring) for --summarize-valu")
     ap.add_argument("--title", default="")
     ap.add_argument("--notes", default="")
@@ -484,7 +536,7 @@ def main():
         summarize_trace(*args.summarize_trace, args.title, args.command, args.notes)
         return
     if args.summarize_valu:
-        summarize_valu(*args.summarize_valu, args.command, args.kernel)
+        summarize_valu(*args.summarize_valu, args.command, args.kernel, sq2_csv=args.sq2)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
@@ -564,6 +616,11 @@ def main():
         roofline["traffic"] = tr["bytes_per_launch"]
     frame_ms, _, frame_bytes = frame_roofline_ms(scene.n, len(cams), info["n_pairs"], npx, info["n_contrib"])
     frame_roofline = {"ms": frame_ms, "frac": frame_ms / ms_per_step, "algorithmic_bytes": frame_bytes}
+    ceiling = valu_ceiling(torch, R, device)
+    roofline["measured_fp32_ceiling_tflops"] = ceiling["tflops"]
+    roofline["frac_of_measured_ceiling"] = achieved / ceiling["tflops"]
+    print(f"bench: VALU ceiling {ceiling['tflops']:.1f} TFLOP/s ({ceiling['inst_per_simd_per_clk']:.3f} "
+          f"inst/SIMD/clk)", file=sys.stderr, flush=True)
 
     config2 = None
     if not args.no_config2:
@@ -608,6 +665,7 @@ def main():
                    "pixels_per_step": npx, "pairs": info["n_pairs"]},
         "roofline": roofline,
         "frame_roofline": frame_roofline,
+        "valu_ceiling": ceiling,
         "cpu_baseline": cpu,
         "fwd_bwd": fwd_bwd,
         "config2": config2,

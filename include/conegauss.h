@@ -179,6 +179,8 @@ typedef struct {
   int64_t n_order_overflow; /* order_mode RAY: pairs deferred to a further walk of
                                their tile list because a pixel's pending buffer was
                                full; the order stays exact (else -1)                */
+  int64_t max_tile_pairs;   /* longest tile list, when the call considered the split
+                               tile render (see cg_set_tile_split; else -1)         */
 } cg_fwd_stats;
 
 int cg_version(void);
@@ -325,10 +327,24 @@ void cg_profile_enable_stages(uint32_t mask);
 cg_status cg_profile_collect(void);
 void cg_profile_read(double* total_ms /* host */, int64_t* launches /* host */);
 
-/* Split tile render.  A forward call without training state, pair counting or per-ray
- * order whose launch has fewer than max_tiles tiles (over all views) and more than
- * min_avg_pairs pairs per tile on average (a small view of a large scene) would leave
- * most compute units idle while each tile's workgroup walks a long list.  Each tile's
+/* Calibration kernel for the VALU rate (profiling only; not part of rendering): n_blocks
+ * workgroups of 256 threads, each thread running `iters` rounds of 8 independent
+ * float32 FMA chains, so it issues exactly 8 * iters v_fma_f32 per wave (plus loop
+ * control) and touches no memory; out (device, one float) is never written in
+ * practice.  Timed with the stage profiler ("valu_probe") and read by rocprofv3's SQ
+ * counters, it gives the FP32 issue rate the hardware sustains and what the counters
+ * read at that rate.  Enqueued on `stream`. */
+cg_status cg_profile_valu_probe(int32_t n_blocks, int32_t iters, float* out, hipStream_t stream);
+
+/* Split tile render.  One workgroup per tile takes at least as long as the longest tile
+ * list, walked by one workgroup while the rest of the chip may be idle (a small view of
+ * a large scene, or a low resolution where a few tiles hold most pairs).  A forward
+ * call without training state, pair counting or per-ray order whose launch has fewer
+ * than max_tiles tiles (over all views) reads the longest list back after the tile
+ * sort (one more host synchronisation) and splits when it exceeds both min_longest and
+ * P / 1024 (P: pairs of the launch; about half the pairs each of the chip's ~2048
+ * resident workgroups would get were the work spread evenly, since the split render
+ * makes about two passes over every pair).  Each tile's
  * depth-ordered list is then cut into segments of seg_len pairs (0: about 16384
  * segments in all, at least 384 pairs each), each rendered by its own workgroup:
  * one pass takes every segment's per-pixel transmittance product (Eq. 4's factors
@@ -338,7 +354,7 @@ void cg_profile_read(double* total_ms /* host */, int64_t* launches /* host */);
  * one-workgroup-per-tile render up to the rounding order of those products.
  * Arguments <= 0 restore the defaults (2048 tiles, 2048 pairs, seg_len 0).
  * Process-wide; calls already enqueued keep the values they were issued with. */
-void cg_set_tile_split(int64_t max_tiles, int64_t min_avg_pairs, int64_t seg_len);
+void cg_set_tile_split(int64_t max_tiles, int64_t min_longest, int64_t seg_len);
 
 /* Returns the library's cached scratch memory to the device. */
 cg_status cg_release_cached_memory(void);

@@ -60,7 +60,7 @@ class CgStats(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("n_tiles", C.c_int64), ("n_pixels", C.c_int64),
                 ("n_gaussian_views", C.c_int64), ("sort_bits", C.c_int32), ("n_segments", C.c_int32),
                 ("n_evaluated", C.c_int64), ("n_full", C.c_int64), ("n_contrib", C.c_int64),
-                ("n_order_overflow", C.c_int64)]
+                ("n_order_overflow", C.c_int64), ("max_tile_pairs", C.c_int64)]
 
 
 # Every symbol the header declares, with its ctypes signature.
@@ -83,6 +83,7 @@ SIGNATURES = {
     "cg_set_tile_split": (None, [C.c_int64, C.c_int64, C.c_int64]),
     "cg_profile_collect": (C.c_int, []),
     "cg_profile_read": (None, [_vp, _vp]),
+    "cg_profile_valu_probe": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp]),
     "cg_release_cached_memory": (C.c_int, []),
 }
 

@@ -283,4 +283,39 @@ hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* ord
   return hipGetLastError();
 }
 
+// One workgroup per view: the longest of its tile lists and its pair count, for views
+// with fewer than max_tiles tiles (the ones the split tile render may take).
+__global__ __launch_bounds__(256) void k_view_stats(const DevCamera* __restrict__ cams, const uint2* __restrict__ ranges,
+                                                    int64_t max_tiles, uint32_t* __restrict__ stats) {
+  __shared__ uint32_t s_long, s_pairs;
+  const DevCamera& c = cams[blockIdx.x];
+  const int tiles = c.tiles_x * c.tiles_y;
+  if (threadIdx.x == 0) {
+    s_long = 0u;
+    s_pairs = 0u;
+  }
+  __syncthreads();
+  if (tiles < max_tiles) {
+    uint32_t lng = 0u, sum = 0u;
+    for (int k = threadIdx.x; k < tiles; k += blockDim.x) {
+      const uint2 r = ranges[c.tile_offset + k];
+      lng = max(lng, r.y - r.x);
+      sum += r.y - r.x;
+    }
+    atomicMax(&s_long, lng);
+    atomicAdd(&s_pairs, sum);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    stats[2 * blockIdx.x] = s_long;
+    stats[2 * blockIdx.x + 1] = s_pairs;
+  }
+}
+
+hipError_t launch_view_stats(const DevCamera* cams, int n_views, const uint2* ranges, int64_t max_tiles,
+                             uint32_t* stats, hipStream_t s) {
+  k_view_stats<<<dim3((unsigned)n_views), dim3(256), 0, s>>>(cams, ranges, max_tiles, stats);
+  return hipGetLastError();
+}
+
 }  // namespace cg

@@ -314,18 +314,16 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     // sorted stably by tile, per-tile ranges and the render's state
     const int64_t P1 = std::max<int64_t>(P, 1);
     const bool ray_order = o.order_mode == CG_ORDER_RAY;
-    // long lists on a launch with few tiles: segments of the lists on separate workgroups
+    // long lists on views with few tiles: each such view's longest list and pair count,
+    // read back after the tile sort, decide whether its lists are cut into segments on
+    // separate workgroups (per view, so that a view renders the same alone or fused)
     const SplitPolicy pol = split_policy();
-    const bool split = !st && !opts_in->count_pairs && !ray_order && P > 0 && total_tiles < pol.max_tiles &&
-                       P > total_tiles * pol.min_avg_pairs;
-    SegPlan sp{};
-    if (split) {
-      int64_t L = pol.seg_len > 0 ? pol.seg_len : std::max<int64_t>(384, (P + 16383) / 16384);
-      L = std::min<int64_t>(L, int64_t(1) << 30);
-      sp.seg_len = (uint32_t)L;
-      sp.max_segs = total_tiles + (P + L - 1) / L;
-      CG_CHECK_ARG(sp.max_segs < (int64_t(1) << 31), "too many tile segments");
-    }
+    bool may_split = false;
+    if (!st && !opts_in->count_pairs && !ray_order && P > 0)
+      for (int v = 0; v < n_views; ++v) {
+        const int64_t tv = (int64_t)hc[v].tiles_x * hc[v].tiles_y;
+        may_split = may_split || (tv > 0 && tv < pol.max_tiles);
+      }
     // training: per wave, the pairs at which some pixel had alpha >= alpha_min (4 waves
     // per tile; two words of slack so the backward can read the word after a batch)
     const int64_t mask_words = P / 64 + 2;
@@ -335,6 +333,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     void* sort_tmp;
     unsigned long long *wmask = nullptr, *counters = nullptr;
     float *final_T = nullptr, *tlo_suffix = nullptr;
+    uint32_t* view_stats = nullptr;
     {
       Carve c;
       c.add(&keys, P1);
@@ -354,14 +353,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       // counters [0..2]: pair counts (count_pairs); [3]: early composites (order_mode RAY)
       if (opts_in->count_pairs || ray_order) c.add(&counters, 4);
       if (ray_order) c.add(&tlo_suffix, P1);
-      if (split) {
-        c.add(&sp.nseg, total_tiles);
-        c.add(&sp.seg_off, total_tiles);
-        c.add(&sp.seg_tile, sp.max_segs);
-        c.add(&sp.seg_prod, sp.max_segs * kTilePx);
-        c.add(&sp.seg_out, sp.max_segs * kTilePx);
-        c.add_bytes(&sp.scan_tmp, scan_temp_bytes(total_tiles));
-      }
+      if (may_split) c.add(&view_stats, 2 * (int64_t)n_views);
       sc.get(c);
     }
 
@@ -390,6 +382,41 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       CG_HIP(launch_tile_ranges(skeys, svals, slot_gid, P, ranges, st ? sorted_gid : nullptr, s));
       CG_HIP(launch_tile_order(ranges, (int)total_tiles, tile_order, s));
     }
+    int64_t max_tile_pairs = -1;
+    int n_split = 0;
+    SegPlan sp{};
+    if (may_split) {
+      std::vector<uint32_t> vs(2 * (size_t)n_views);
+      CG_HIP(launch_view_stats(dcams, n_views, ranges, pol.max_tiles, view_stats, s));
+      CG_HIP(hipMemcpyAsync(vs.data(), view_stats, sizeof(uint32_t) * vs.size(), hipMemcpyDeviceToHost, s));
+      CG_HIP(hipStreamSynchronize(s));
+      for (int v = 0; v < n_views; ++v) {
+        const int64_t tv = (int64_t)hc[v].tiles_x * hc[v].tiles_y, longest = vs[2 * v], pv = vs[2 * v + 1];
+        if (tv == 0 || tv >= pol.max_tiles) continue;
+        max_tile_pairs = std::max(max_tile_pairs, longest);
+        if (!split_wins(pol, longest, pv)) continue;
+        int64_t L = pol.seg_len > 0 ? pol.seg_len : std::max<int64_t>(kMinSegLen, (pv + kSegTarget - 1) / kSegTarget);
+        L = std::min<int64_t>(L, int64_t(1) << 30);
+        hc[v].seg_len = (uint32_t)L;
+        sp.max_segs += tv + (pv + L - 1) / L;
+        ++n_split;
+      }
+    }
+    const bool split = n_split > 0;
+    if (split) {
+      CG_CHECK_ARG(sp.max_segs < (int64_t(1) << 31), "too many tile segments");
+      // the split views' segment lengths, for the render kernels
+      CG_HIP(hipMemcpyAsync(dcams, hc.data(), sizeof(DevCamera) * n_views, hipMemcpyHostToDevice, s));
+      // phase 3: the split render's per-segment state
+      Carve c;
+      c.add(&sp.nseg, total_tiles);
+      c.add(&sp.seg_off, total_tiles);
+      c.add(&sp.seg_tile, sp.max_segs);
+      c.add(&sp.seg_prod, sp.max_segs * kTilePx);
+      c.add(&sp.seg_out, sp.max_segs * kTilePx);
+      c.add_bytes(&sp.scan_tmp, scan_temp_bytes(total_tiles));
+      sc.get(c);
+    }
     if (counters) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counters), 0u, 8, s));
     if (ray_order && P > 0) {
       ProfScope ps(ST_RANGES, s);
@@ -400,7 +427,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       if (wmask) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(wmask), 0u, 8 * mask_words, s));
       if (split)
         CG_HIP(launch_render_fwd_split(dcams, n_views, (int)total_tiles, o, rec, n, ranges, sp, sorted_gid, pix, s));
-      else
+      // the views rendered in whole tiles (the kernel skips the split views' tiles)
+      if (n_split < n_views)
         CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, tile_order, sorted_gid, pix,
                                  tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, s));
     }
@@ -421,6 +449,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       stats->n_gaussian_views = nv;
       stats->sort_bits = end_bit;
       stats->n_segments = split ? (int32_t)sp.max_segs : 0;
+      stats->max_tile_pairs = max_tile_pairs;
     }
     if (st) {
       st->g = g;

@@ -30,7 +30,7 @@ struct DevCamera {
   int32_t tiles_x, tiles_y, groups_x, groups_y;
   int32_t tile_offset;   // first global tile index of this view
   int32_t group_offset;  // first global group index of this view
-  int32_t pad0;
+  uint32_t seg_len;      // split tile render: pairs per segment of this view's lists (0: whole tiles)
   int64_t px_offset;     // first pixel of this view in the per-pixel arrays
   float* out;            // this view's RGBA output, [crop_h][crop_w][4]
   double fx, fy, cx, cy, inv_fx, inv_fy, inv_w, inv_h;
@@ -169,6 +169,10 @@ hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const 
                               uint2* ranges, uint32_t* sorted_gid, hipStream_t s);
 // order: a permutation of the tiles, heaviest (most pairs) first, for the render launches
 hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
+// Per view v with fewer than max_tiles tiles: stats[2v] = its longest tile list,
+// stats[2v + 1] = its pairs (0, 0 for larger views).
+hipError_t launch_view_stats(const DevCamera* cams, int n_views, const uint2* ranges, int64_t max_tiles,
+                             uint32_t* stats, hipStream_t s);
 
 // sort.hip
 size_t scan_temp_bytes(int64_t n);
@@ -196,12 +200,13 @@ hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles
                              float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
                              unsigned long long* counters, hipStream_t s);
 
-// Split tile render (long lists on launches with few tiles; render_fwd.hip).  Buffers:
+// Split tile render (long lists on views with few tiles; render_fwd.hip).  The tiles of
+// views with DevCamera::seg_len > 0 are cut into segments of that many pairs; the
+// others are left to launch_render_fwd (which skips the split views' tiles).  Buffers:
 // nseg, seg_off: total_tiles entries; seg_tile: max_segs; seg_prod: max_segs * 256
 // floats; seg_out: max_segs * 256 float4; scan_tmp: scan_temp_bytes(total_tiles).
-// max_segs must be at least total_tiles + P / seg_len (P: pairs of the launch).
+// max_segs must be at least the sum over split views of tiles + pairs / seg_len.
 struct SegPlan {
-  uint32_t seg_len;
   int64_t max_segs;
   uint32_t* nseg;
   uint32_t* seg_off;
@@ -215,9 +220,20 @@ hipError_t launch_render_fwd_split(const DevCamera* cams, int n_views, int total
                                    const uint32_t* sorted_gid, const float4* pix, hipStream_t s);
 // The thresholds of the split render (cg_set_tile_split; runtime.cpp).
 struct SplitPolicy {
-  int64_t max_tiles, min_avg_pairs, seg_len;
+  int64_t max_tiles, min_longest, seg_len;
 };
 SplitPolicy split_policy();
+// Segment length of the split render: about kSegTarget segments in all, at least
+// kMinSegLen pairs each.
+constexpr int64_t kMinSegLen = 384, kSegTarget = 16384;
+// The one-workgroup-per-tile render takes at least as long as its longest list on one
+// workgroup; the split render about two passes over all P pairs spread over the chip's
+// ~2048 resident workgroups, plus its set-up.  Split when the longest list exceeds
+// both policy.min_longest and P / kSplitShare.
+constexpr int64_t kSplitShare = 1024;
+inline bool split_wins(const SplitPolicy& p, int64_t longest, int64_t P) {
+  return longest > p.min_longest && longest > P / kSplitShare;
+}
 
 // bake.hip
 hipError_t launch_bake_rho2(const GaussPtrs& g, const DevCamera* cams, int n_views, float t_near, float* rho2,
@@ -226,7 +242,7 @@ hipError_t launch_bake_rho2(const GaussPtrs& g, const DevCamera* cams, int n_vie
 // ---------------------------------------------------------------- profiling (pool.cpp)
 enum Stage {
   ST_CAMERA = 0, ST_PREPROCESS, ST_BIN_COUNT, ST_DEPTH_SORT, ST_SCAN, ST_BIN_EMIT, ST_SORT, ST_RANGES, ST_RENDER,
-  ST_BWD_RENDER, ST_BWD_REDUCE, ST_BWD_PREPROCESS, ST_BAKE, ST_NUM
+  ST_BWD_RENDER, ST_BWD_REDUCE, ST_BWD_PREPROCESS, ST_BAKE, ST_PROBE, ST_NUM
 };
 void prof_begin(int stage, hipStream_t s);
 void prof_end(int stage, hipStream_t s);

@@ -39,6 +39,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int t = (int)tile_order[blockIdx.x];
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
+  if (c.seg_len != 0u) return;  // a view of the split tile render (launch_render_fwd_split)
   const int lane = threadIdx.x & 63;
   int i, j;
   tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
@@ -401,10 +402,12 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
 }
 
 // ---------------------------------------------------------------------------- split tiles
-// A launch with few tiles and long lists (a small view of a large scene) leaves most of
-// the GPU idle while each workgroup walks its list alone.  The lists are then cut into
-// segments of L pairs, each rendered by its own workgroup (k_seg_plan lists them:
-// nseg[t] segments per tile from seg_off[t], seg_tile[b] the tile of segment b).
+// A view with few tiles and a few very long lists (a small view of a large scene, or a
+// low resolution) leaves most of the GPU idle while one workgroup walks the longest
+// list.  That view's lists are then cut into segments of L = DevCamera::seg_len pairs,
+// each rendered by its own workgroup (k_seg_count / scan / k_seg_fill list them:
+// nseg[t] segments per tile from seg_off[t], seg_tile[b] the tile of segment b; tiles
+// of views rendered whole get none).
 // Pass 1 takes, per pixel, the transmittance product of each segment but the last:
 // the factors (1 - alpha) of its pairs with alpha >= alpha_min, from T = 1, ending
 // with the first factor that takes the product below T_min.  k_seg_prefix replaces
@@ -414,11 +417,13 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
 // every factor before a pair is below T_min exactly when the walk terminated before
 // it).  k_seg_combine sums the segments' colours up to the one where the pixel
 // terminated.  Up to the order of the products, this is the walk of k_render.
-__global__ void k_seg_count(const uint2* __restrict__ ranges, int total_tiles, uint32_t L, uint32_t* __restrict__ nseg) {
+__global__ void k_seg_count(const DevCamera* __restrict__ cams, int n_views, const uint2* __restrict__ ranges,
+                            int total_tiles, uint32_t* __restrict__ nseg) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total_tiles) return;
+  const uint32_t L = cams[view_of_tile(cams, n_views, t)].seg_len;  // 0: a view rendered in whole tiles
   const uint32_t len = ranges[t].y - ranges[t].x;
-  nseg[t] = len > L ? (len + L - 1) / L : 1u;
+  nseg[t] = L == 0u ? 0u : (len > L ? (len + L - 1) / L : 1u);
 }
 
 __global__ void k_seg_fill(const uint32_t* __restrict__ nseg, const uint32_t* __restrict__ seg_off, int total_tiles,
@@ -432,7 +437,7 @@ template <int FILTER, bool MARGINAL, bool GEER, int PASS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_render_seg(
     const DevCamera* __restrict__ cams, int n_views, int total_tiles, Opts o, const Record* __restrict__ rec,
     int64_t n_gauss, const uint2* __restrict__ ranges, const uint32_t* __restrict__ nseg,
-    const uint32_t* __restrict__ seg_off, const uint32_t* __restrict__ seg_tile, uint32_t L,
+    const uint32_t* __restrict__ seg_off, const uint32_t* __restrict__ seg_tile,
     const uint32_t* __restrict__ sorted_gid, const float4* __restrict__ pix, float* __restrict__ seg_prod,
     float4* __restrict__ seg_out) {
   __shared__ Record srec[kFwdBatch];
@@ -453,6 +458,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const Origin org = make_origin(c);
   const WaveCone wc = wave_cone(px, valid);
   const uint2 rg = ranges[t];
+  const uint32_t L = c.seg_len;
   const uint32_t s0 = rg.x + q * L, s1 = min(s0 + L, rg.y);
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool done = !valid;
@@ -573,11 +579,11 @@ static void launch_seg_passes(const DevCamera* cams, int n_views, int total_tile
                               const float4* pix, hipStream_t s) {
   const dim3 grid((unsigned)sp.max_segs), block(256);
   k_render_seg<FILTER, MARGINAL, GEER, 1><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss, ranges,
-                                                                 sp.nseg, sp.seg_off, sp.seg_tile, sp.seg_len,
+                                                                 sp.nseg, sp.seg_off, sp.seg_tile,
                                                                  sorted_gid, pix, sp.seg_prod, sp.seg_out);
   k_seg_prefix<<<dim3((unsigned)total_tiles), block, 0, s>>>(sp.nseg, sp.seg_off, sp.seg_prod);
   k_render_seg<FILTER, MARGINAL, GEER, 2><<<grid, block, 0, s>>>(cams, n_views, total_tiles, o, rec, n_gauss, ranges,
-                                                                 sp.nseg, sp.seg_off, sp.seg_tile, sp.seg_len,
+                                                                 sp.nseg, sp.seg_off, sp.seg_tile,
                                                                  sorted_gid, pix, sp.seg_prod, sp.seg_out);
 }
 
@@ -586,7 +592,7 @@ hipError_t launch_render_fwd_split(const DevCamera* cams, int n_views, int total
                                    const uint32_t* sorted_gid, const float4* pix, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   const unsigned tb = (unsigned)((total_tiles + 255) / 256);
-  k_seg_count<<<dim3(tb), dim3(256), 0, s>>>(ranges, total_tiles, sp.seg_len, sp.nseg);
+  k_seg_count<<<dim3(tb), dim3(256), 0, s>>>(cams, n_views, ranges, total_tiles, sp.nseg);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_exclusive_scan(sp.nseg, sp.seg_off, total_tiles, sp.scan_tmp, s);

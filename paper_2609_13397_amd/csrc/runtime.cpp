@@ -141,7 +141,7 @@ namespace {
 
 const char* kStageNames[ST_NUM] = {"camera",     "preprocess", "bin_count",      "depth_sort", "scan",
                                    "bin_emit",   "sort",       "tile_ranges",    "render",     "bwd_render",
-                                   "bwd_reduce", "bwd_preprocess", "bake_rho2"};
+                                   "bwd_reduce", "bwd_preprocess", "bake_rho2", "valu_probe"};
 
 struct Pending {
   int stage;
@@ -152,8 +152,8 @@ std::mutex g_prof_mu;
 uint32_t g_prof_mask = 0;  // bit i: stage i is bracketed
 
 // split tile render thresholds (cg_set_tile_split)
-constexpr int64_t kSplitMaxTiles = 2048, kSplitMinAvgPairs = 2048;
-std::atomic<int64_t> g_split_max_tiles{kSplitMaxTiles}, g_split_min_avg{kSplitMinAvgPairs}, g_split_len{0};
+constexpr int64_t kSplitMaxTiles = 2048, kSplitMinLongest = 2048;
+std::atomic<int64_t> g_split_max_tiles{kSplitMaxTiles}, g_split_min_long{kSplitMinLongest}, g_split_len{0};
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 double g_total_ms[ST_NUM];
@@ -175,7 +175,7 @@ hipEvent_t get_event() {
 
 }  // namespace
 
-SplitPolicy split_policy() { return SplitPolicy{g_split_max_tiles.load(), g_split_min_avg.load(), g_split_len.load()}; }
+SplitPolicy split_policy() { return SplitPolicy{g_split_max_tiles.load(), g_split_min_long.load(), g_split_len.load()}; }
 
 void prof_begin(int stage, hipStream_t s) {
   if (!((g_prof_mask >> stage) & 1u)) return;
@@ -207,9 +207,9 @@ void cg_profile_enable(int on) { cg::g_prof_mask = on ? ~0u : 0u; }
 
 void cg_profile_enable_stages(uint32_t mask) { cg::g_prof_mask = mask; }
 
-void cg_set_tile_split(int64_t max_tiles, int64_t min_avg_pairs, int64_t seg_len) {
+void cg_set_tile_split(int64_t max_tiles, int64_t min_longest, int64_t seg_len) {
   cg::g_split_max_tiles = max_tiles > 0 ? max_tiles : cg::kSplitMaxTiles;
-  cg::g_split_min_avg = min_avg_pairs > 0 ? min_avg_pairs : cg::kSplitMinAvgPairs;
+  cg::g_split_min_long = min_longest > 0 ? min_longest : cg::kSplitMinLongest;
   cg::g_split_len = seg_len > 0 ? seg_len : 0;
 }
 

@@ -64,16 +64,17 @@ struct cg_server {
   // Scratch estimate of one view: per (view, Gaussian) record, keys, cone and counts;
   // per pair the tile key and value (twice, for the sort) plus slack; per tile its
   // cones and its 256 slots of the 64-byte pixel ray buffer; per pixel the output
-  // staging; when the estimated pairs would take the split tile render, its
-  // per-segment state (tiles + pairs / 384 segments, at most tiles + 16384, of 256
-  // pixels, 20 bytes each).  pairs_per_px is refreshed from completed calls.
+  // staging; when the launch is small enough to take the split tile render (which one
+  // decides from its longest tile list), its per-segment state (tiles + pairs / 384
+  // segments, at most tiles + 16384, of 256 pixels, 20 bytes each).  pairs_per_px is
+  // refreshed from completed calls.
   size_t estimate(const SceneEntry& sc, const cg_camera& cam) const {
     const int64_t px = (int64_t)cam.crop_w * cam.crop_h;
     const int64_t tiles = (int64_t)((cam.crop_w + 15) / 16) * ((cam.crop_h + 15) / 16);
     const double pairs = sc.pairs_per_px * (double)px + 64.0 * (double)tiles;
     const SplitPolicy pol = split_policy();
-    const double segs = (tiles < pol.max_tiles && pairs > (double)tiles * (double)pol.min_avg_pairs)
-                            ? (double)tiles + std::min(16384.0, pairs / 384.0)
+    const double segs = tiles < pol.max_tiles
+                            ? (double)tiles + std::min((double)kSegTarget, pairs / (double)kMinSegLen)
                             : 0.0;
     return (size_t)(sc.g.n * 192 + pairs * 24.0 + (double)tiles * (48.0 + 256.0 * 64.0) + (double)px * 8.0 + (1 << 20) +
                     segs * 256.0 * 20.0);

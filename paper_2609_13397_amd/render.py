@@ -222,7 +222,7 @@ def render_forward(scene: Scene, cams: Sequence[dict], opts: RenderOpts = None, 
     info = {"n_pairs": stats.n_pairs, "n_tiles": stats.n_tiles, "n_pixels": stats.n_pixels,
             "sort_bits": stats.sort_bits, "n_evaluated": stats.n_evaluated, "n_full": stats.n_full,
             "n_contrib": stats.n_contrib, "n_order_overflow": stats.n_order_overflow,
-            "n_segments": stats.n_segments}
+            "n_segments": stats.n_segments, "max_tile_pairs": stats.max_tile_pairs}
     return out, info, fs
 
 
@@ -250,9 +250,9 @@ def render_forward_noalloc(scene: Scene, cams: Sequence[dict], opts: RenderOpts 
     return out, {"n_pairs": stats.n_pairs, "n_tiles": stats.n_tiles, "n_segments": stats.n_segments}
 
 
-def set_tile_split(max_tiles: int = 0, min_avg_pairs: int = 0, seg_len: int = 0) -> None:
+def set_tile_split(max_tiles: int = 0, min_longest: int = 0, seg_len: int = 0) -> None:
     """Thresholds of the split tile render (cg_set_tile_split); zeros restore the defaults."""
-    _lib.lib().cg_set_tile_split(int(max_tiles), int(min_avg_pairs), int(seg_len))
+    _lib.lib().cg_set_tile_split(int(max_tiles), int(min_longest), int(seg_len))
 
 
 def split_views(rgba: torch.Tensor, cams: Sequence[dict]) -> List[torch.Tensor]:

@@ -62,6 +62,30 @@ def test_served_equals_alone():
         assert torch.equal(out, alone), r.rid
 
 
+def test_served_equals_alone_all_scales_and_split_views():
+    """Requests at every serving scale, 1/8 to x8 (the x2..x8 ones crops of the base size
+    of a larger virtual image), over a 20k and a 500k scene: small views of the 500k scene
+    take the split tile render (decided per view, from the view's own lists), fused or
+    alone.  Every served image equals the request rendered alone, bit for bit."""
+    import torch
+    from paper_2609_13397_amd import render as R
+    scenes = _setup(2, (20000, 500000))
+    reqs = synth.serving_trace(40, qps=1000.0, seed=74, n_scenes=2)
+    _say("server: all scales, 3 workers")
+    outs, res, stats = _serve(scenes, reqs, n_workers=3, max_batch_views=8)
+    _say(f"   {res.summary()} stats {stats}")
+    assert (res.statuses == 0).all()
+    assert stats["max_batch_views"] > 1
+    n_split = 0
+    for r, out in zip(reqs, outs):
+        alone, info, _ = R.render_forward(scenes[r.scene], [r.camera], R.RenderOpts(use_floor=True))
+        n_split += info["n_segments"] > 0
+        assert torch.equal(out, alone), (r.rid, r.camera["full_w"], r.camera["crop"], info["n_segments"])
+    zoomed = sum(r.camera["full_w"] > 2048 for r in reqs)
+    _say(f"   requests rendered alone with the split tile render: {n_split}; zoomed crops: {zoomed}")
+    assert n_split > 0 and zoomed > 0
+
+
 def test_served_matches_oracle_sample():
     """One served view checked against the FP64 oracle (a small scene so the oracle is
     quick), to tie the serving path to the same parity bar as the renderer."""

@@ -21,8 +21,8 @@ def _say(*a):
 
 
 def _render(scene, cams, opts, split):
-    """split: (max_tiles, min_avg_pairs, seg_len) for cg_set_tile_split, or None for
-    a render that never splits."""
+    """split: (max_tiles, min_longest, seg_len) for cg_set_tile_split, or None for a
+    render that never splits."""
     import torch
     from paper_2609_13397_amd import render as R
     assert torch.cuda.is_available(), "no GPU"
@@ -94,8 +94,9 @@ def test_split_render_options_and_batches():
 
 
 def test_small_view_of_large_scene_splits_by_default():
-    """A 240x135 view of the 100k-Gaussian pinhole scene has few tiles and long lists:
-    the default thresholds take the split path; its image matches the oracle."""
+    """A 240x135 view of the 100k-Gaussian pinhole scene has few tiles and a few very
+    long lists: the longest list exceeds the default thresholds, so the call takes the
+    split path; its image matches the oracle."""
     from paper_2609_13397_amd import render as R
     scene, views = synth.pinhole_config()
     scene["rho2"] = O.bake_rho2(scene, views).astype(np.float32)
@@ -104,8 +105,8 @@ def test_small_view_of_large_scene_splits_by_default():
     _say("small view of the pinhole scene")
     got, info = _render(scene, [cam], opts, (0, 0, 0))
     _say(f"   pairs {info['n_pairs']} tiles {info['n_tiles']} segments {info['n_segments']}")
-    if info["n_pairs"] > info["n_tiles"] * 2048:
-        assert info["n_segments"] > 0
+    assert info["max_tile_pairs"] > max(2048, info["n_pairs"] // 1024)
+    assert info["n_segments"] > 0
     ref, _ = _render(scene, [cam], opts, None)
     assert (np.abs(ref[0] - got[0]).max(axis=-1) > 1e-5).mean() < 0.002
     refo = O.render(scene, cam, O.Opts(use_floor=1), mode="culled", with_alt=True)
