@@ -44,7 +44,8 @@ typedef enum {
   CG_ERR_UNSUPPORTED = -2,
   CG_ERR_OUT_OF_MEMORY = -3,
   CG_ERR_HIP = -4,
-  CG_ERR_STATE = -5
+  CG_ERR_STATE = -5,
+  CG_ERR_TIMEOUT = -6  /* a server request not admitted within its time limit */
 } cg_status;
 
 /* Camera models.  The paper names pinhole and fisheye cameras only (Sec. 5); the
@@ -263,7 +264,10 @@ cg_status cg_bake_rho2(const cg_gaussians* g /* host struct, device arrays */, c
  * max_batch_views views and max_batch_pixels pixels, while they fit the budget.
  * A fused call renders each view bit for bit as a call with that view alone.
  * With n_workers = 1 and max_batch_views = 1 the server is the plain one-view-per-
- * launch renderer.  fake_executor = 1 replaces rendering by a sleep of
+ * launch renderer.  With request_timeout_ms > 0, a request still queued that long
+ * after its submission is not rendered: it completes with CG_ERR_TIMEOUT and its
+ * output buffer is left untouched (checked whenever a worker looks for work, at
+ * least every request_timeout_ms while one waits, and by every poll and drain).  fake_executor = 1 replaces rendering by a sleep of
  * fake_ns_per_call + fake_ns_per_pixel * pixels (scheduler tests without a GPU). */
 typedef struct cg_server cg_server;
 
@@ -276,9 +280,10 @@ typedef struct {
   int32_t device;              /* [0]      HIP device of the worker streams                 */
   double fake_ns_per_pixel;    /* [1]                                                       */
   double fake_ns_per_call;     /* [50000]                                                   */
+  double request_timeout_ms;   /* [0]      time limit from submission to admission (0: none) */
 } cg_server_config;
 
-/* One finished (or cancelled: status CG_ERR_STATE) request.  Times are seconds on the
+/* One finished (or cancelled: status CG_ERR_STATE; timed out: CG_ERR_TIMEOUT) request.  Times are seconds on the
  * clock of cg_server_now(): submission, admission, start and end of its render call. */
 typedef struct {
   int64_t request_id;
@@ -293,6 +298,7 @@ typedef struct {
 typedef struct {
   int64_t queued, in_flight, completed, batches, views, max_batch_views;
   int64_t reserved_bytes, peak_reserved_bytes;
+  int64_t timed_out;           /* requests completed with CG_ERR_TIMEOUT */
 } cg_server_stats;
 
 void cg_server_default_config(cg_server_config* cfg /* host */);
@@ -338,23 +344,38 @@ cg_status cg_profile_valu_probe(int32_t n_blocks, int32_t iters, float* out, hip
 
 /* Split tile render.  One workgroup per tile takes at least as long as the longest tile
  * list, walked by one workgroup while the rest of the chip may be idle (a small view of
- * a large scene, or a low resolution where a few tiles hold most pairs).  A forward
- * call without training state, pair counting or per-ray order whose launch has fewer
- * than max_tiles tiles (over all views) reads the longest list back after the tile
- * sort (one more host synchronisation) and splits when it exceeds both min_longest and
- * P / 1024 (P: pairs of the launch; about half the pairs each of the chip's ~2048
- * resident workgroups would get were the work spread evenly, since the split render
- * makes about two passes over every pair).  Each tile's
- * depth-ordered list is then cut into segments of seg_len pairs (0: about 16384
- * segments in all, at least 384 pairs each), each rendered by its own workgroup:
- * one pass takes every segment's per-pixel transmittance product (Eq. 4's factors
- * 1 - alpha, ending with the one that takes it below T_min), a second composites each
- * segment from the product of the segments in front of it, and a last step sums the
- * segments up to the one where the pixel terminated.  The image equals the
- * one-workgroup-per-tile render up to the rounding order of those products.
- * Arguments <= 0 restore the defaults (2048 tiles, 2048 pairs, seg_len 0).
+ * a large scene, or a low resolution where a few tiles hold most pairs).  In a forward
+ * call without training state, pair counting or per-ray order, every view with fewer
+ * than max_tiles tiles has its longest list and its pair count P_v read back after the
+ * tile sort (one more host synchronisation), and is split when its longest list
+ * exceeds both min_longest and P_v / 1024 (about half the pairs each of the chip's
+ * ~2048 resident workgroups would get were the view's work spread evenly, since the
+ * split render makes about two passes over every pair).  The decision and the segment
+ * length depend on the view alone, so a view renders the same in any call.  Each
+ * tile's depth-ordered list of a split view is cut into segments of seg_len pairs
+ * (0: max(384, P_v / 16384)), each rendered by its own workgroup: one pass takes every
+ * segment's per-pixel transmittance product (Eq. 4's factors 1 - alpha, ending with the
+ * one that takes it below T_min), a second composites each segment from the product of
+ * the segments in front of it, and a last step sums the segments up to the one where
+ * the pixel terminated.  The image equals the one-workgroup-per-tile render up to the
+ * rounding order of those products.  The other views of the call render in whole
+ * tiles.  Arguments <= 0 restore the defaults (2048 tiles, 2048 pairs, seg_len 0).
  * Process-wide; calls already enqueued keep the values they were issued with. */
 void cg_set_tile_split(int64_t max_tiles, int64_t min_longest, int64_t seg_len);
+
+/* Scratch guard bands (a debugging aid, off by default; extension of the renderer, not
+ * part of the paper's method).  mode 1: every scratch buffer of the forward and
+ * backward calls is followed by a 256-byte band of a fixed 32-bit pattern, written
+ * before the call's kernels and compared after them (one more host synchronisation
+ * per call); a changed word makes the call return CG_ERR_STATE, naming the number of
+ * changed words, and adds it to cg_debug_guard_violations().  mode 2: as 1, and the
+ * host overwrites one word of the call's first band before the comparison, so that a
+ * test can see the check fire without a kernel writing out of bounds.  mode 0 (or any
+ * other value): off.  Process-wide; takes effect for calls issued afterwards.  Images
+ * and gradients do not depend on the mode. */
+void cg_debug_set_scratch_guards(int32_t mode);
+/* Total number of changed guard words found since the library was loaded. */
+int64_t cg_debug_guard_violations(void);
 
 /* Returns the library's cached scratch memory to the device. */
 cg_status cg_release_cached_memory(void);

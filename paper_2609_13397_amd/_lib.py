@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libconegaus
 
 CG_OK = 0
 STATUS_NAMES = {0: "CG_OK", -1: "CG_ERR_INVALID_ARG", -2: "CG_ERR_UNSUPPORTED", -3: "CG_ERR_OUT_OF_MEMORY",
-                -4: "CG_ERR_HIP", -5: "CG_ERR_STATE"}
+                -4: "CG_ERR_HIP", -5: "CG_ERR_STATE", -6: "CG_ERR_TIMEOUT"}
 
 
 class CgError(RuntimeError):
@@ -81,6 +81,8 @@ SIGNATURES = {
     "cg_profile_enable": (None, [C.c_int]),
     "cg_profile_enable_stages": (None, [C.c_uint32]),
     "cg_set_tile_split": (None, [C.c_int64, C.c_int64, C.c_int64]),
+    "cg_debug_set_scratch_guards": (None, [C.c_int32]),
+    "cg_debug_guard_violations": (C.c_int64, []),
     "cg_profile_collect": (C.c_int, []),
     "cg_profile_read": (None, [_vp, _vp]),
     "cg_profile_valu_probe": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp]),

@@ -27,9 +27,9 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *COMMON, "-x", "hip", "-c", src, "-o", obj]
+def _compile(src: str, verbose: bool, out_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = ["hipcc", *COMMON, *extra, "-x", "hip", "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,6 +49,20 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+def build_variant(out: str, extra_compile=(), extra_link=(), verbose: bool = False, jobs: int = 8) -> str:
+    """The library built into `out` with extra compiler and linker flags (objects in a
+    folder `obj` beside it), e.g. an instrumented build for tests of the host code."""
+    out_dir = os.path.join(os.path.dirname(os.path.abspath(out)), "obj")
+    os.makedirs(out_dir, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose, out_dir, tuple(extra_compile)), sources()))
+    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-fPIC", *extra_link, "-o", out, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -9,14 +9,16 @@
 // across the wave, reading the group cones through the scalar cache) and records the
 // groups it overlaps.  Phase 2: the wave walks the lanes' hit groups together, one
 // lane per member tile, reading the group-major member copy (one coalesced 1 KiB
-// load per group), so the 64 tile tests of a group run as one vector step and their
-// ballot gives both the count and, in the emit pass, each pair's position.
+// load per group, several groups ahead), so the 64 tile tests of a group run as one
+// vector step and their ballot gives both the count and, in the emit pass, each
+// pair's position.
 #include "camera_dev.hpp"
 
 namespace cg {
 
-constexpr int kMaxGroupHits = 16;
+constexpr int kMaxGroupHits = kBinHitList;
 constexpr int kPhase1Unroll = 8;
+constexpr int kPhase2Depth = 4;
 
 __device__ __forceinline__ float readlane_f(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -28,119 +30,185 @@ __device__ __forceinline__ uint32_t readlane_u(uint32_t x, int l) {
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restrict__ cams,
                                              const float4* __restrict__ cone, const float4* __restrict__ groups,
-                                             const float4* __restrict__ members,
-                                             const uint32_t* __restrict__ member_tile, uint32_t* __restrict__ counts,
+                                             const float4* __restrict__ members, uint32_t* __restrict__ counts,
                                              const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
-                                             uint32_t* __restrict__ vals, uint32_t* __restrict__ slot_gid) {
-  __shared__ uint16_t hits[4][64][kMaxGroupHits];
+                                             uint32_t* __restrict__ vals, uint32_t* __restrict__ slot_gid,
+                                             uint8_t* __restrict__ hit_n, uint16_t* __restrict__ hit_list) {
+  __shared__ __align__(16) uint16_t hitbuf[4][64 * kMaxGroupHits];  // per wave: the lanes' hit groups
+  __shared__ uint32_t flat[4][64 * kMaxGroupHits];
   const int v = blockIdx.y;
   const DevCamera& c = cams[v];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint16_t* __restrict__ hits = hitbuf[wave] + lane * kMaxGroupHits;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = i < n;
   const int64_t gv = (int64_t)v * n + i;
   const float4 cn = in ? cone[gv] : make_float4(0.f, 0.f, 1.f, kChordNever);
   const int ng = c.groups_x * c.groups_y;
   const float4* __restrict__ vgroups = groups + c.group_offset;
+  const float4* __restrict__ vmem = members + (int64_t)c.group_offset * kGroupTiles + lane;
+  const uint32_t my_base = (EMIT && in) ? offsets[gv] : 0u;
+  const float inv_gx = 1.f / (float)c.groups_x;
+  uint32_t my_count = 0;
 
-  // phase 1: overlapping groups of this lane's Gaussian.  The group cones are loaded
-  // kPhase1Unroll at a time before any is tested: the LDS writes of the hits share the
-  // scalar loads' wait counter, so loads interleaved with them would be waited for one
-  // at a time.
+  // phase 1: overlapping groups of this lane's Gaussian.  The count pass tests them and
+  // keeps each Gaussian's list (up to kMaxGroupHits groups, ascending, and their number)
+  // for the emit pass, which reads it back instead of testing again.
   int nh = 0;
-  if (__ballot(cn.w >= 0.f) != 0) {
-    int gi = 0;
-    for (; gi + kPhase1Unroll <= ng; gi += kPhase1Unroll) {
-      float4 G[kPhase1Unroll];
+  if (EMIT) {
+    if (in) {
+      nh = (int)hit_n[gv];
+      const uint4* src = reinterpret_cast<const uint4*>(hit_list + gv * kMaxGroupHits);
+      uint4* dst = reinterpret_cast<uint4*>(hits);
+      dst[0] = src[0];
+      dst[1] = src[1];
+    }
+  } else {
+    if (__ballot(cn.w >= 0.f) != 0) {
+      int gi = 0;
+      for (; gi + kPhase1Unroll <= ng; gi += kPhase1Unroll) {
+        float4 G[kPhase1Unroll];
 #pragma unroll
-      for (int u = 0; u < kPhase1Unroll; ++u) G[u] = vgroups[gi + u];
-      bool h[kPhase1Unroll];
+        for (int u = 0; u < kPhase1Unroll; ++u) G[u] = vgroups[gi + u];
+        bool h[kPhase1Unroll];
 #pragma unroll
-      for (int u = 0; u < kPhase1Unroll; ++u) h[u] = chords_overlap(G[u], cn.x, cn.y, cn.z, cn.w);
+        for (int u = 0; u < kPhase1Unroll; ++u) h[u] = chords_overlap(G[u], cn.x, cn.y, cn.z, cn.w);
 #pragma unroll
-      for (int u = 0; u < kPhase1Unroll; ++u) {
-        if (h[u]) {
-          if (nh < kMaxGroupHits) hits[wave][lane][nh] = (uint16_t)(gi + u);
+        for (int u = 0; u < kPhase1Unroll; ++u) {
+          if (h[u]) {
+            if (nh < kMaxGroupHits) hits[nh] = (uint16_t)(gi + u);
+            ++nh;
+          }
+        }
+      }
+      for (; gi < ng; ++gi) {
+        if (chords_overlap(vgroups[gi], cn.x, cn.y, cn.z, cn.w)) {
+          if (nh < kMaxGroupHits) hits[nh] = (uint16_t)gi;
           ++nh;
         }
       }
     }
-    for (; gi < ng; ++gi) {
-      if (chords_overlap(vgroups[gi], cn.x, cn.y, cn.z, cn.w)) {
-        if (nh < kMaxGroupHits) hits[wave][lane][nh] = (uint16_t)gi;
-        ++nh;
-      }
+    if (in) {
+      hit_n[gv] = (uint8_t)min(nh, 255);
+      const uint4* src = reinterpret_cast<const uint4*>(hits);
+      uint4* dst = reinterpret_cast<uint4*>(hit_list + gv * kMaxGroupHits);
+      dst[0] = src[0];
+      dst[1] = src[1];
     }
   }
 
-  // phase 2: tile tests, one lane per member tile of a hit group
-  uint32_t my_count = 0;
-  const uint32_t my_base = (EMIT && in) ? offsets[gv] : 0u;
-  const float4* __restrict__ vmem = members + (int64_t)c.group_offset * kGroupTiles + lane;
-  const uint32_t* __restrict__ vtile = member_tile + (int64_t)c.group_offset * kGroupTiles + lane;
-  for (int l = 0; l < 64; ++l) {
-    const int nh_l = __builtin_amdgcn_readlane(nh, l);
-    if (nh_l == 0) continue;
-    const float cx = readlane_f(cn.x, l), cy = readlane_f(cn.y, l), cz = readlane_f(cn.z, l);
-    const float cw = readlane_f(cn.w, l);
-    const uint32_t base = EMIT ? readlane_u(my_base, l) : 0u;
-    const bool ovf = nh_l > kMaxGroupHits;
-    uint32_t cnt = 0;
-    // one hit group: the ballot of its member-tile tests gives the pairs and their positions
-    auto group = [&](int gi, const float4& T) {
-      const bool hit = chords_overlap(T, cx, cy, cz, cw);
-      const uint64_t m = __ballot(hit);
-      if (EMIT && hit) {
-        const uint32_t pos = base + cnt + (uint32_t)__popcll(m & __lanemask_lt());
-        const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63) + l);
-        keys[pos] = vtile[gi * kGroupTiles];
-        if (slot_gid) {
-          vals[pos] = pos;
-          slot_gid[pos] = gid;
-        } else {
-          vals[pos] = gid;
-        }
+  // phase 2: tile tests, one lane per member tile of a hit group.
+  // One hit group of lane l's Gaussian: m holds the member tiles it overlaps.  Groups
+  // of one lane come one after the other, in ascending order; cur, cnt and the cone /
+  // base registers follow the lane being walked.
+  int cur = -1;
+  float cx = 0.f, cy = 0.f, cz = 0.f, cw = 0.f;
+  uint32_t base = 0u, cnt = 0u;
+  auto take_lane = [&](int l) {
+    if (l == cur) return;
+    if (lane == cur) my_count = cnt;
+    cur = l;
+    cnt = 0u;
+    cx = readlane_f(cn.x, l);
+    cy = readlane_f(cn.y, l);
+    cz = readlane_f(cn.z, l);
+    cw = readlane_f(cn.w, l);
+    if (EMIT) base = readlane_u(my_base, l);
+  };
+  auto group_hits = [&](int l, int gi, uint64_t m) {
+    if (EMIT && ((m >> lane) & 1ull)) {
+      const uint32_t pos = base + cnt + (uint32_t)__popcll(m & __lanemask_lt());
+      // gi / groups_x in float32: exact for gi < 2^16 (the quotient is at least
+      // 0.5 / groups_x from an integer, the rounding error below 2^16 * 2^-23 / groups_x)
+      const int gy = (int)(((float)gi + 0.5f) * inv_gx), gx = gi - gy * c.groups_x;
+      const int tx = gx * kGroup + (lane % kGroup), ty = gy * kGroup + lane / kGroup;
+      const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63) + l);
+      keys[pos] = (uint32_t)(c.tile_offset + ty * c.tiles_x + tx);
+      if (slot_gid) {
+        vals[pos] = pos;
+        slot_gid[pos] = gid;
+      } else {
+        vals[pos] = gid;
       }
-      cnt += (uint32_t)__popcll(m);
-    };
-    if (!ovf) {
-      // software-pipelined: the next hit group's member cones load while this one is tested
-      int gi_next = __builtin_amdgcn_readfirstlane((int)hits[wave][l][0]);
-      float4 T_next = vmem[gi_next * kGroupTiles];
-      for (int h = 0; h < nh_l; ++h) {
-        const int gi = gi_next;
-        const float4 T = T_next;
-        if (h + 1 < nh_l) {
-          gi_next = __builtin_amdgcn_readfirstlane((int)hits[wave][l][h + 1]);
-          T_next = vmem[gi_next * kGroupTiles];
-        }
-        group(gi, T);
-      }
-    } else {
-      for (int gi = 0; gi < ng; ++gi)
-        if (chords_overlap(vgroups[gi], cx, cy, cz, cw)) group(gi, vmem[gi * kGroupTiles]);
     }
-    if (lane == l) my_count = cnt;
+    cnt += (uint32_t)__popcll(m);
+  };
+
+  // The wave's hit groups (lane by lane, each lane's in ascending group order) are
+  // laid out as one list in LDS, and the member cones of the next kPhase2Depth entries
+  // load while the current one is tested: the walk waits on one round trip per
+  // kPhase2Depth groups, not per group.  Lanes with more than kMaxGroupHits groups are
+  // walked afterwards.
+  const uint64_t ovf = __ballot(nh > kMaxGroupHits);
+  {
+    // exclusive prefix of the listed counts over the wave (lanes below this one)
+    const int listed = nh > kMaxGroupHits ? 0 : nh;
+    int incl = listed;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+    const int start = incl - listed;
+    for (int h = 0; h < listed; ++h) flat[wave][start + h] = (uint32_t)(lane << 16) | hits[h];
+    // the list is read by the whole wave below (LDS writes and reads of one wave are in order)
+    __builtin_amdgcn_wave_barrier();
+    float4 T[kPhase2Depth];
+    uint32_t E[kPhase2Depth];  // list entries (lane << 16 | group)
+    // entries past the end of the list repeat its last one (loaded, never tested), so
+    // that every load is unconditional and each test waits for its own load only
+    auto fetch = [&](int u, int f) {
+      E[u] = (uint32_t)__builtin_amdgcn_readfirstlane((int)flat[wave][min(f, total - 1)]);
+      T[u] = vmem[(int)(E[u] & 0xffffu) * kGroupTiles];
+    };
+    if (total > 0) {
+#pragma unroll
+      for (int u = 0; u < kPhase2Depth; ++u) fetch(u, u);
+      for (int f0 = 0; f0 < total; f0 += kPhase2Depth) {
+#pragma unroll
+        for (int u = 0; u < kPhase2Depth; ++u) {
+          const int f = f0 + u;
+          const int l = (int)(E[u] >> 16);
+          const bool live = f < total;
+          if (live) take_lane(l);
+          const uint64_t m = __ballot(live && chords_overlap(T[u], cx, cy, cz, cw));
+          if (live) group_hits(l, (int)(E[u] & 0xffffu), m);
+          fetch(u, f + kPhase2Depth);  // this slot's entry kPhase2Depth ahead
+        }
+      }
+    }
   }
+  // lanes whose hit groups overflowed the list: every group tested again, one lane at a time
+  for (uint64_t om = ovf; om; om &= om - 1) {
+    const int l = (int)__builtin_ctzll(om);
+    take_lane(l);
+    for (int gi = 0; gi < ng; ++gi) {
+      if (!chords_overlap(vgroups[gi], cx, cy, cz, cw)) continue;
+      group_hits(l, gi, __ballot(chords_overlap(vmem[gi * kGroupTiles], cx, cy, cz, cw)));
+    }
+  }
+  if (lane == cur) my_count = cnt;
   if (!EMIT && in) counts[gv] = my_count;
 }
 
 hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
-                            const float4* members, uint32_t* counts, hipStream_t s) {
+                            const float4* members, uint32_t* counts, uint8_t* hit_n, uint16_t* hit_list,
+                            hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
-  k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, nullptr, counts, nullptr, nullptr, nullptr,
-                                          nullptr);
+  k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, counts, nullptr, nullptr, nullptr, nullptr,
+                                          hit_n, hit_list);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
-                           const float4* members, const uint32_t* member_tile, const uint32_t* offsets,
-                           uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, hipStream_t s) {
+                           const float4* members, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
+                           uint32_t* slot_gid, uint8_t* hit_n, uint16_t* hit_list, hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
-  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, member_tile, nullptr, offsets, keys, vals,
-                                         slot_gid);
+  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, nullptr, offsets, keys, vals, slot_gid,
+                                         hit_n, hit_list);
   return hipGetLastError();
 }
 

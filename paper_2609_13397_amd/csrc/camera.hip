@@ -106,8 +106,7 @@ hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles
 // contend across the XCDs).
 __global__ __launch_bounds__(64) void k_group_cones(const DevCamera* __restrict__ cams, int n_views,
                                                    const TileCone* __restrict__ tiles, float4* __restrict__ groups,
-                                                   float4* __restrict__ members, uint32_t* __restrict__ member_tile,
-                                                   float* __restrict__ view_cmax) {
+                                                   float4* __restrict__ members, float* __restrict__ view_cmax) {
   const int g = blockIdx.x;
   const int v = view_of_group(cams, n_views, g);
   const DevCamera& c = cams[v];
@@ -115,14 +114,9 @@ __global__ __launch_bounds__(64) void k_group_cones(const DevCamera* __restrict_
   const int gx = lg % c.groups_x, gy = lg / c.groups_x;
   const int tx = gx * kGroup + (threadIdx.x % kGroup), ty = gy * kGroup + (threadIdx.x / kGroup);
   TileCone tc{0.f, 0.f, 1.f, -1.f, 0.f, 1.f, 0.f, 0.f};
-  uint32_t tile = 0;
-  if (tx < c.tiles_x && ty < c.tiles_y) {
-    tile = (uint32_t)(c.tile_offset + ty * c.tiles_x + tx);
-    tc = tiles[tile];
-  }
+  if (tx < c.tiles_x && ty < c.tiles_y) tc = tiles[c.tile_offset + ty * c.tiles_x + tx];
   const bool live = tc.beta >= 0.f;
   members[(int64_t)g * kGroupTiles + threadIdx.x] = make_float4(tc.ax, tc.ay, tc.az, chord_radius(tc.beta));
-  member_tile[(int64_t)g * kGroupTiles + threadIdx.x] = tile;
   float sx = live ? tc.ax : 0.f, sy = live ? tc.ay : 0.f, sz = live ? tc.az : 0.f, cnt = live ? 1.f : 0.f;
   float bmax = live ? tc.beta : -1.f, cm = live ? tc.cmax : 0.f;
   for (int o = 32; o > 0; o >>= 1) {
@@ -155,10 +149,10 @@ __global__ __launch_bounds__(64) void k_group_cones(const DevCamera* __restrict_
 }
 
 hipError_t launch_group_cones(const DevCamera* cams, int n_views, int total_groups, const TileCone* tiles,
-                              float4* groups, float4* members, uint32_t* member_tile, float* view_cmax,
+                              float4* groups, float4* members, float* view_cmax,
                               hipStream_t s) {
   if (total_groups == 0) return hipSuccess;
-  k_group_cones<<<dim3(total_groups), dim3(kGroupTiles), 0, s>>>(cams, n_views, tiles, groups, members, member_tile,
+  k_group_cones<<<dim3(total_groups), dim3(kGroupTiles), 0, s>>>(cams, n_views, tiles, groups, members,
                                                                 view_cmax);
   return hipGetLastError();
 }
@@ -171,6 +165,18 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_fill_u32<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+// Counts the words of g[0, n) that differ from v (guard bands after scratch buffers).
+__global__ void k_guard_check(const uint32_t* g, int n, uint32_t v, uint32_t* bad) {
+  uint32_t k = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) k += g[i] != v;
+  if (k) atomicAdd(bad, k);
+}
+
+hipError_t launch_guard_check(const uint32_t* g, int n, uint32_t v, uint32_t* bad, hipStream_t s) {
+  k_guard_check<<<dim3(1), dim3(64), 0, s>>>(g, n, v, bad);
   return hipGetLastError();
 }
 

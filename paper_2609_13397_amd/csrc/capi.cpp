@@ -229,19 +229,20 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     DevCamera* dcams;
     TileCone* tiles;
     float4 *groups, *members, *pix, *cone;
-    uint32_t *member_tile, *depth_key, *counts, *offsets, *items, *items_alt, *counts_sorted, *offs_sorted;
+    uint32_t *depth_key, *counts, *offsets, *items, *items_alt, *counts_sorted, *offs_sorted;
     float* view_cmax;
     unsigned long long* pair_total;
     Record* rec;
     uint64_t *dkeys, *dkeys_alt;
     void *scan_tmp, *dsort_tmp;
+    uint8_t* hit_n;
+    uint16_t* hit_list;
     {
       Carve c;
       c.add(&dcams, n_views);
       c.add(&tiles, total_tiles);
       c.add(&groups, total_groups);
       c.add(&members, total_groups * kGroupTiles);
-      c.add(&member_tile, total_groups * kGroupTiles);
       c.add(&view_cmax, n_views);
       c.add(&pair_total, 1);
       c.add(&pix, std::max<int64_t>(total_tiles, 1) * kTilePx * 4);
@@ -249,6 +250,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       c.add(&depth_key, nv1);
       c.add(&cone, nv1);
       c.add(&counts, nv1);
+      c.add(&hit_n, nv1);
+      c.add(&hit_list, nv1 * kBinHitList);
       c.add(&offsets, nv1);
       c.add_bytes(&scan_tmp, scan_temp_bytes(nv));
       c.add(&dkeys, nv1);
@@ -267,7 +270,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(view_cmax), 0u, n_views, s));
       CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(pair_total), 0u, 2, s));
       CG_HIP(launch_tile_cones(dcams, n_views, (int)total_tiles, o.fs, tiles, pix, s));
-      CG_HIP(launch_group_cones(dcams, n_views, (int)total_groups, tiles, groups, members, member_tile,
+      CG_HIP(launch_group_cones(dcams, n_views, (int)total_groups, tiles, groups, members,
                                 view_cmax, s));
     }
     {
@@ -276,7 +279,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     }
     {
       ProfScope ps(ST_BIN_COUNT, s);
-      CG_HIP(launch_bin_count(n, n_views, dcams, cone, groups, members, counts, s));
+      CG_HIP(launch_bin_count(n, n_views, dcams, cone, groups, members, counts, hit_n, hit_list, s));
     }
     // compositing order of the (view, Gaussian) items, then pair offsets in that order
     const int view_bits = bits_for(std::max(n_views - 1, 1));
@@ -362,8 +365,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     if (P > 0) {
       {
         ProfScope ps(ST_BIN_EMIT, s);
-        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, member_tile, offsets, keys, vals,
-                               slot_gid, s));
+        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, offsets, keys, vals, slot_gid, hit_n,
+                               hit_list, s));
       }
       {
         ProfScope ps(ST_SORT, s);
@@ -451,6 +454,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       stats->n_segments = split ? (int32_t)sp.max_segs : 0;
       stats->max_tile_pairs = max_tile_pairs;
     }
+    sc.check_guards();
     if (st) {
       st->g = g;
       st->opts = o;

@@ -134,13 +134,14 @@ hipError_t launch_unproject(const DevCamera* cam, int64_t n, const float* pix_xy
 hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles, float fs, TileCone* tiles,
                              float4* pix, hipStream_t s);
 // Per 8x8 tile group: its chord cone (groups), and a group-major copy of its 64 member
-// tiles' chord cones (members, kChordNever for tiles outside the view) with their
-// global tile indices (member_tile).  view_cmax: per-view maximum footprint
-// coefficient, zeroed beforehand.
+// tiles' chord cones (members, kChordNever for tiles outside the view; member l of
+// group (gx, gy) is tile (8 gx + l % 8, 8 gy + l / 8)).  view_cmax: per-view maximum
+// footprint coefficient, zeroed beforehand.
 hipError_t launch_group_cones(const DevCamera* cams, int n_views, int total_groups, const TileCone* tiles,
-                              float4* groups, float4* members, uint32_t* member_tile, float* view_cmax,
+                              float4* groups, float4* members, float* view_cmax,
                               hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_guard_check(const uint32_t* g, int n, uint32_t v, uint32_t* bad, hipStream_t s);
 
 // preprocess.hip
 hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,
@@ -148,11 +149,16 @@ hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_vi
 
 // binning.hip
 // cone: per (view, Gaussian) chord cone of its influence cone (from the preprocess)
+// The count pass keeps each (view, Gaussian) item's overlapping tile groups for the
+// emit pass: hit_n[item] (their number, capped at 255) and hit_list[16 item ...] (the
+// first 16, ascending).
+constexpr int kBinHitList = 16;
 hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
-                            const float4* members, uint32_t* counts, hipStream_t s);
+                            const float4* members, uint32_t* counts, uint8_t* hit_n, uint16_t* hit_list,
+                            hipStream_t s);
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
-                           const float4* members, const uint32_t* member_tile, const uint32_t* offsets,
-                           uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, hipStream_t s);
+                           const float4* members, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
+                           uint32_t* slot_gid, uint8_t* hit_n, uint16_t* hit_list, hipStream_t s);
 // compositing keys (view << 31 | float32 depth key) and item indices; the 32-bit form
 // holds up to two views
 hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,

@@ -172,48 +172,124 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (valid && !done && Ttr != (inside ? final_T[p] : 1.f)) atomicAdd(mismatch, 1u);
 }
 
-// Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt),
-// added in slot order.  The items are taken in compositing order (counts, offsets
-// and items per position), whose slot ranges follow each other, so the partials are
-// read front to back.  20 lanes per item, one gradient component each, 3 items per
-// wave step: a wave waits on the largest of 3 slot counts instead of 64, and each
-// slot's row is read as one contiguous 80-byte segment.  The waves stride over the
-// item triples and load the next step's count and offset while the current step's
-// rows are in flight: the kernel is bound by memory latency, not bandwidth.
-constexpr int kReduceItemsPerWave = 64 / kGradLen;
+// Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt).
+// The items are taken in compositing order (counts, offsets and items per position),
+// whose slot ranges follow each other, so the partials are read front to back.
+// 5 lanes per item, each holding 4 of the 20 components of a row (one 16-byte load
+// per lane; a row is one contiguous 80-byte segment), 12 items per wave step.  An
+// item's rows are fetched kReduceBatch at a time, all loads of a batch in flight
+// together (one round trip to memory whatever the count, no serial remainder), and
+// added in slot order.  An item with more than kReduceLong slots (a Gaussian over
+// many tiles) would hold its wave for cnt / kReduceBatch round trips, long after the
+// rest of the grid has finished: it is only listed here, and k_reduce_long sums it
+// with a whole workgroup.
+constexpr int kReduceLanes = kGradLen / 4;
+constexpr int kReduceItemsPerWave = 64 / kReduceLanes;
+constexpr int kReduceBatch = 8;
+constexpr int kReduceLong = 128;
 constexpr int kReduceBlocks = 16384;
+constexpr int kReduceLongBlocks = 2048;
+typedef float red4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_reduce_items(const uint32_t* __restrict__ counts,
                                                       const uint32_t* __restrict__ offsets,
                                                       const uint32_t* __restrict__ items, int64_t nv,
                                                       const float* __restrict__ partial,
-                                                      float* __restrict__ item_grad) {
+                                                      float* __restrict__ item_grad,
+                                                      uint32_t* __restrict__ long_items,
+                                                      uint32_t* __restrict__ n_long) {
   const int lane = threadIdx.x & 63;
-  const int sub = lane / kGradLen, q = lane - sub * kGradLen;
+  const int sub = lane / kReduceLanes, c = lane - sub * kReduceLanes;
   if (sub >= kReduceItemsPerWave) return;
   const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int64_t it = wave * kReduceItemsPerWave + sub;
-  uint32_t cnt = 0, off = 0;
+  uint32_t cnt = 0, off = 0, dst = 0;
   if (it < nv) {
     cnt = counts[it];
     off = offsets[it];
+    dst = items[it];
   }
-  for (; it < nv; wave += n_waves) {
+  while (it < nv) {
+    // the next step's count, offset and destination load while this step's rows are in flight
     const int64_t next = (wave + n_waves) * kReduceItemsPerWave + sub;
-    uint32_t ncnt = 0, noff = 0;
+    uint32_t ncnt = 0, noff = 0, ndst = 0;
     if (next < nv) {
       ncnt = counts[next];
       noff = offsets[next];
+      ndst = items[next];
     }
-    const float* src = partial + (int64_t)off * kGradLen + q;
-    float acc = 0.f;
-#pragma unroll 8
-    for (uint32_t k = 0; k < cnt; ++k) acc += src[(int64_t)k * kGradLen];
-    item_grad[(int64_t)items[it] * kGradLen + q] = acc;
+    if (cnt > (uint32_t)kReduceLong) {
+      if (c == 0) long_items[atomicAdd(n_long, 1u)] = (uint32_t)it;
+    } else {
+      const red4* src = reinterpret_cast<const red4*>(partial + (int64_t)off * kGradLen) + c;
+      red4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (uint32_t k = 0; k < cnt; k += kReduceBatch) {
+        // rows past the end re-read the last row (already on its way) and count as zero
+        red4 v[kReduceBatch];
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u)
+          v[u] = __builtin_nontemporal_load(src + (int64_t)min(k + u, cnt - 1u) * kReduceLanes);
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u)
+          if (k + u < cnt) acc += v[u];
+      }
+      reinterpret_cast<red4*>(item_grad + (int64_t)dst * kGradLen)[c] = acc;
+    }
+    wave += n_waves;
     it = next;
     cnt = ncnt;
     off = noff;
+    dst = ndst;
+  }
+}
+
+// The items k_reduce_items listed (more than kReduceLong slots), one workgroup each:
+// its 48 lane groups take every 48th slot, kReduceLongBatch slots in flight per group,
+// and their 48 partial sums are added in group order through LDS.  The order of the
+// list does not matter: each item's sum is formed the same way wherever it is listed.
+constexpr int kReduceLongGroups = 256 / 64 * kReduceItemsPerWave;  // 48
+constexpr int kReduceLongBatch = 4;
+
+__global__ __launch_bounds__(256) void k_reduce_long(const uint32_t* __restrict__ counts,
+                                                     const uint32_t* __restrict__ offsets,
+                                                     const uint32_t* __restrict__ items,
+                                                     const float* __restrict__ partial,
+                                                     float* __restrict__ item_grad,
+                                                     const uint32_t* __restrict__ long_items,
+                                                     const uint32_t* __restrict__ n_long) {
+  __shared__ red4 part[kReduceLongGroups][kReduceLanes];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sub = lane / kReduceLanes, c = lane - sub * kReduceLanes;
+  const bool active = sub < kReduceItemsPerWave;
+  const int grp = wave * kReduceItemsPerWave + sub;
+  const uint32_t total = *n_long;
+  for (uint32_t e = blockIdx.x; e < total; e += gridDim.x) {
+    const uint32_t it = long_items[e];
+    const uint32_t cnt = counts[it];
+    if (active) {
+      const red4* src = reinterpret_cast<const red4*>(partial + (int64_t)offsets[it] * kGradLen) + c;
+      red4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (uint32_t k = grp; k < cnt; k += kReduceLongGroups * kReduceLongBatch) {
+        red4 v[kReduceLongBatch];
+#pragma unroll
+        for (int u = 0; u < kReduceLongBatch; ++u) {
+          const uint32_t r = min(k + (uint32_t)(u * kReduceLongGroups), cnt - 1u);
+          v[u] = __builtin_nontemporal_load(src + (int64_t)r * kReduceLanes);
+        }
+#pragma unroll
+        for (int u = 0; u < kReduceLongBatch; ++u)
+          if (k + (uint32_t)(u * kReduceLongGroups) < cnt) acc += v[u];
+      }
+      part[grp][c] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kReduceLanes) {
+      red4 s = part[0][threadIdx.x];
+      for (int q = 1; q < kReduceLongGroups; ++q) s += part[q][threadIdx.x];
+      reinterpret_cast<red4*>(item_grad + (int64_t)items[it] * kGradLen)[threadIdx.x] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -390,11 +466,15 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
   Scratch sc(&st->alloc, s);
   float *partial, *item_grad;
   unsigned int* mismatch;
+  uint32_t *long_items, *n_long;
   {
     Carve c;
     c.add(&partial, (size_t)std::max<int64_t>(st->P, 1) * kGradLen);
     c.add(&item_grad, (size_t)nv * kGradLen);
     c.add(&mismatch, 4);
+    // items with more than kReduceLong slots: at most P / kReduceLong of them
+    c.add(&long_items, (size_t)(st->P / kReduceLong + 1));
+    c.add(&n_long, 1);
     sc.get(c);
   }
   CG_HIP(launch_fill_u32(mismatch, 0u, 1, s));
@@ -418,8 +498,12 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
     ProfScope ps(ST_BWD_REDUCE, s);
     const int64_t waves = (nv + kReduceItemsPerWave - 1) / kReduceItemsPerWave;
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, kReduceBlocks);
+    CG_HIP(launch_fill_u32(n_long, 0u, 1, s));
     k_reduce_items<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(st->counts, st->offsets, st->sorted_items, nv,
-                                                                partial, item_grad);
+                                                                partial, item_grad, long_items, n_long);
+    CG_HIP(hipGetLastError());
+    k_reduce_long<<<dim3(kReduceLongBlocks), dim3(256), 0, s>>>(st->counts, st->offsets, st->sorted_items, partial,
+                                                               item_grad, long_items, n_long);
     CG_HIP(hipGetLastError());
   }
   {
@@ -432,6 +516,7 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
   CG_HIP(hipMemcpyAsync(&host_mismatch, mismatch, 4, hipMemcpyDeviceToHost, s));
   CG_HIP(hipStreamSynchronize(s));
   st->replay_mismatches = host_mismatch;
+  sc.check_guards();
 }
 
 }  // namespace cg

@@ -130,6 +130,32 @@ void free_block(const cg_allocator& a, void* p, hipStream_t s) {
   else if (!a.alloc) pool_free(p, s);
 }
 
+void Scratch::get(const Carve& c) {
+  char* base = static_cast<char*>(get(c.bytes()));
+  c.place(base);
+  for (size_t off : c.guards()) {
+    uint32_t* g = reinterpret_cast<uint32_t*>(base + off);
+    CG_HIP(launch_fill_u32(g, kGuardWord, kGuardBytes / 4, s_));
+    guards_.push_back(g);
+  }
+}
+
+void Scratch::check_guards() {
+  if (guards_.empty()) return;
+  if (guard_mode() == 2) CG_HIP(launch_fill_u32(guards_.front(), ~kGuardWord, 1, s_));
+  uint32_t* bad = static_cast<uint32_t*>(get(16));
+  CG_HIP(launch_fill_u32(bad, 0u, 1, s_));
+  for (const uint32_t* g : guards_) CG_HIP(launch_guard_check(g, (int)(kGuardBytes / 4), kGuardWord, bad, s_));
+  uint32_t host_bad = 0;
+  CG_HIP(hipMemcpyAsync(&host_bad, bad, sizeof(host_bad), hipMemcpyDeviceToHost, s_));
+  CG_HIP(hipStreamSynchronize(s_));
+  if (host_bad) {
+    add_guard_violations(host_bad);
+    throw Error(CG_ERR_STATE, "scratch guard bands overwritten: " + std::to_string(host_bad) + " word(s) in " +
+                                  std::to_string(guards_.size()) + " guard bands");
+  }
+}
+
 void Scratch::release() {
   for (void* p : blocks_) free_block(user_, p, s_);
   blocks_.clear();
@@ -154,6 +180,8 @@ uint32_t g_prof_mask = 0;  // bit i: stage i is bracketed
 // split tile render thresholds (cg_set_tile_split)
 constexpr int64_t kSplitMaxTiles = 2048, kSplitMinLongest = 2048;
 std::atomic<int64_t> g_split_max_tiles{kSplitMaxTiles}, g_split_min_long{kSplitMinLongest}, g_split_len{0};
+std::atomic<int> g_guard_mode{0};
+std::atomic<int64_t> g_guard_violations{0};
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 double g_total_ms[ST_NUM];
@@ -174,6 +202,9 @@ hipEvent_t get_event() {
 }
 
 }  // namespace
+
+int guard_mode() { return g_guard_mode.load(); }
+void add_guard_violations(int64_t n) { g_guard_violations += n; }
 
 SplitPolicy split_policy() { return SplitPolicy{g_split_max_tiles.load(), g_split_min_long.load(), g_split_len.load()}; }
 
@@ -212,6 +243,10 @@ void cg_set_tile_split(int64_t max_tiles, int64_t min_longest, int64_t seg_len) 
   cg::g_split_min_long = min_longest > 0 ? min_longest : cg::kSplitMinLongest;
   cg::g_split_len = seg_len > 0 ? seg_len : 0;
 }
+
+void cg_debug_set_scratch_guards(int32_t mode) { cg::g_guard_mode = (mode >= 0 && mode <= 2) ? mode : 0; }
+
+int64_t cg_debug_guard_violations(void) { return cg::g_guard_violations.load(); }
 
 cg_status cg_profile_collect(void) {
   std::vector<cg::Pending> pend;

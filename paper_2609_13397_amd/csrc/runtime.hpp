@@ -36,9 +36,20 @@ void* pool_alloc(size_t bytes, hipStream_t s);
 void pool_free(void* p, hipStream_t s);
 void pool_release_all();
 
+// Guard bands (a debugging aid, off by default): while enabled, every buffer placed
+// by a Carve is followed by kGuardBytes holding kGuardWord, written before the call's
+// kernels run and compared after them; a changed word means some kernel wrote past
+// the end of its buffer.  Mode 2 also overwrites one guard word from the host before
+// the comparison, to show that the check reports it.
+constexpr size_t kGuardBytes = 256;
+constexpr uint32_t kGuardWord = 0xC3A5F00Du;
+int guard_mode();
+void add_guard_violations(int64_t n);
+
 // The buffers of one allocation phase, laid out back to back in one block: each
-// starts on a 256-byte boundary and has 16 bytes of slack after it.  add() records
-// where to store a buffer's address; place() stores them all once the block exists.
+// starts on a 256-byte boundary and has 16 bytes of slack after it (then its guard
+// band, when guard bands are on).  add() records where to store a buffer's address;
+// place() stores them all once the block exists.
 class Carve {
  public:
   template <class T>
@@ -47,12 +58,20 @@ class Carve {
   }
   void add_bytes(void** out, size_t bytes) {
     items_.push_back(Item{out, offset_});
-    offset_ += (bytes + 16 + 255) / 256 * 256;
+    size_t end = offset_ + bytes + 16;
+    if (guard_) {
+      end = (end + 3) / 4 * 4;
+      guards_.push_back(end);
+      end += kGuardBytes;
+    }
+    offset_ = (end + 255) / 256 * 256;
   }
   size_t bytes() const { return offset_ == 0 ? 256 : offset_; }
   void place(void* base) const {
     for (const Item& it : items_) *it.out = static_cast<char*>(base) + it.offset;
   }
+  // Offsets of the guard bands in the block (empty when guard bands are off).
+  const std::vector<size_t>& guards() const { return guards_; }
 
  private:
   struct Item {
@@ -60,7 +79,9 @@ class Carve {
     size_t offset;
   };
   std::vector<Item> items_;
+  std::vector<size_t> guards_;
   size_t offset_ = 0;
+  bool guard_ = guard_mode() != 0;
 };
 
 // A caller-provided device region that stands in for every allocation of a call.
@@ -85,8 +106,12 @@ class Scratch {
   T* get_n(size_t n) {
     return static_cast<T*>(get(n * sizeof(T) + 16));
   }
-  // One block for every buffer of `c` (one allocator call per phase).
-  void get(const Carve& c) { c.place(get(c.bytes())); }
+  // One block for every buffer of `c` (one allocator call per phase); writes the
+  // guard bands, if any.
+  void get(const Carve& c);
+  // Compares every guard band written so far with its pattern (synchronises the
+  // stream); throws CG_ERR_STATE if a word changed.  No-op without guard bands.
+  void check_guards();
   // Hands ownership of every block allocated so far to `out` (which releases them
   // later with the same allocator and stream).
   void transfer(std::vector<void*>& out) {
@@ -103,6 +128,7 @@ class Scratch {
   FixedRegion fixed_;
   size_t fixed_used_ = 0;
   std::vector<void*> blocks_;
+  std::vector<uint32_t*> guards_;
 };
 
 void free_block(const cg_allocator& a, void* p, hipStream_t s);

@@ -9,7 +9,8 @@
 // caps.  Requests that arrive while others are on the device are admitted as soon as
 // a worker and memory free up; the calls of different workers overlap on the GPU.
 // The per-view-launch baseline is the same server with one worker and one view per
-// call.  The scheduler is independent of the executor, so a CPU stand-in executor
+// call.  With a request time limit, requests still queued past it complete with
+// CG_ERR_TIMEOUT, unrendered.  The scheduler is independent of the executor, so a CPU stand-in executor
 // (a timed sleep) exercises admission, batching and cancellation without a GPU.
 #include <algorithm>
 #include <chrono>
@@ -55,13 +56,14 @@ struct cg_server {
   std::vector<cg_server_completion> done;
   size_t reserved = 0, peak_reserved = 0;
   int in_flight = 0;
-  int64_t next_id = 1, completed = 0, batches = 0, views = 0, max_batch_seen = 0;
+  int64_t next_id = 1, completed = 0, batches = 0, views = 0, max_batch_seen = 0, timed_out = 0;
   bool stopping = false;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::vector<std::thread> workers;
 
-  // Scratch estimate of one view: per (view, Gaussian) record, keys, cone and counts;
+  // Scratch estimate of one view: per (view, Gaussian) record, keys, cone, counts and
+  // tile-group list;
   // per pair the tile key and value (twice, for the sort) plus slack; per tile its
   // cones and its 256 slots of the 64-byte pixel ray buffer; per pixel the output
   // staging; when the launch is small enough to take the split tile render (which one
@@ -76,8 +78,35 @@ struct cg_server {
     const double segs = tiles < pol.max_tiles
                             ? (double)tiles + std::min((double)kSegTarget, pairs / (double)kMinSegLen)
                             : 0.0;
-    return (size_t)(sc.g.n * 192 + pairs * 24.0 + (double)tiles * (48.0 + 256.0 * 64.0) + (double)px * 8.0 + (1 << 20) +
+    return (size_t)(sc.g.n * 232 + pairs * 24.0 + (double)tiles * (48.0 + 256.0 * 64.0) + (double)px * 8.0 + (1 << 20) +
                     segs * 256.0 * 20.0);
+  }
+
+  // Completes every queued request older than the time limit with CG_ERR_TIMEOUT
+  // (caller holds mu).
+  void expire_locked() {
+    if (!(cfg.request_timeout_ms > 0.0)) return;
+    const double t = now_s(), limit = cfg.request_timeout_ms * 1e-3;
+    bool any = false;
+    for (auto it = queue.begin(); it != queue.end();) {
+      if (t - it->t_submit > limit) {
+        cg_server_completion c;
+        std::memset(&c, 0, sizeof(c));
+        c.request_id = it->id;
+        c.status = CG_ERR_TIMEOUT;
+        c.scene = it->scene;
+        c.t_submit = it->t_submit;
+        c.t_done = t;
+        done.push_back(c);
+        ++completed;
+        ++timed_out;
+        it = queue.erase(it);
+        any = true;
+      } else {
+        ++it;
+      }
+    }
+    if (any) cv_done.notify_all();
   }
 
   bool can_admit_head() const {
@@ -125,7 +154,14 @@ struct cg_server {
       SceneEntry scene;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stopping || can_admit_head(); });
+        for (;;) {
+          expire_locked();
+          if (stopping || can_admit_head()) break;
+          if (cfg.request_timeout_ms > 0.0)
+            cv_work.wait_for(lk, std::chrono::duration<double, std::milli>(cfg.request_timeout_ms));
+          else
+            cv_work.wait(lk);
+        }
         if (stopping) break;
         Request head = queue.front();
         queue.pop_front();
@@ -211,6 +247,7 @@ cg_status cg_server_create(const cg_server_config* cfg, cg_server** out) {
     CG_CHECK_ARG(cfg->max_batch_views >= 1 && cfg->max_batch_views <= 256, "max_batch_views must be in [1, 256]");
     CG_CHECK_ARG(cfg->max_batch_pixels >= 1, "max_batch_pixels must be >= 1");
     CG_CHECK_ARG(cfg->hbm_budget_bytes > 0, "hbm_budget_bytes must be > 0");
+    CG_CHECK_ARG(cfg->request_timeout_ms >= 0.0, "request_timeout_ms must be >= 0");
     *out = nullptr;
     cg_server* s = new cg_server();
     s->cfg = *cfg;
@@ -287,6 +324,7 @@ cg_status cg_server_poll(cg_server* s, cg_server_completion* out, int32_t capaci
   return guarded([&] {
     CG_CHECK_ARG(s && n_out && (capacity == 0 || out), "null argument");
     std::unique_lock<std::mutex> lk(s->mu);
+    s->expire_locked();
     if (s->done.empty() && wait_ms > 0)
       s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !s->done.empty(); });
     const int32_t n = (int32_t)std::min<size_t>((size_t)std::max(capacity, 0), s->done.size());
@@ -300,6 +338,7 @@ cg_status cg_server_drain(cg_server* s) {
   return guarded([&] {
     CG_CHECK_ARG(s, "null server");
     std::unique_lock<std::mutex> lk(s->mu);
+    s->expire_locked();
     s->cv_done.wait(lk, [&] { return s->queue.empty() && s->in_flight == 0; });
   });
 }
@@ -316,6 +355,7 @@ cg_status cg_server_get_stats(cg_server* s, cg_server_stats* out) {
     out->max_batch_views = s->max_batch_seen;
     out->reserved_bytes = (int64_t)s->reserved;
     out->peak_reserved_bytes = (int64_t)s->peak_reserved;
+    out->timed_out = s->timed_out;
   });
 }
 

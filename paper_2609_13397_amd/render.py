@@ -255,6 +255,17 @@ def set_tile_split(max_tiles: int = 0, min_longest: int = 0, seg_len: int = 0) -
     _lib.lib().cg_set_tile_split(int(max_tiles), int(min_longest), int(seg_len))
 
 
+def set_scratch_guards(mode: int) -> None:
+    """Scratch guard bands (cg_debug_set_scratch_guards): 0 off, 1 on, 2 on with one
+    band overwritten from the host before the check."""
+    _lib.lib().cg_debug_set_scratch_guards(int(mode))
+
+
+def guard_violations() -> int:
+    """Changed guard words found since the library was loaded (cg_debug_guard_violations)."""
+    return int(_lib.lib().cg_debug_guard_violations())
+
+
 def split_views(rgba: torch.Tensor, cams: Sequence[dict]) -> List[torch.Tensor]:
     """Per-view [h, w, 4] views of a flat forward output."""
     outs = []

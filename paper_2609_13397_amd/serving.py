@@ -19,7 +19,8 @@ from . import _lib
 class CgServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_batch_views", C.c_int32), ("n_workers", C.c_int32),
                 ("max_batch_pixels", C.c_int64), ("fake_executor", C.c_int32), ("device", C.c_int32),
-                ("fake_ns_per_pixel", C.c_double), ("fake_ns_per_call", C.c_double)]
+                ("fake_ns_per_pixel", C.c_double), ("fake_ns_per_call", C.c_double),
+                ("request_timeout_ms", C.c_double)]
 
 
 class CgServerCompletion(C.Structure):
@@ -31,7 +32,7 @@ class CgServerCompletion(C.Structure):
 class CgServerStats(C.Structure):
     _fields_ = [("queued", C.c_int64), ("in_flight", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
                 ("views", C.c_int64), ("max_batch_views", C.c_int64), ("reserved_bytes", C.c_int64),
-                ("peak_reserved_bytes", C.c_int64)]
+                ("peak_reserved_bytes", C.c_int64), ("timed_out", C.c_int64)]
 
 
 SERVER_SIGNATURES = {

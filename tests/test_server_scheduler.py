@@ -145,3 +145,42 @@ def test_cancel_queued_request_and_invalid_submit():
         s.submit(7, _cam(), 1)
     s.drain()
     s.close()
+
+
+def test_request_timeout_completes_unrendered():
+    """A request still queued past request_timeout_ms completes with CG_ERR_TIMEOUT and
+    is never handed to the executor; the one admitted at once completes normally."""
+    s = _server(n_workers=1, max_batch_views=1, fake_ns_per_call=80e6, fake_ns_per_pixel=0.0,
+                request_timeout_ms=20.0)
+    g, o, keep = _fake_scene()
+    sid = s.add_scene(g, o, keep)
+    ids = [s.submit(sid, _cam(), 1) for _ in range(4)]
+    s.drain()
+    done = {c.request_id: c for c in _collect(s, 4)}
+    assert done[ids[0]].status == 0
+    for rid in ids[1:]:
+        c = done[rid]
+        assert c.status == -6, c.status  # CG_ERR_TIMEOUT
+        assert c.t_done - c.t_submit >= 0.020
+        assert c.batch_views == 0 and c.t_start == 0.0  # never started
+    st = s.stats()
+    assert st["timed_out"] == 3 and st["batches"] == 1 and st["completed"] == 4
+    s.close()
+
+
+def test_request_timeout_generous_limit_changes_nothing():
+    s = _server(n_workers=2, max_batch_views=4, request_timeout_ms=10000.0)
+    g, o, keep = _fake_scene()
+    sid = s.add_scene(g, o, keep)
+    ids = [s.submit(sid, _cam(), 1) for _ in range(16)]
+    done = _collect(s, 16)
+    assert sorted(c.request_id for c in done) == sorted(ids)
+    assert all(c.status == 0 for c in done)
+    assert s.stats()["timed_out"] == 0
+    s.close()
+
+
+def test_negative_timeout_is_an_argument_error():
+    from paper_2609_13397_amd import serving
+    with pytest.raises(_lib.CgError, match="request_timeout_ms"):
+        serving.RenderServer(serving.default_config(fake_executor=1, request_timeout_ms=-1.0))
