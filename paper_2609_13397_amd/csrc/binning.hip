@@ -31,7 +31,8 @@ template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restrict__ cams,
                                              const float4* __restrict__ cone, const float4* __restrict__ groups,
                                              const float4* __restrict__ members, uint32_t* __restrict__ counts,
-                                             const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys,
+                                             const uint32_t* __restrict__ offsets,
+                                             const uint32_t* __restrict__ slot_offs, uint32_t* __restrict__ keys,
                                              uint32_t* __restrict__ vals, uint32_t* __restrict__ slot_gid,
                                              uint8_t* __restrict__ hit_n, uint16_t* __restrict__ hit_list) {
   __shared__ __align__(16) uint16_t hitbuf[4][64 * kMaxGroupHits];  // per wave: the lanes' hit groups
@@ -48,6 +49,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
   const float4* __restrict__ vgroups = groups + c.group_offset;
   const float4* __restrict__ vmem = members + (int64_t)c.group_offset * kGroupTiles + lane;
   const uint32_t my_base = (EMIT && in) ? offsets[gv] : 0u;
+  const uint32_t my_slot = (EMIT && in && slot_gid) ? slot_offs[gv] : 0u;
   const float inv_gx = 1.f / (float)c.groups_x;
   uint32_t my_count = 0;
 
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
   // base registers follow the lane being walked.
   int cur = -1;
   float cx = 0.f, cy = 0.f, cz = 0.f, cw = 0.f;
-  uint32_t base = 0u, cnt = 0u;
+  uint32_t base = 0u, slot0 = 0u, cnt = 0u;
   auto take_lane = [&](int l) {
     if (l == cur) return;
     if (lane == cur) my_count = cnt;
@@ -113,11 +115,15 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
     cy = readlane_f(cn.y, l);
     cz = readlane_f(cn.z, l);
     cw = readlane_f(cn.w, l);
-    if (EMIT) base = readlane_u(my_base, l);
+    if (EMIT) {
+      base = readlane_u(my_base, l);
+      if (slot_gid) slot0 = readlane_u(my_slot, l);
+    }
   };
   auto group_hits = [&](int l, int gi, uint64_t m) {
     if (EMIT && ((m >> lane) & 1ull)) {
-      const uint32_t pos = base + cnt + (uint32_t)__popcll(m & __lanemask_lt());
+      const uint32_t j = cnt + (uint32_t)__popcll(m & __lanemask_lt());
+      const uint32_t pos = base + j;
       // gi / groups_x in float32: exact for gi < 2^16 (the quotient is at least
       // 0.5 / groups_x from an integer, the rounding error below 2^16 * 2^-23 / groups_x)
       const int gy = (int)(((float)gi + 0.5f) * inv_gx), gx = gi - gy * c.groups_x;
@@ -125,8 +131,8 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
       const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63) + l);
       keys[pos] = (uint32_t)(c.tile_offset + ty * c.tiles_x + tx);
       if (slot_gid) {
-        vals[pos] = pos;
-        slot_gid[pos] = gid;
+        vals[pos] = slot0 + j;
+        slot_gid[slot0 + j] = gid;
       } else {
         vals[pos] = gid;
       }
@@ -198,17 +204,18 @@ hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
   k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, counts, nullptr, nullptr, nullptr, nullptr,
-                                          hit_n, hit_list);
+                                          nullptr, hit_n, hit_list);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
-                           const float4* members, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
-                           uint32_t* slot_gid, uint8_t* hit_n, uint16_t* hit_list, hipStream_t s) {
+                           const float4* members, const uint32_t* offsets, const uint32_t* slot_offs,
+                           uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, uint8_t* hit_n,
+                           uint16_t* hit_list, hipStream_t s) {
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
-  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, nullptr, offsets, keys, vals, slot_gid,
-                                         hit_n, hit_list);
+  k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, nullptr, offsets, slot_offs, keys, vals,
+                                         slot_gid, hit_n, hit_list);
   return hipGetLastError();
 }
 

@@ -237,6 +237,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     void *scan_tmp, *dsort_tmp;
     uint8_t* hit_n;
     uint16_t* hit_list;
+    uint32_t* slot_offs = nullptr;  // training: first gradient slot per item, in item order
     {
       Carve c;
       c.add(&dcams, n_views);
@@ -251,6 +252,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       c.add(&cone, nv1);
       c.add(&counts, nv1);
       c.add(&hit_n, nv1);
+      if (state_out) c.add(&slot_offs, nv1);
       c.add(&hit_list, nv1 * kBinHitList);
       c.add(&offsets, nv1);
       c.add_bytes(&scan_tmp, scan_temp_bytes(nv));
@@ -305,6 +307,10 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
         CG_HIP(launch_gather_total(counts, sorted_items, nv, counts_sorted, pair_total, s));
         CG_HIP(launch_exclusive_scan(counts_sorted, offs_sorted, nv, scan_tmp, s));
         CG_HIP(launch_scatter_u32(offs_sorted, sorted_items, nv, offsets, s));
+        // training: the pairs' gradient slots are laid out item by item (each item's
+        // slots contiguous, items in index order), so that the backward's per-item sums
+        // read and write in one front-to-back sweep
+        if (slot_offs) CG_HIP(launch_exclusive_scan(counts, slot_offs, nv, scan_tmp, s));
       }
       CG_HIP(hipMemcpyAsync(&host_total, pair_total, sizeof(host_total), hipMemcpyDeviceToHost, s));
     }
@@ -365,8 +371,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     if (P > 0) {
       {
         ProfScope ps(ST_BIN_EMIT, s);
-        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, offsets, keys, vals, slot_gid, hit_n,
-                               hit_list, s));
+        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, offsets, slot_offs, keys, vals, slot_gid,
+                               hit_n, hit_list, s));
       }
       {
         ProfScope ps(ST_SORT, s);
@@ -465,9 +471,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       st->total_px = total_px;
       st->P = P;
       st->rec = rec;
-      st->counts = counts_sorted;
-      st->offsets = offs_sorted;
-      st->sorted_items = sorted_items;
+      st->counts = counts;
+      st->offsets = slot_offs;
       st->sorted_slots = sslots;
       st->sorted_gid = sorted_gid;
       st->ranges = ranges;

@@ -156,9 +156,13 @@ constexpr int kBinHitList = 16;
 hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
                             const float4* members, uint32_t* counts, uint8_t* hit_n, uint16_t* hit_list,
                             hipStream_t s);
+// Emit pass: pair (tile, Gaussian) of item gv at positions offsets[gv] + j (compositing
+// order).  Inference: vals = Gaussian index.  Training (slot_offs, slot_gid non-null):
+// vals = the pair's gradient slot slot_offs[gv] + j, and slot_gid[slot] = Gaussian.
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
-                           const float4* members, const uint32_t* offsets, uint32_t* keys, uint32_t* vals,
-                           uint32_t* slot_gid, uint8_t* hit_n, uint16_t* hit_list, hipStream_t s);
+                           const float4* members, const uint32_t* offsets, const uint32_t* slot_offs,
+                           uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, uint8_t* hit_n,
+                           uint16_t* hit_list, hipStream_t s);
 // compositing keys (view << 31 | float32 depth key) and item indices; the 32-bit form
 // holds up to two views
 hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,

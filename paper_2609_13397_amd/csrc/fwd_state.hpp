@@ -13,10 +13,9 @@ struct cg_fwd_state {
   cg::DevCamera* dcams = nullptr;
   int64_t total_tiles = 0, total_px = 0, P = 0;
   cg::Record* rec = nullptr;          // [views][n]
-  const uint32_t* sorted_items = nullptr;  // (view, Gaussian) item at each position of the compositing order
-  uint32_t* counts = nullptr;         // pairs per position of the compositing order
-  uint32_t* offsets = nullptr;        // first emission slot per position of the compositing order
-  uint32_t* sorted_slots = nullptr;   // emission slot of each sorted pair
+  uint32_t* counts = nullptr;         // pairs per (view, Gaussian) item
+  uint32_t* offsets = nullptr;        // first gradient slot per item (slots in item order)
+  uint32_t* sorted_slots = nullptr;   // gradient slot of each sorted pair
   uint32_t* sorted_gid = nullptr;     // Gaussian of each sorted pair
   uint2* ranges = nullptr;            // per tile [start, end)
   uint32_t* tile_order = nullptr;     // render launch order of the tiles (heaviest first)

@@ -172,75 +172,120 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (valid && !done && Ttr != (inside ? final_T[p] : 1.f)) atomicAdd(mismatch, 1u);
 }
 
-// Per (view, Gaussian): sum of its pairs' partials, emission slots [off, off + cnt).
-// The items are taken in compositing order (counts, offsets and items per position),
-// whose slot ranges follow each other, so the partials are read front to back.
-// 5 lanes per item, each holding 4 of the 20 components of a row (one 16-byte load
-// per lane; a row is one contiguous 80-byte segment), 12 items per wave step.  An
-// item's rows are fetched kReduceBatch at a time, all loads of a batch in flight
-// together (one round trip to memory whatever the count, no serial remainder), and
-// added in slot order.  An item with more than kReduceLong slots (a Gaussian over
-// many tiles) would hold its wave for cnt / kReduceBatch round trips, long after the
-// rest of the grid has finished: it is only listed here, and k_reduce_long sums it
-// with a whole workgroup.
+// Per (view, Gaussian) item: sum of its pairs' partials, gradient slots [off, off + cnt),
+// added in slot order.  The forward lays the slots out item by item, in item order, so
+// the items' slot ranges follow each other and the sums are read and written front to
+// back.  5 lanes per item, each
+// holding 4 of the 20 components of a row (one 16-byte load per lane; a row is one
+// contiguous 80-byte segment).  Each lane group owns a run of kReduceRun consecutive
+// items, i.e. one contiguous stretch of rows, which it streams kReduceBatch rows at a
+// time whatever the items' sizes, closing an item's sum at its last row.  Plain
+// (temporal) loads: a 128-byte line holds parts of two rows that one group reads in
+// consecutive batches, and it must still be in the cache for the second.  The sums are
+// kept in LDS and written once the whole chunk is summed: vector loads and stores
+// share one wait counter, so a store among the loads would make every later wait for
+// data also wait for that store's completion.  An item with more than kReduceLong
+// slots (a Gaussian over many tiles) would hold its lane group for cnt / kReduceBatch
+// batches after the others have finished: its rows are skipped here, and
+// k_reduce_long sums it with a whole workgroup.
 constexpr int kReduceLanes = kGradLen / 4;
-constexpr int kReduceItemsPerWave = 64 / kReduceLanes;
-constexpr int kReduceBatch = 8;
+constexpr int kReduceItemsPerWave = 64 / kReduceLanes;         // 12 lane groups
+constexpr int kReduceBatch = 16;
 constexpr int kReduceLong = 128;
+constexpr int kReduceRun = 8;                                   // consecutive items per lane group
+constexpr int kReduceChunk = kReduceRun * kReduceItemsPerWave;  // 96 items per wave
 constexpr int kReduceBlocks = 16384;
 constexpr int kReduceLongBlocks = 2048;
 typedef float red4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_reduce_items(const uint32_t* __restrict__ counts,
-                                                      const uint32_t* __restrict__ offsets,
-                                                      const uint32_t* __restrict__ items, int64_t nv,
+                                                      const uint32_t* __restrict__ offsets, int64_t nv,
                                                       const float* __restrict__ partial,
                                                       float* __restrict__ item_grad,
                                                       uint32_t* __restrict__ long_items,
                                                       uint32_t* __restrict__ n_long) {
-  const int lane = threadIdx.x & 63;
+  __shared__ uint32_t s_cnt[4][kReduceChunk];
+  __shared__ red4 s_sum[4][kReduceChunk][kReduceLanes];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sub = lane / kReduceLanes, c = lane - sub * kReduceLanes;
-  if (sub >= kReduceItemsPerWave) return;
+  const bool grp = sub < kReduceItemsPerWave;
   const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int64_t it = wave * kReduceItemsPerWave + sub;
-  uint32_t cnt = 0, off = 0, dst = 0;
-  if (it < nv) {
-    cnt = counts[it];
-    off = offsets[it];
-    dst = items[it];
-  }
-  while (it < nv) {
-    // the next step's count, offset and destination load while this step's rows are in flight
-    const int64_t next = (wave + n_waves) * kReduceItemsPerWave + sub;
-    uint32_t ncnt = 0, noff = 0, ndst = 0;
-    if (next < nv) {
-      ncnt = counts[next];
-      noff = offsets[next];
-      ndst = items[next];
-    }
-    if (cnt > (uint32_t)kReduceLong) {
-      if (c == 0) long_items[atomicAdd(n_long, 1u)] = (uint32_t)it;
-    } else {
-      const red4* src = reinterpret_cast<const red4*>(partial + (int64_t)off * kGradLen) + c;
-      red4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (uint32_t k = 0; k < cnt; k += kReduceBatch) {
-        // rows past the end re-read the last row (already on its way) and count as zero
+  const red4 zero = {0.f, 0.f, 0.f, 0.f};
+  red4* __restrict__ sums = &s_sum[wave][0][0];
+  for (int64_t ch = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; ch * kReduceChunk < nv; ch += n_waves) {
+    const int64_t base = ch * kReduceChunk;
+    const int m = (int)min<int64_t>(kReduceChunk, nv - base);
+    for (int k = lane; k < m; k += 64) s_cnt[wave][k] = counts[base + k];
+    // empty and long items keep a zero sum here (k_reduce_long writes the long ones later)
+    for (int k = lane; k < m * kReduceLanes; k += 64) sums[k] = zero;
+    __builtin_amdgcn_wave_barrier();
+    // this group's run of items [j, jend): a contiguous stretch of rows, except that the
+    // rows of long items are skipped
+    int j = grp ? sub * kReduceRun : m;
+    const int jend = min(j + kReduceRun, m);
+    uint32_t row = 0;
+    if (j < m) row = offsets[base + j];
+    for (int q = j; q < jend; ++q)
+      if (s_cnt[wave][q] > (uint32_t)kReduceLong && c == 0) long_items[atomicAdd(n_long, 1u)] = (uint32_t)(base + q);
+    // Positions the group at its next item with rows, jumping over the rows of long
+    // items; seg_end: where the next long item (or the run's rows) begins, the end of
+    // the stretch that the batches may read.
+    uint32_t left = 0, seg_end = row;
+    auto settle = [&]() {
+      while (j < jend) {
+        const uint32_t cq = s_cnt[wave][j];
+        if (cq == 0u) {
+          ++j;
+        } else if (cq > (uint32_t)kReduceLong) {
+          row += cq;
+          ++j;
+        } else {
+          break;
+        }
+      }
+      if (j < jend) {
+        left = s_cnt[wave][j];
+        if (row >= seg_end) {
+          seg_end = row;
+          for (int q = j; q < jend; ++q) {
+            const uint32_t cq = s_cnt[wave][q];
+            if (cq > (uint32_t)kReduceLong) break;
+            seg_end += cq;
+          }
+        }
+      }
+    };
+    settle();
+    red4 acc = zero;
+    while (__ballot(j < jend) != 0) {
+      if (j < jend) {
+        const uint32_t r0 = row;
         red4 v[kReduceBatch];
 #pragma unroll
         for (int u = 0; u < kReduceBatch; ++u)
-          v[u] = __builtin_nontemporal_load(src + (int64_t)min(k + u, cnt - 1u) * kReduceLanes);
+          v[u] = reinterpret_cast<const red4*>(partial)[(int64_t)min(r0 + (uint32_t)u, seg_end - 1u) * kReduceLanes + c];
 #pragma unroll
-        for (int u = 0; u < kReduceBatch; ++u)
-          if (k + u < cnt) acc += v[u];
+        for (int u = 0; u < kReduceBatch; ++u) {
+          if (r0 + (uint32_t)u < seg_end && j < jend) {
+            acc += v[u];
+            ++row;
+            if (--left == 0u) {
+              sums[j * kReduceLanes + c] = acc;
+              acc = zero;
+              ++j;
+              while (j < jend && s_cnt[wave][j] == 0u) ++j;
+              if (j < jend) left = s_cnt[wave][j];
+            }
+          }
+        }
+        if (row >= seg_end) settle();
       }
-      reinterpret_cast<red4*>(item_grad + (int64_t)dst * kGradLen)[c] = acc;
     }
-    wave += n_waves;
-    it = next;
-    cnt = ncnt;
-    off = noff;
-    dst = ndst;
+    __builtin_amdgcn_wave_barrier();
+    // the chunk's sums: one contiguous stretch of item_grad
+    red4* __restrict__ out = reinterpret_cast<red4*>(item_grad + base * kGradLen);
+    for (int k = lane; k < m * kReduceLanes; k += 64) out[k] = sums[k];
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -253,7 +298,6 @@ constexpr int kReduceLongBatch = 4;
 
 __global__ __launch_bounds__(256) void k_reduce_long(const uint32_t* __restrict__ counts,
                                                      const uint32_t* __restrict__ offsets,
-                                                     const uint32_t* __restrict__ items,
                                                      const float* __restrict__ partial,
                                                      float* __restrict__ item_grad,
                                                      const uint32_t* __restrict__ long_items,
@@ -287,7 +331,7 @@ __global__ __launch_bounds__(256) void k_reduce_long(const uint32_t* __restrict_
     if (threadIdx.x < kReduceLanes) {
       red4 s = part[0][threadIdx.x];
       for (int q = 1; q < kReduceLongGroups; ++q) s += part[q][threadIdx.x];
-      reinterpret_cast<red4*>(item_grad + (int64_t)items[it] * kGradLen)[threadIdx.x] = s;
+      reinterpret_cast<red4*>(item_grad + (int64_t)it * kGradLen)[threadIdx.x] = s;
     }
     __syncthreads();
   }
@@ -496,13 +540,13 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
   }
   {
     ProfScope ps(ST_BWD_REDUCE, s);
-    const int64_t waves = (nv + kReduceItemsPerWave - 1) / kReduceItemsPerWave;
+    const int64_t waves = (nv + kReduceChunk - 1) / kReduceChunk;
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, kReduceBlocks);
     CG_HIP(launch_fill_u32(n_long, 0u, 1, s));
-    k_reduce_items<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(st->counts, st->offsets, st->sorted_items, nv,
+    k_reduce_items<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(st->counts, st->offsets, nv,
                                                                 partial, item_grad, long_items, n_long);
     CG_HIP(hipGetLastError());
-    k_reduce_long<<<dim3(kReduceLongBlocks), dim3(256), 0, s>>>(st->counts, st->offsets, st->sorted_items, partial,
+    k_reduce_long<<<dim3(kReduceLongBlocks), dim3(256), 0, s>>>(st->counts, st->offsets, partial,
                                                                item_grad, long_items, n_long);
     CG_HIP(hipGetLastError());
   }
