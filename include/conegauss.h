@@ -261,7 +261,10 @@ cg_status cg_bake_rho2(const cg_gaussians* g /* host struct, device arrays */, c
  * request when its estimated scratch memory fits hbm_budget_bytes next to the
  * requests already running (or when nothing runs), and fuses further queued
  * requests for the same scene into the same multi-view render call, up to
- * max_batch_views views and max_batch_pixels pixels, while they fit the budget.
+ * max_batch_views views, max_batch_pixels pixels and max_batch_pairs estimated pairs
+ * (a + b * pixels per view, a and b fitted per scene to the calls completed so far; a
+ * request above the cap runs alone), while they fit the budget.  The pair cap bounds a fused
+ * call's duration, which every request in it waits for.
  * A fused call renders each view bit for bit as a call with that view alone.
  * With n_workers = 1 and max_batch_views = 1 the server is the plain one-view-per-
  * launch renderer.  With request_timeout_ms > 0, a request still queued that long
@@ -281,6 +284,7 @@ typedef struct {
   double fake_ns_per_pixel;    /* [1]                                                       */
   double fake_ns_per_call;     /* [50000]                                                   */
   double request_timeout_ms;   /* [0]      time limit from submission to admission (0: none) */
+  double max_batch_pairs;      /* [12e6]   estimated (tile, Gaussian) pairs of one fused call  */
 } cg_server_config;
 
 /* One finished (or cancelled: status CG_ERR_STATE; timed out: CG_ERR_TIMEOUT) request.  Times are seconds on the
@@ -377,7 +381,8 @@ void cg_debug_set_scratch_guards(int32_t mode);
 /* Total number of changed guard words found since the library was loaded. */
 int64_t cg_debug_guard_violations(void);
 
-/* Returns the library's cached scratch memory to the device. */
+/* Returns the library's cached scratch memory to the device (waits for the device to
+ * be idle). */
 cg_status cg_release_cached_memory(void);
 
 #ifdef __cplusplus

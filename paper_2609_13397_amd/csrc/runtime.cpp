@@ -34,6 +34,9 @@ std::mutex g_pool_mu;
 std::multimap<size_t, std::pair<void*, PoolBlock>> g_pool_free;  // by size
 std::unordered_map<void*, PoolBlock> g_pool_live;
 
+size_t g_pool_cached = 0;                                        // bytes in g_pool_free
+constexpr size_t kPoolCacheLimit = size_t(64) << 30;             // beyond it the cache is returned
+
 size_t round_bytes(size_t b) {
   if (b <= (1u << 20)) {
     size_t r = 256;
@@ -52,16 +55,25 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
   const size_t want = round_bytes(bytes);
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    for (auto it = g_pool_free.lower_bound(want); it != g_pool_free.end() && it->first <= want + want / 4 + (2u << 20);
-         ++it) {
+    // best fit: the smallest cached block of this stream that holds the request, however
+    // much larger (it is held for one call only), so that calls of varying sizes reuse
+    // the blocks they have rather than adding one for every size they ask for
+    for (auto it = g_pool_free.lower_bound(want); it != g_pool_free.end(); ++it) {
       if (it->second.second.stream == s && it->second.second.device == dev) {
         void* p = it->second.first;
         g_pool_live[p] = it->second.second;
+        g_pool_cached -= it->first;
         g_pool_free.erase(it);
         return p;
       }
     }
   }
+  bool trim = false;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    trim = g_pool_cached > kPoolCacheLimit;
+  }
+  if (trim) pool_release_all();  // a bound on the cache; rare (synchronises the device)
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess) {
@@ -88,6 +100,7 @@ void pool_free(void* p, hipStream_t s) {
   b.stream = s;
   g_pool_live.erase(it);
   g_pool_free.emplace(b.bytes, std::make_pair(p, b));
+  g_pool_cached += b.bytes;
 }
 
 void pool_release_all() {
@@ -95,6 +108,7 @@ void pool_release_all() {
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     blocks.swap(g_pool_free);
+    g_pool_cached = 0;
   }
   if (blocks.empty()) return;
   (void)hipDeviceSynchronize();

@@ -31,7 +31,8 @@ void set_last_error(const std::string& msg);
   } while (0)
 
 // Library-owned caching pool: blocks freed on a stream are reused only on the same
-// stream (stream order makes that safe without events).
+// stream (stream order makes that safe without events), best fit; the cache is
+// returned to the device when it exceeds 64 GiB.
 void* pool_alloc(size_t bytes, hipStream_t s);
 void pool_free(void* p, hipStream_t s);
 void pool_release_all();

@@ -41,10 +41,37 @@ struct Request {
   int64_t px;
 };
 
+// Pairs of a view of a scene, estimated as a + b * pixels: a view of a large scene at
+// low resolution has most of its Gaussians in few tiles, so the pairs do not scale with
+// the pixels alone.  a and b are the least-squares fit over completed calls (k views,
+// their pixels and pairs), with older calls weighted down by 0.9 per call.
+struct PairModel {
+  double kk = 0, kp = 0, pp = 0, ky = 0, py = 0;  // decayed sums of k^2, k px, px^2, k y, px y
+  double a = 0.0, b = 4.0;                        // before any call: 4 pairs per pixel
+  void add(double k, double px, double y) {
+    constexpr double decay = 0.9;
+    kk = decay * kk + k * k;
+    kp = decay * kp + k * px;
+    pp = decay * pp + px * px;
+    ky = decay * ky + k * y;
+    py = decay * py + px * y;
+    const double det = kk * pp - kp * kp;
+    double na = det > 1e-9 * kk * pp ? (ky * pp - kp * py) / det : -1.0;
+    double nb = det > 1e-9 * kk * pp ? (kk * py - kp * ky) / det : -1.0;
+    if (!(na >= 0.0 && nb >= 0.0)) {  // degenerate or negative: per-pixel rate only
+      na = 0.0;
+      nb = pp > 0.0 ? py / pp : b;
+    }
+    a = na;
+    b = nb;
+  }
+  double pairs(double px) const { return a + b * px; }
+};
+
 struct SceneEntry {
   cg_gaussians g;
   cg_render_opts opts;
-  double pairs_per_px;  // running estimate used by admission
+  PairModel model;  // running estimate used by admission and fusion
 };
 
 }  // namespace
@@ -68,12 +95,18 @@ struct cg_server {
   // cones and its 256 slots of the 64-byte pixel ray buffer; per pixel the output
   // staging; when the launch is small enough to take the split tile render (which one
   // decides from its longest tile list), its per-segment state (tiles + pairs / 384
-  // segments, at most tiles + 16384, of 256 pixels, 20 bytes each).  pairs_per_px is
+  // segments, at most tiles + 16384, of 256 pixels, 20 bytes each).  The pair model is
   // refreshed from completed calls.
+  static double estimate_pairs(const SceneEntry& sc, const cg_camera& cam) {
+    const int64_t px = (int64_t)cam.crop_w * cam.crop_h;
+    const int64_t tiles = (int64_t)((cam.crop_w + 15) / 16) * ((cam.crop_h + 15) / 16);
+    return sc.model.pairs((double)px) + 64.0 * (double)tiles;
+  }
+
   size_t estimate(const SceneEntry& sc, const cg_camera& cam) const {
     const int64_t px = (int64_t)cam.crop_w * cam.crop_h;
     const int64_t tiles = (int64_t)((cam.crop_w + 15) / 16) * ((cam.crop_h + 15) / 16);
-    const double pairs = sc.pairs_per_px * (double)px + 64.0 * (double)tiles;
+    const double pairs = estimate_pairs(sc, cam);
     const SplitPolicy pol = split_policy();
     const double segs = tiles < pol.max_tiles
                             ? (double)tiles + std::min((double)kSegTarget, pairs / (double)kMinSegLen)
@@ -169,11 +202,16 @@ struct cg_server {
         batch.push_back(head);
         est_total = head.est;
         px_total = head.px;
+        // the scene's estimate as it stands now (refreshed by completed calls)
+        const auto pairs_of = [&](const Request& r) { return estimate_pairs(scene, r.cam); };
+        double pairs_total = pairs_of(head);
         for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < cfg.max_batch_views;) {
           if (it->scene == head.scene && px_total + it->px <= cfg.max_batch_pixels &&
+              pairs_total + pairs_of(*it) <= cfg.max_batch_pairs &&
               reserved + est_total + it->est <= cfg.hbm_budget_bytes) {
             est_total += it->est;
             px_total += it->px;
+            pairs_total += pairs_of(*it);
             batch.push_back(*it);
             it = queue.erase(it);
           } else {
@@ -200,7 +238,7 @@ struct cg_server {
         max_batch_seen = std::max<int64_t>(max_batch_seen, (int64_t)batch.size());
         if (status == CG_OK && px_total > 0 && !cfg.fake_executor) {
           SceneEntry& sc = scenes[batch[0].scene];
-          sc.pairs_per_px = 0.7 * sc.pairs_per_px + 0.3 * (double)pairs / (double)px_total;
+          sc.model.add((double)batch.size(), (double)px_total, (double)pairs);
         }
         for (auto& r : batch) {
           cg_server_completion c;
@@ -238,6 +276,8 @@ void cg_server_default_config(cg_server_config* c) {
   c->fake_ns_per_pixel = 1.0;
   c->fake_ns_per_call = 50000.0;
   c->device = 0;
+  c->request_timeout_ms = 0.0;
+  c->max_batch_pairs = 12e6;
 }
 
 cg_status cg_server_create(const cg_server_config* cfg, cg_server** out) {
@@ -248,6 +288,7 @@ cg_status cg_server_create(const cg_server_config* cfg, cg_server** out) {
     CG_CHECK_ARG(cfg->max_batch_pixels >= 1, "max_batch_pixels must be >= 1");
     CG_CHECK_ARG(cfg->hbm_budget_bytes > 0, "hbm_budget_bytes must be > 0");
     CG_CHECK_ARG(cfg->request_timeout_ms >= 0.0, "request_timeout_ms must be >= 0");
+    CG_CHECK_ARG(cfg->max_batch_pairs > 0.0, "max_batch_pairs must be > 0");
     *out = nullptr;
     cg_server* s = new cg_server();
     s->cfg = *cfg;
@@ -262,7 +303,7 @@ cg_status cg_server_add_scene(cg_server* s, const cg_gaussians* g, const cg_rend
     (void)make_gauss(*g);
     (void)make_opts(*opts);
     std::lock_guard<std::mutex> lk(s->mu);
-    s->scenes.push_back(SceneEntry{*g, *opts, 4.0});
+    s->scenes.push_back(SceneEntry{*g, *opts, PairModel{}});
     *scene_id = (int32_t)s->scenes.size() - 1;
   });
 }

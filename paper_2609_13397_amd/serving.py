@@ -20,7 +20,7 @@ class CgServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_batch_views", C.c_int32), ("n_workers", C.c_int32),
                 ("max_batch_pixels", C.c_int64), ("fake_executor", C.c_int32), ("device", C.c_int32),
                 ("fake_ns_per_pixel", C.c_double), ("fake_ns_per_call", C.c_double),
-                ("request_timeout_ms", C.c_double)]
+                ("request_timeout_ms", C.c_double), ("max_batch_pairs", C.c_double)]
 
 
 class CgServerCompletion(C.Structure):
