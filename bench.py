@@ -409,6 +409,46 @@ def summarize_traffic(fetch_csv: str, write_csv: str, commands) -> dict:
     return out
 
 
+def summarize_kernel_traffic(fetch_csv: str, write_csv: str, trace_csv: str, out_md: str, kernels, commands,
+                             title: str, notes: str = "") -> None:
+    """HBM bytes per dispatch of the given kernels from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, both with --copy-calibration), each scaled by what the
+    counter reads for the 256 MiB calibration copies, over the average duration of the
+    same kernel in a --kernel-trace run of the same command."""
+    import csv
+    fetch = _counter_rows(fetch_csv, "FETCH_SIZE")
+    write = _counter_rows(write_csv, "WRITE_SIZE")
+
+    def calib(rows):
+        vals = sorted((float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]), reverse=True)[:3]
+        return 256 * 1024 / (sum(vals) / len(vals))
+
+    ff, wf = calib(fetch), calib(write)
+    with open(trace_csv) as f:
+        trace = list(csv.DictReader(f))
+    lines = [f"# {title}", "", "Commands (run from the repository root on the GPU box):", "", "```", *commands, "```", "",
+             f"Bytes = counter KiB x 1024 x calibration factor (FETCH_SIZE {ff:.4f}, WRITE_SIZE {wf:.4f}: 256 MiB "
+             "device copies read as that much); ms = average duration of the kernel in the kernel trace; "
+             "share = (fetch + write) / ms against MI355X's 8 TB/s.", ""]
+    if notes:
+        lines += [notes, ""]
+    lines += ["| kernel | dispatches | fetch (MB) | write (MB) | avg ms | TB/s | share of 8 TB/s |",
+              "|---|---:|---:|---:|---:|---:|---:|"]
+    for k in kernels:
+        fr = [float(r["Counter_Value"]) for r in fetch if k in r["Kernel_Name"]]
+        wr = [float(r["Counter_Value"]) for r in write if k in r["Kernel_Name"]]
+        ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace if k in r["Kernel_Name"]]
+        if not fr or not wr or not ns:
+            continue
+        fb = sum(fr) / len(fr) * 1024 * ff
+        wb = sum(wr) / len(wr) * 1024 * wf
+        ms = sum(ns) / len(ns) / 1e6
+        tbs = (fb + wb) / (ms * 1e-3) / 1e12
+        lines.append(f"| `{k}` | {len(fr)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {ms:.3f} | {tbs:.2f} | {tbs / 8.0:.1%} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 # Two rocprofv3 --pmc passes (at most 8 SQ counters each):
 SQ_COUNTERS = ["SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_VALU2", "SQ_THREAD_CYCLES_VALU",
                "SQ_INSTS_VALU_TRANS_F32", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAVES"]
@@ -497,7 +537,7 @@ def summarize_trace(stats_csv: str, out_md: str, title: str, commands, notes: st
         lines += [notes, ""]
     lines += ["| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
     for r in rows[:20]:
-        name = r["Name"].split("(")[0].replace("void ", "")
+        name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
     with open(out_md, "w") as f:
@@ -522,6 +562,7 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--summarize-trace", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT_MD"))
     ap.add_argument("--summarize-valu", nargs=3, metavar=("SQ_COUNTER_CSV", "KERNEL_TRACE_CSV", "OUT_MD"))
+    ap.add_argument("--summarize-kernel-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_TRACE_CSV", "OUT_MD"))
     ap.add_argument("--sq2", default=None, help="second SQ counter CSV (SQ_COUNTERS_2) for --summarize-valu")
     ap.add_argument("--kernel", action="append", default=[], help="kernel name (substring) for --summarize-valu")
     ap.add_argument("--title", default="")
@@ -534,6 +575,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, args.title, args.command, args.notes)
+        return
+    if args.summarize_kernel_traffic:
+        summarize_kernel_traffic(*args.summarize_kernel_traffic, args.kernel, args.command, args.title, args.notes)
         return
     if args.summarize_valu:
         summarize_valu(*args.summarize_valu, args.command, args.kernel, sq2_csv=args.sq2)
