@@ -39,6 +39,45 @@ def _render(scene, cams, opts, split):
     return [v.cpu().numpy().astype(np.float64) for v in R.split_views(rgba, cams)], info
 
 
+U32 = 2.0 ** -24  # float32 unit roundoff
+
+
+def _split_bounds(scene, cams, opts, longest):
+    """Bounds on |split - unsplit| per pixel and channel, from the arithmetic.  Both renders
+    evaluate the same pairs identically; the split one groups the transmittance product
+    T_k = prod (1 - alpha_j) per segment and sums the colour per segment.  Each T_k is a
+    product of at most L factors (L: the longest tile list), so its rounding differs by at
+    most about 2 L u T_k between the two, and the colour sums by L u of their total, whose
+    weights T_k alpha_k sum to at most 1: |dC| <= 3 L u cmax (first order, doubled here),
+    cmax bounding every pair colour, the background and the alpha channel's 1.  Where the
+    rounding moves Ttr (1 - alpha) across T_min, one render composites a pair that the
+    other stops before; the transmittance there is below T_min / (1 - alpha_max), which
+    bounds the rest of the pixel: |d| <= T_min / (1 - alpha_max) (cmax + |bg|) + the
+    rounding bound.  Returns (rounding bound, termination bound)."""
+    cmax = 1.0
+    for c in cams:
+        pre, _ = O.preprocess(scene, c["origin"], O.Opts(use_floor=int(opts.use_floor)))
+        cmax = max(cmax, float(np.abs(pre[:, 4:7]).max()))
+    bg = max(abs(b) for b in opts.bg)
+    cmax = max(cmax, bg)
+    b_round = 2 * 3 * longest * U32 * cmax
+    b_flip = opts.T_min / (1.0 - opts.alpha_max) * (cmax + bg) + b_round
+    return b_round, b_flip
+
+
+def _check_split(ref, got, bounds, what):
+    """Every pixel within the rounding bound, except pixels where the termination test
+    fell differently, which stay within the termination bound and are rare."""
+    b_round, b_flip = bounds
+    n_px = sum(a.shape[0] * a.shape[1] for a in ref)
+    over = sum(int((np.abs(a - b).max(axis=-1) > b_round).sum()) for a, b in zip(ref, got))
+    worst = max(float(np.abs(a - b).max()) for a, b in zip(ref, got))
+    _say(f"   {what}: max |split - unsplit| {worst:.3e} (rounding bound {b_round:.2e}, termination bound "
+         f"{b_flip:.2e}); pixels beyond the rounding bound: {over} of {n_px}")
+    assert worst <= b_flip
+    assert over <= max(2, n_px // 1000)
+
+
 def _small_wide_scene():
     scene = synth.make_scene(2000, seed=22, layout="clusters", color="sh3", log_scale_mean=-3.0, log_scale_std=0.6)
     scene["means"] *= 0.3
@@ -62,13 +101,9 @@ def test_split_render_equals_unsplit_and_oracle(seg_len):
     assert info0["n_segments"] == 0
     assert info1["n_segments"] > info1["n_tiles"]  # some tile has more than one segment
     assert info1["n_pairs"] == info0["n_pairs"]
+    _check_split(ref, got, _split_bounds(scene, cams, opts, info1["max_tile_pairs"]), f"seg_len {seg_len}")
     oopts = O.Opts(use_floor=1)
     for a, b, c in zip(ref, got, cams):
-        diff = np.abs(a - b)
-        _say(f"   max |split - unsplit| {diff.max():.3e}, pixels above 1e-5: {(diff.max(axis=-1) > 1e-5).sum()}")
-        # the same pairs and arithmetic; only the products of the transmittance factors
-        # are grouped per segment (pixels at a near-threshold decision may differ more)
-        assert (diff.max(axis=-1) > 1e-5).mean() < 0.002
         refo = O.render(scene, c, oopts, mode="brute", with_alt=True)
         nfail, worst, det = compare_image(b, refo, TOL_IMAGE)
         _say(f"   oracle parity: fail={nfail} worst={worst:.3e} {det}")
@@ -86,11 +121,9 @@ def test_split_render_options_and_batches():
         opts = R.RenderOpts(**kw)
         ref, _ = _render(scene, cams, opts, None)
         got, info = _render(scene, cams, opts, (1 << 20, 1, 128))
-        worst = max(float(np.abs(a - b).max()) for a, b in zip(ref, got))
-        frac = max(float((np.abs(a - b).max(axis=-1) > 1e-5).mean()) for a, b in zip(ref, got))
-        _say(f"   {kw}: segments {info['n_segments']} max diff {worst:.2e} frac>1e-5 {frac:.4f}")
         assert info["n_segments"] > info["n_tiles"]
-        assert frac < 0.002 and worst < 0.05
+        _check_split(ref, got, _split_bounds(scene, cams, opts, info["max_tile_pairs"]),
+                     f"{kw} ({info['n_segments']} segments)")
 
 
 def test_small_view_of_large_scene_splits_by_default():
@@ -108,7 +141,7 @@ def test_small_view_of_large_scene_splits_by_default():
     assert info["max_tile_pairs"] > max(2048, info["n_pairs"] // 1024)
     assert info["n_segments"] > 0
     ref, _ = _render(scene, [cam], opts, None)
-    assert (np.abs(ref[0] - got[0]).max(axis=-1) > 1e-5).mean() < 0.002
+    _check_split(ref, got, _split_bounds(scene, [cam], opts, info["max_tile_pairs"]), "default thresholds")
     refo = O.render(scene, cam, O.Opts(use_floor=1), mode="culled", with_alt=True)
     nfail, worst, det = compare_image(got[0], refo, TOL_IMAGE)
     _say(f"   oracle parity: fail={nfail} worst={worst:.3e} {det}")
