@@ -357,12 +357,14 @@ cg_status cg_profile_valu_probe(int32_t n_blocks, int32_t iters, float* out, hip
  * split render makes about two passes over every pair).  The decision and the segment
  * length depend on the view alone, so a view renders the same in any call.  Each
  * tile's depth-ordered list of a split view is cut into segments of seg_len pairs
- * (0: max(384, P_v / 16384)), each rendered by its own workgroup: one pass takes every
- * segment's per-pixel transmittance product (Eq. 4's factors 1 - alpha, ending with the
- * one that takes it below T_min), a second composites each segment from the product of
- * the segments in front of it, and a last step sums the segments up to the one where
- * the pixel terminated.  The image equals the one-workgroup-per-tile render up to the
- * rounding order of those products.  The other views of the call render in whole
+ * (0: max(384, P_v / 16384)), each rendered by its own workgroup: one pass composites
+ * every segment on its own from T = 1 (its colour and its transmittance product, Eq. 4's
+ * factors 1 - alpha, ending with the one that takes it below T_min); where a pixel's
+ * walk ends inside a segment (the product of the segments in front is at least T_min,
+ * times this one's below it), a second pass composites that segment again from the
+ * product in front; a last step adds the segments' colours, each scaled by the product
+ * in front, up to the one where the pixel terminated.  The image equals the
+ * one-workgroup-per-tile render up to the rounding order of those products and sums.  The other views of the call render in whole
  * tiles.  Arguments <= 0 restore the defaults (2048 tiles, 2048 pairs, seg_len 0).
  * Process-wide; calls already enqueued keep the values they were issued with. */
 void cg_set_tile_split(int64_t max_tiles, int64_t min_longest, int64_t seg_len);

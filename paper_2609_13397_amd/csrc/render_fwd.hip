@@ -408,15 +408,16 @@ __global__ __launch_bounds__(256) void k_render_ray(const DevCamera* __restrict_
 // each rendered by its own workgroup (k_seg_count / scan / k_seg_fill list them:
 // nseg[t] segments per tile from seg_off[t], seg_tile[b] the tile of segment b; tiles
 // of views rendered whole get none).
-// Pass 1 takes, per pixel, the transmittance product of each segment but the last:
-// the factors (1 - alpha) of its pairs with alpha >= alpha_min, from T = 1, ending
-// with the first factor that takes the product below T_min.  k_seg_prefix replaces
-// them, in place, by T_in = the product of the earlier segments' factors (taken left
-// to right).  Pass 2 composites each segment front to back from its T_in; a
-// pixel whose T_in is below T_min terminated in an earlier segment (the product of
-// every factor before a pair is below T_min exactly when the walk terminated before
-// it).  k_seg_combine sums the segments' colours up to the one where the pixel
-// terminated.  Up to the order of the products, this is the walk of k_render.
+// Pass 1 composites every segment on its own, per pixel, from T = 1: its colour with
+// the segment-local weights, and its transmittance product (the factors (1 - alpha) of
+// its pairs with alpha >= alpha_min, ending with the first factor that takes the
+// product below T_min).  A tile of one segment is then done.  k_seg_prefix turns the
+// products into each segment's T_in = the product of the earlier segments' factors
+// (left to right).  The walk of k_render ends inside segment q exactly when T_in >=
+// T_min > T_in * (product of q): only there does pass 2 composite the segment again,
+// from T_in and with the termination test.  k_seg_combine adds the segments' colours,
+// each local one scaled by its T_in, up to the one where the pixel terminated.  Up to
+// the order of the products and sums, this is the walk of k_render.
 __global__ void k_seg_count(const DevCamera* __restrict__ cams, int n_views, const uint2* __restrict__ ranges,
                             int total_tiles, uint32_t* __restrict__ nseg) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   if (b >= n_segs) return;
   const int t = (int)seg_tile[b];
   const uint32_t ns = nseg[t], q = b - seg_off[t];
-  if (PASS == 1 && q + 1 == ns) return;  // no segment follows the last one
+  if (PASS == 2 && ns == 1) return;  // a one-segment tile was finished by pass 1
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
   const int lane = threadIdx.x & 63;
@@ -462,9 +463,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const uint32_t s0 = rg.x + q * L, s1 = min(s0 + L, rg.y);
   float Ttr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool done = !valid;
-  if (PASS == 2 && q > 0) {
-    Ttr = seg_prod[(int64_t)b * kTilePx + threadIdx.x];  // T_in, from k_seg_prefix
-    if (Ttr < o.T_min) done = true;                       // terminated in an earlier segment
+  bool redo = false;  // pass 2: this pixel's walk ends inside this segment
+  if (PASS == 2) {
+    // T_in (k_seg_prefix) and the segment's own product (pass 1): composite again only
+    // where the walk terminates inside this segment
+    const int64_t slot = (int64_t)b * kTilePx + threadIdx.x;
+    const float T_in = q > 0 ? seg_prod[slot] : 1.f;
+    const float f = seg_out[slot].w;
+    redo = valid && T_in >= o.T_min && T_in * f < o.T_min;
+    done = !redo;
+    Ttr = T_in;
   }
   const Record* vrec = rec + (int64_t)v * n_gauss;
   for (uint32_t base = s0; base < s1; base += kFwdBatch) {
@@ -488,14 +496,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                 const float test = Ttr * (1.f - alpha);
                 if (test < o.T_min) {
                   done = true;
-                  if (PASS == 1) Ttr = test;  // the product includes the factor that ends it
+                  // pass 1 of a multi-segment tile keeps the product, which includes the
+                  // factor that ends it; otherwise T stays where the walk ended (Eq. 4)
+                  if (PASS == 1 && ns > 1) Ttr = test;
                 } else {
-                  if (PASS == 2) {
-                    const float w = Ttr * alpha;
-                    C0 = fmaf(w, srec[k].rgb[0], C0);
-                    C1 = fmaf(w, srec[k].rgb[1], C1);
-                    C2 = fmaf(w, srec[k].rgb[2], C2);
-                  }
+                  const float w = Ttr * alpha;
+                  C0 = fmaf(w, srec[k].rgb[0], C0);
+                  C1 = fmaf(w, srec[k].rgb[1], C1);
+                  C2 = fmaf(w, srec[k].rgb[2], C2);
                   Ttr = test;
                 }
               }
@@ -509,19 +517,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     __syncthreads();
   }
   const int64_t slot = (int64_t)b * kTilePx + threadIdx.x;
-  if (PASS == 1) {
+  if (PASS == 1 && ns == 1) {
+    if (inside) {  // T_in = 1: the segment's walk is the pixel's
+      float4 out;
+      out.x = C0 + Ttr * o.bg[0];
+      out.y = C1 + Ttr * o.bg[1];
+      out.z = C2 + Ttr * o.bg[2];
+      out.w = 1.f - Ttr;
+      reinterpret_cast<float4*>(c.out)[(int64_t)j * c.crop_w + i] = out;
+    }
+  } else if (PASS == 1) {
+    // the local colour and the segment's product (its factors, up to the one that ends it)
     seg_prod[slot] = Ttr;
-  } else if (ns > 1) {
-    // colour, and the transmittance at the end of the segment (or where the pixel
-    // terminated: stored as -(1 + T))
-    seg_out[slot] = make_float4(C0, C1, C2, done ? -(1.f + Ttr) : Ttr);
-  } else if (inside) {
-    float4 out;
-    out.x = C0 + Ttr * o.bg[0];
-    out.y = C1 + Ttr * o.bg[1];
-    out.z = C2 + Ttr * o.bg[2];
-    out.w = 1.f - Ttr;
-    reinterpret_cast<float4*>(c.out)[(int64_t)j * c.crop_w + i] = out;
+    seg_out[slot] = make_float4(C0, C1, C2, Ttr);
+  } else if (redo) {
+    // composited again from T_in: the absolute colour and the transmittance where the
+    // pixel terminated, stored as -(1 + T) (or, if rounding let it run to the end of the
+    // segment, the transmittance there as -(3 + T))
+    seg_out[slot] = make_float4(C0, C1, C2, done ? -(1.f + Ttr) : -(3.f + Ttr));
   }
 }
 
@@ -544,6 +557,7 @@ __global__ __launch_bounds__(256) void k_seg_prefix(const uint32_t* __restrict__
 __global__ __launch_bounds__(256) void k_seg_combine(const DevCamera* __restrict__ cams, int n_views, Opts o,
                                                      const uint32_t* __restrict__ nseg,
                                                      const uint32_t* __restrict__ seg_off,
+                                                     const float* __restrict__ seg_prod,
                                                      const float4* __restrict__ seg_out) {
   const int t = blockIdx.x;
   const uint32_t ns = nseg[t];
@@ -555,15 +569,24 @@ __global__ __launch_bounds__(256) void k_seg_combine(const DevCamera* __restrict
   if (i >= c.crop_w || j >= c.crop_h) return;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
   for (uint32_t q = 0; q < ns; ++q) {
-    const float4 r = seg_out[(int64_t)(seg_off[t] + q) * kTilePx + threadIdx.x];
-    C0 += r.x;
-    C1 += r.y;
-    C2 += r.z;
-    if (r.w < 0.f) {
-      T = -r.w - 1.f;
-      break;
+    const int64_t slot = (int64_t)(seg_off[t] + q) * kTilePx + threadIdx.x;
+    const float4 r = seg_out[slot];
+    if (r.w < 0.f) {  // composited again from T_in by pass 2: absolute colour
+      C0 += r.x;
+      C1 += r.y;
+      C2 += r.z;
+      if (r.w >= -2.f) {  // terminated in this segment
+        T = -r.w - 1.f;
+        break;
+      }
+      T = -r.w - 3.f;
+      continue;
     }
-    T = r.w;
+    const float T_in = q > 0 ? seg_prod[slot] : 1.f;
+    C0 = fmaf(T_in, r.x, C0);
+    C1 = fmaf(T_in, r.y, C1);
+    C2 = fmaf(T_in, r.z, C2);
+    T = T_in * r.w;
   }
   float4 out;
   out.x = C0 + T * o.bg[0];
@@ -615,7 +638,8 @@ hipError_t launch_render_fwd_split(const DevCamera* cams, int n_views, int total
       break;
   }
 #undef CG_SEG
-  k_seg_combine<<<dim3((unsigned)total_tiles), dim3(256), 0, s>>>(cams, n_views, o, sp.nseg, sp.seg_off, sp.seg_out);
+  k_seg_combine<<<dim3((unsigned)total_tiles), dim3(256), 0, s>>>(cams, n_views, o, sp.nseg, sp.seg_off, sp.seg_prod,
+                                                                  sp.seg_out);
   return hipGetLastError();
 }
 
