@@ -22,6 +22,9 @@ __device__ __noinline__ float depth_key_f32(float mx, float my, float mz, float 
   return s;
 }
 
+constexpr int kRecF4 = (int)(sizeof(Record) / sizeof(float4));  // 8
+static_assert(sizeof(Record) % sizeof(float4) == 0, "Record is a whole number of 16-byte pieces");
+
 // Block order: workgroup b runs on XCD b % 8.  The views of one 256-Gaussian chunk are
 // given to workgroups b, b + 8, b + 16, ... (same XCD, consecutive in dispatch order),
 // so the views after the first read the chunk's parameters (48 SH coefficients each)
@@ -30,12 +33,16 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
                                                     const float* __restrict__ view_cmax, Opts o,
                                                     Record* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     float4* __restrict__ cone) {
+  __shared__ float4 s_rec[4][64 * (kRecF4 + 1)];  // per wave: 64 records, padded against bank conflicts
   const int q8 = (int)(blockIdx.x >> 3);
   const int v = q8 % n_views;
   const int64_t chunk = (int64_t)(q8 / n_views) * 8 + (blockIdx.x & 7);
   const int64_t n = g.n;
-  const int64_t i = chunk * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i0 = chunk * blockDim.x + threadIdx.x;
+  const bool live = i0 < n;
+  if (__ballot(live) == 0) return;  // the whole wave is past the end
+  // lanes past the end (in the last wave) recompute the last item, and write nothing
+  const int64_t i = live ? i0 : n - 1;
   const DevCamera& c = cams[v];
   const int64_t out = (int64_t)v * n + i;
 
@@ -102,7 +109,7 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
     }
   }
 
-  depth_key[out] = __float_as_uint(depth_key_f32(mu[0], mu[1], mu[2], c.of[0], c.of[1], c.of[2]));
+  if (live) depth_key[out] = __float_as_uint(depth_key_f32(mu[0], mu[1], mu[2], c.of[0], c.of[1], c.of[2]));
 
   // Influence cone.  If T >= alpha_min then q^T A^{-1} q <= L = 2 ln(sigma_b /
   // alpha_min) (sigma_b = sigma_eff times the backbone's largest factor), and
@@ -190,8 +197,25 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
   if (gamma < 0.f) r.lim = -1.f;
   else if (gamma >= kPiF) r.lim = 3.f;
   else r.lim = 2.f * sinf(0.5f * gamma) + 1e-5f;
-  rec[out] = r;
-  cone[out] = make_float4(ux, uy, uz, chord_radius(gamma));
+  if (live) cone[out] = make_float4(ux, uy, uz, chord_radius(gamma));
+  // The wave's 64 records are consecutive in rec: staged in LDS and written back as 1 KiB
+  // contiguous stores (a direct 128-byte store per lane writes 16 bytes of 64 different
+  // lines per instruction, which reached HBM as 1.6 times the record bytes).
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float4* __restrict__ stage = s_rec[wave];
+  const float4* rv = reinterpret_cast<const float4*>(&r);
+#pragma unroll
+  for (int k = 0; k < kRecF4; ++k) stage[lane * (kRecF4 + 1) + k] = rv[k];
+  __builtin_amdgcn_wave_barrier();
+  const int64_t wave_i0 = i0 - lane;  // the wave's first item (the same in every lane)
+  const int64_t first = (int64_t)v * n + wave_i0;
+  const int64_t n_live = min<int64_t>(64, n - wave_i0);
+  float4* __restrict__ dst = reinterpret_cast<float4*>(rec + first);
+#pragma unroll
+  for (int k = 0; k < kRecF4; ++k) {
+    const int e = k * 64 + lane, rr = e / kRecF4, part = e - rr * kRecF4;
+    if (rr < n_live) dst[e] = stage[rr * (kRecF4 + 1) + part];
+  }
 }
 
 hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,
