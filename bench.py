@@ -143,6 +143,10 @@ def train_step_bench(torch, R, synth, device, steps, warmup):
     npx = sum(R.view_pixels(cams))
 
     def step():
+        # gradients reset as an optimizer's zero_grad(set_to_none=True) does, so autograd
+        # stores the library's gradient tensors instead of adding them into old ones
+        for p in params:
+            p.grad = None
         rgba = R.ConeGaussRender.apply(*params, scene.rho2, cams, opts, scene.color_mode)
         loss = (rgba - tgt).abs().mean()
         loss.backward()

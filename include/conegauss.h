@@ -226,7 +226,8 @@ cg_status cg_render_forward_noalloc(const cg_gaussians* g /* host struct, device
  * parameters of the forward call that produced `st` (summed over its views).  The
  * outputs have the shapes of the inputs and are OVERWRITTEN; rho2 gets no gradient.
  * Pairs are reduced per tile and then per Gaussian without atomics, so the result is
- * deterministic.  grad_rgba has the layout of out_rgba. */
+ * deterministic.  grad_rgba has the layout of out_rgba.  The call is asynchronous
+ * on `stream` (no host synchronisation unless scratch guard bands are enabled). */
 cg_status cg_render_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, float* d_log_scales,
                              float* d_quats, float* d_opacity_logits, float* d_color, hipStream_t stream);
 
@@ -234,7 +235,8 @@ void cg_fwd_state_release(cg_fwd_state* st);
 
 /* Diagnostic of the last cg_render_backward on `st`: the number of pixels whose
  * replayed front-to-back walk did not end at the transmittance the forward stored
- * (0 when the replay is exact); -1 before any backward call. */
+ * (0 when the replay is exact); -1 before any backward call or on a HIP error.  The
+ * count stays on the device until this call, which waits for the backward's stream. */
 int64_t cg_bwd_replay_mismatches(const cg_fwd_state* st);
 
 /* Inverse mapping Pi^{-1} (Sec. 3) of n continuous full-image pixel coordinates.

@@ -305,7 +305,12 @@ hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t 
 __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                               const uint32_t* __restrict__ slot_gid, int64_t n, uint2* __restrict__ ranges,
                               uint32_t* __restrict__ sorted_gid) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // Workgroup b runs on XCD b mod 8: each XCD takes one contiguous run of the blocks, so
+  // the neighbouring tiles of a row, which share most of their Gaussians, read the
+  // slot-to-Gaussian table through the same L2.
+  const unsigned nb = gridDim.x, q = nb / 8, r = nb % 8, x = blockIdx.x % 8;
+  const unsigned blk = x * q + min(x, r) + blockIdx.x / 8;
+  const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t tile = keys[i];
   if (slot_gid) sorted_gid[i] = slot_gid[vals[i]];

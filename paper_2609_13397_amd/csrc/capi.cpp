@@ -252,7 +252,10 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       c.add(&cone, nv1);
       c.add(&counts, nv1);
       c.add(&hit_n, nv1);
-      if (state_out) c.add(&slot_offs, nv1);
+      if (state_out) {
+        c.add(&slot_offs, nv1);
+        c.add(&st->bwd_mismatch, 1);
+      }
       c.add(&hit_list, nv1 * kBinHitList);
       c.add(&offsets, nv1);
       c.add_bytes(&scan_tmp, scan_temp_bytes(nv));
@@ -528,6 +531,9 @@ cg_status cg_render_forward(const cg_gaussians* g, const cg_camera* cams, int32_
 
 void cg_fwd_state_release(cg_fwd_state* st) {
   if (!st) return;
+  // the blocks go back in the order of the forward's stream; a backward enqueued on
+  // another stream may still read them
+  if (st->bwd_ran && st->bwd_stream != st->stream) (void)hipStreamSynchronize(st->bwd_stream);
   for (void* p : st->blocks) free_block(st->alloc, p, st->stream);
   delete st;
 }

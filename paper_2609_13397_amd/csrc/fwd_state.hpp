@@ -28,7 +28,9 @@ struct cg_fwd_state {
   cg_allocator alloc{nullptr, nullptr, nullptr};
   hipStream_t stream = nullptr;
   std::vector<void*> blocks;          // scratch owned by the state
-  int64_t replay_mismatches = -1;     // set by the backward pass
+  uint32_t* bwd_mismatch = nullptr;   // device counter the backward replay adds to
+  hipStream_t bwd_stream = nullptr;   // stream of the last backward call
+  bool bwd_ran = false;               // a backward call was enqueued on this state
 };
 
 namespace cg {

@@ -509,13 +509,12 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
   const int64_t nv = n * st->n_views;
   Scratch sc(&st->alloc, s);
   float *partial, *item_grad;
-  unsigned int* mismatch;
   uint32_t *long_items, *n_long;
+  unsigned int* mismatch = st->bwd_mismatch;
   {
     Carve c;
     c.add(&partial, (size_t)std::max<int64_t>(st->P, 1) * kGradLen);
     c.add(&item_grad, (size_t)nv * kGradLen);
-    c.add(&mismatch, 4);
     // items with more than kReduceLong slots: at most P / kReduceLong of them
     c.add(&long_items, (size_t)(st->P / kReduceLong + 1));
     c.add(&n_long, 1);
@@ -556,10 +555,9 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
         st->g, st->dcams, st->n_views, st->opts, item_grad, d_means, d_log_scales, d_quats, d_opacity, d_color);
     CG_HIP(hipGetLastError());
   }
-  unsigned int host_mismatch = 0;
-  CG_HIP(hipMemcpyAsync(&host_mismatch, mismatch, 4, hipMemcpyDeviceToHost, s));
-  CG_HIP(hipStreamSynchronize(s));
-  st->replay_mismatches = host_mismatch;
+  // no host synchronisation: the replay diagnostic stays on the device until asked for
+  st->bwd_stream = s;
+  st->bwd_ran = true;
   sc.check_guards();
 }
 
@@ -580,4 +578,11 @@ extern "C" cg_status cg_render_backward(cg_fwd_state* st, const float* grad_rgba
   }
 }
 
-extern "C" int64_t cg_bwd_replay_mismatches(const cg_fwd_state* st) { return st ? st->replay_mismatches : -1; }
+extern "C" int64_t cg_bwd_replay_mismatches(const cg_fwd_state* st) {
+  if (!st || !st->bwd_ran) return -1;
+  unsigned int host = 0;
+  if (hipMemcpyAsync(&host, st->bwd_mismatch, 4, hipMemcpyDeviceToHost, st->bwd_stream) != hipSuccess ||
+      hipStreamSynchronize(st->bwd_stream) != hipSuccess)
+    return -1;
+  return host;
+}
