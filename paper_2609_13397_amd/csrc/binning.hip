@@ -219,29 +219,15 @@ hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const 
   return hipGetLastError();
 }
 
-// Compositing order of the (view, Gaussian) items: key (view << 31 | float32 depth
-// key), sorted stably so that equal keys keep the Gaussian index order.
-template <class K>
-__global__ void k_depth_items(const uint32_t* __restrict__ depth_key, int64_t n, int64_t nv, K* __restrict__ keys,
-                              uint32_t* __restrict__ items) {
+// items[k] = k: the (view, Gaussian) item indices the depth sort permutes.
+__global__ void k_iota_items(int64_t nv, uint32_t* __restrict__ items) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nv) return;
-  const K v = (K)(k / n);
-  keys[k] = (v << 31) | (K)depth_key[k];
-  items[k] = (uint32_t)k;
+  if (k < nv) items[k] = (uint32_t)k;
 }
 
-hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,
-                              hipStream_t s) {
+hipError_t launch_iota_items(int64_t nv, uint32_t* items, hipStream_t s) {
   if (nv == 0) return hipSuccess;
-  k_depth_items<uint64_t><<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(depth_key, n, nv, keys, items);
-  return hipGetLastError();
-}
-
-hipError_t launch_depth_items32(const uint32_t* depth_key, int64_t n, int64_t nv, uint32_t* keys, uint32_t* items,
-                                hipStream_t s) {
-  if (nv == 0) return hipSuccess;
-  k_depth_items<uint32_t><<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(depth_key, n, nv, keys, items);
+  k_iota_items<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(nv, items);
   return hipGetLastError();
 }
 

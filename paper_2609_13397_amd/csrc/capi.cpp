@@ -233,7 +233,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     float* view_cmax;
     unsigned long long* pair_total;
     Record* rec;
-    uint64_t *dkeys, *dkeys_alt;
+    uint32_t* dkeys_alt;
     void *scan_tmp, *dsort_tmp;
     uint8_t* hit_n;
     uint16_t* hit_list;
@@ -259,7 +259,6 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       c.add(&hit_list, nv1 * kBinHitList);
       c.add(&offsets, nv1);
       c.add_bytes(&scan_tmp, scan_temp_bytes(nv));
-      c.add(&dkeys, nv1);
       c.add(&dkeys_alt, nv1);
       c.add(&items, nv1);
       c.add(&items_alt, nv1);
@@ -286,23 +285,19 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       ProfScope ps(ST_BIN_COUNT, s);
       CG_HIP(launch_bin_count(n, n_views, dcams, cone, groups, members, counts, hit_n, hit_list, s));
     }
-    // compositing order of the (view, Gaussian) items, then pair offsets in that order
-    const int view_bits = bits_for(std::max(n_views - 1, 1));
+    // compositing order of the (view, Gaussian) items, then pair offsets in that order.
+    // The items of all views are sorted together, stably, on the float32 depth key
+    // alone (it is consumed here): a tile holds pairs of one view only, so each tile's
+    // list comes out in its view's depth order, equal keys in Gaussian index order,
+    // whatever the order between views.
     unsigned long long host_total = 0;
     const uint32_t* sorted_items = items;
     if (nv > 0) {
       int d_alt = 0;
       {
         ProfScope ps(ST_DEPTH_SORT, s);
-        if (31 + view_bits <= 32) {  // one or two views: 32-bit keys
-          uint32_t* k32 = reinterpret_cast<uint32_t*>(dkeys);
-          uint32_t* k32_alt = reinterpret_cast<uint32_t*>(dkeys_alt);
-          CG_HIP(launch_depth_items32(depth_key, n, nv, k32, items, s));
-          CG_HIP(launch_radix_sort32(k32, items, k32_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
-        } else {
-          CG_HIP(launch_depth_items(depth_key, n, nv, dkeys, items, s));
-          CG_HIP(launch_radix_sort(dkeys, items, dkeys_alt, items_alt, nv, 31 + view_bits, dsort_tmp, &d_alt, s));
-        }
+        CG_HIP(launch_iota_items(nv, items, s));
+        CG_HIP(launch_radix_sort32(depth_key, items, dkeys_alt, items_alt, nv, 32, dsort_tmp, &d_alt, s));
       }
       sorted_items = d_alt ? items_alt : items;
       {

@@ -163,12 +163,8 @@ hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const 
                            const float4* members, const uint32_t* offsets, const uint32_t* slot_offs,
                            uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, uint8_t* hit_n,
                            uint16_t* hit_list, hipStream_t s);
-// compositing keys (view << 31 | float32 depth key) and item indices; the 32-bit form
-// holds up to two views
-hipError_t launch_depth_items(const uint32_t* depth_key, int64_t n, int64_t nv, uint64_t* keys, uint32_t* items,
-                              hipStream_t s);
-hipError_t launch_depth_items32(const uint32_t* depth_key, int64_t n, int64_t nv, uint32_t* keys, uint32_t* items,
-                                hipStream_t s);
+// items[k] = k for k < nv
+hipError_t launch_iota_items(int64_t nv, uint32_t* items, hipStream_t s);
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
 // The gather above that also adds the sum of the gathered values to *total (64 bits,
 // zeroed beforehand): the exact pair count, which 32-bit offsets cannot hold.
@@ -190,8 +186,6 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, v
 size_t radix_temp_bytes(int64_t n);
 // Sorts (keys, vals) stably on bits [0, end_bit); returns 0 if the result is in
 // (keys, vals) and 1 if it is in (keys_alt, vals_alt).
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                             int end_bit, void* temp, int* result_in_alt, hipStream_t s);
 hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
                                int end_bit, void* temp, int* result_in_alt, hipStream_t s);
 

@@ -239,11 +239,6 @@ static hipError_t radix_sort_t(K* keys, uint32_t* vals, K* keys_alt, uint32_t* v
   return hipSuccess;
 }
 
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                             int end_bit, void* temp, int* result_in_alt, hipStream_t s) {
-  return radix_sort_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, end_bit, temp, result_in_alt, s);
-}
-
 hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
                                int end_bit, void* temp, int* result_in_alt, hipStream_t s) {
   return radix_sort_t<uint32_t>(keys, vals, keys_alt, vals_alt, n, end_bit, temp, result_in_alt, s);
