@@ -183,9 +183,9 @@ def test_fisheye_and_equirect_small_parity(backbone):
 
 def test_more_than_65536_tiles_three_sort_passes():
     """Three 4096x2048 equirect views in one call: 98,304 tiles, so the tile ids need
-    17 bits and the tile sort a third 8-bit pass, and more than two views take the
-    64-bit depth keys.  Three rows of every view (near the top, the middle, the last)
-    are checked against the oracle."""
+    17 bits and the tile sort a third 8-bit pass, and the depth sort orders the items of
+    three views together on the depth key alone.  Three rows of every view (near the
+    top, the middle, the last) are checked against the oracle."""
     torch, R = _gpu()
     scene = synth.make_scene(2000, seed=23, layout="clusters", color="sh3", log_scale_mean=-3.0, log_scale_std=0.6)
     scene["means"] *= 0.3
