@@ -34,7 +34,8 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
                                              const uint32_t* __restrict__ offsets,
                                              const uint32_t* __restrict__ slot_offs, uint32_t* __restrict__ keys,
                                              uint32_t* __restrict__ vals, uint32_t* __restrict__ slot_gid,
-                                             uint8_t* __restrict__ hit_n, uint16_t* __restrict__ hit_list) {
+                                             uint8_t* __restrict__ hit_n, uint16_t* __restrict__ hit_list,
+                                             uint2* __restrict__ clear_ranges, int64_t n_ranges) {
   __shared__ __align__(16) uint16_t hitbuf[4][64 * kMaxGroupHits];  // per wave: the lanes' hit groups
   __shared__ uint32_t flat[4][64 * kMaxGroupHits];
   const int v = blockIdx.y;
@@ -52,6 +53,12 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
   const uint32_t my_slot = (EMIT && in && slot_gid) ? slot_offs[gv] : 0u;
   const float inv_gx = 1.f / (float)c.groups_x;
   uint32_t my_count = 0;
+  if (EMIT) {  // the tile ranges that k_tile_ranges fills start at (0, 0): zeroed here
+    const int64_t nthreads = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+    for (int64_t k = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; k < n_ranges;
+         k += nthreads)
+      clear_ranges[k] = make_uint2(0u, 0u);
+  }
 
   // phase 1: overlapping groups of this lane's Gaussian.  The count pass tests them and
   // keeps each Gaussian's list (up to kMaxGroupHits groups, ascending, and their number)
@@ -204,30 +211,18 @@ hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
   k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, counts, nullptr, nullptr, nullptr, nullptr,
-                                          nullptr, hit_n, hit_list);
+                                          nullptr, hit_n, hit_list, nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
                            const float4* members, const uint32_t* offsets, const uint32_t* slot_offs,
                            uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, uint8_t* hit_n,
-                           uint16_t* hit_list, hipStream_t s) {
-  if (n == 0 || n_views == 0) return hipSuccess;
+                           uint16_t* hit_list, uint2* ranges, int64_t total_tiles, hipStream_t s) {
+  if (n == 0 || n_views == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s);
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
   k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, nullptr, offsets, slot_offs, keys, vals,
-                                         slot_gid, hit_n, hit_list);
-  return hipGetLastError();
-}
-
-// items[k] = k: the (view, Gaussian) item indices the depth sort permutes.
-__global__ void k_iota_items(int64_t nv, uint32_t* __restrict__ items) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nv) items[k] = (uint32_t)k;
-}
-
-hipError_t launch_iota_items(int64_t nv, uint32_t* items, hipStream_t s) {
-  if (nv == 0) return hipSuccess;
-  k_iota_items<<<dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s>>>(nv, items);
+                                         slot_gid, hit_n, hit_list, ranges, total_tiles);
   return hipGetLastError();
 }
 

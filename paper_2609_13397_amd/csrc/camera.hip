@@ -51,12 +51,18 @@ __device__ __forceinline__ float block_max(float v, float* sh) {
 // margin) and the tile's largest footprint coefficient (|d_x-d|^2 + |d_y-d|^2) / 3,
 // whose per-view maximum (taken by k_group_cones) bounds every pixel's footprint in
 // the Gaussian cones.  Each thread also stores its pixel's rays in the pixel buffer (pixel_buf.hpp), in the
-// slot of the render thread that shades that pixel.
+// slot of the render thread that shades that pixel.  The first workgroup also zeroes
+// the two small arrays of `clr` (accumulators of later kernels), which saves their
+// fill launches.
 __global__ __launch_bounds__(256) void k_tile_cones(const DevCamera* __restrict__ cams, int n_views, float fs,
                                                     int64_t n_slots, TileCone* __restrict__ tiles,
-                                                    float4* __restrict__ pix) {
+                                                    float4* __restrict__ pix, ClearPair clr) {
   __shared__ float sh[4];
   const int t = blockIdx.x;
+  if (t == 0) {
+    for (int k = threadIdx.x; k < clr.n[0]; k += blockDim.x) clr.p[0][k] = 0u;
+    for (int k = threadIdx.x; k < clr.n[1]; k += blockDim.x) clr.p[1][k] = 0u;
+  }
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
   int i, j;
@@ -92,10 +98,16 @@ __global__ __launch_bounds__(256) void k_tile_cones(const DevCamera* __restrict_
 }
 
 hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles, float fs, TileCone* tiles,
-                             float4* pix, hipStream_t s) {
-  if (total_tiles == 0) return hipSuccess;
+                             float4* pix, const ClearPair& clr, hipStream_t s) {
+  if (total_tiles == 0) {
+    for (int k = 0; k < 2; ++k) {
+      const hipError_t e = launch_fill_u32(clr.p[k], 0u, clr.n[k], s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   k_tile_cones<<<dim3(total_tiles), dim3(kTilePx), 0, s>>>(cams, n_views, fs, (int64_t)total_tiles * kTilePx, tiles,
-                                                          pix);
+                                                          pix, clr);
   return hipGetLastError();
 }
 

@@ -271,15 +271,15 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
 
     {
       ProfScope ps(ST_CAMERA, s);
-      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(view_cmax), 0u, n_views, s));
-      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(pair_total), 0u, 2, s));
-      CG_HIP(launch_tile_cones(dcams, n_views, (int)total_tiles, o.fs, tiles, pix, s));
+      const ClearPair clr{{reinterpret_cast<uint32_t*>(view_cmax), reinterpret_cast<uint32_t*>(pair_total)},
+                          {n_views, 2}};
+      CG_HIP(launch_tile_cones(dcams, n_views, (int)total_tiles, o.fs, tiles, pix, clr, s));
       CG_HIP(launch_group_cones(dcams, n_views, (int)total_groups, tiles, groups, members,
                                 view_cmax, s));
     }
     {
       ProfScope ps(ST_PREPROCESS, s);
-      CG_HIP(launch_preprocess(g, dcams, n_views, view_cmax, o, rec, depth_key, cone, s));
+      CG_HIP(launch_preprocess(g, dcams, n_views, view_cmax, o, rec, depth_key, items, cone, s));
     }
     {
       ProfScope ps(ST_BIN_COUNT, s);
@@ -296,7 +296,6 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       int d_alt = 0;
       {
         ProfScope ps(ST_DEPTH_SORT, s);
-        CG_HIP(launch_iota_items(nv, items, s));
         CG_HIP(launch_radix_sort32(depth_key, items, dkeys_alt, items_alt, nv, 32, dsort_tmp, &d_alt, s));
       }
       sorted_items = d_alt ? items_alt : items;
@@ -370,7 +369,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       {
         ProfScope ps(ST_BIN_EMIT, s);
         CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, offsets, slot_offs, keys, vals, slot_gid,
-                               hit_n, hit_list, s));
+                               hit_n, hit_list, ranges, total_tiles, s));
       }
       {
         ProfScope ps(ST_SORT, s);
@@ -385,7 +384,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     const int end_bit = tile_bits;
     {
       ProfScope ps(ST_RANGES, s);
-      CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
+      // (the emit pass zeroed the ranges; with no pairs it did not run)
+      if (P == 0) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
       CG_HIP(launch_tile_ranges(skeys, svals, slot_gid, P, ranges, st ? sorted_gid : nullptr, s));
       CG_HIP(launch_tile_order(ranges, (int)total_tiles, tile_order, s));
     }

@@ -124,15 +124,23 @@ struct GaussPtrs {
   const float* rho2;
 };
 
+// Two small device arrays (p[k], n[k] 32-bit words) that a kernel zeroes on the side,
+// in place of a fill launch of their own.
+struct ClearPair {
+  uint32_t* p[2];
+  int n[2];
+};
+
 // ---------------------------------------------------------------- host-side launch API
 // (each wraps kernels defined in one .hip translation unit)
 
 // camera.hip
 hipError_t launch_unproject(const DevCamera* cam, int64_t n, const float* pix_xy, float* dirs, uint8_t* valid,
                             hipStream_t s);
-// pix: the per-pixel ray buffer, 4 * 16 bytes per slot, total_tiles * 256 slots
+// pix: the per-pixel ray buffer, 4 * 16 bytes per slot, total_tiles * 256 slots; clr:
+// two small arrays zeroed on the side
 hipError_t launch_tile_cones(const DevCamera* cams, int n_views, int total_tiles, float fs, TileCone* tiles,
-                             float4* pix, hipStream_t s);
+                             float4* pix, const ClearPair& clr, hipStream_t s);
 // Per 8x8 tile group: its chord cone (groups), and a group-major copy of its 64 member
 // tiles' chord cones (members, kChordNever for tiles outside the view; member l of
 // group (gx, gy) is tile (8 gx + l % 8, 8 gy + l / 8)).  view_cmax: per-view maximum
@@ -144,8 +152,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_guard_check(const uint32_t* g, int n, uint32_t v, uint32_t* bad, hipStream_t s);
 
 // preprocess.hip
+// items[k] = k for every (view, Gaussian) item k, beside its depth key
 hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,
-                             const Opts& o, Record* rec, uint32_t* depth_key, float4* cone, hipStream_t s);
+                             const Opts& o, Record* rec, uint32_t* depth_key, uint32_t* items, float4* cone,
+                             hipStream_t s);
 
 // binning.hip
 // cone: per (view, Gaussian) chord cone of its influence cone (from the preprocess)
@@ -159,12 +169,11 @@ hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const
 // Emit pass: pair (tile, Gaussian) of item gv at positions offsets[gv] + j (compositing
 // order).  Inference: vals = Gaussian index.  Training (slot_offs, slot_gid non-null):
 // vals = the pair's gradient slot slot_offs[gv] + j, and slot_gid[slot] = Gaussian.
+// The per-tile ranges (total_tiles entries) are zeroed on the side for k_tile_ranges.
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
                            const float4* members, const uint32_t* offsets, const uint32_t* slot_offs,
                            uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, uint8_t* hit_n,
-                           uint16_t* hit_list, hipStream_t s);
-// items[k] = k for k < nv
-hipError_t launch_iota_items(int64_t nv, uint32_t* items, hipStream_t s);
+                           uint16_t* hit_list, uint2* ranges, int64_t total_tiles, hipStream_t s);
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
 // The gather above that also adds the sum of the gathered values to *total (64 bits,
 // zeroed beforehand): the exact pair count, which 32-bit offsets cannot hold.

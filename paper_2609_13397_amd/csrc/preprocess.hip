@@ -32,7 +32,7 @@ static_assert(sizeof(Record) % sizeof(float4) == 0, "Record is a whole number of
 __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera* __restrict__ cams, int n_views,
                                                     const float* __restrict__ view_cmax, Opts o,
                                                     Record* __restrict__ rec, uint32_t* __restrict__ depth_key,
-                                                    float4* __restrict__ cone) {
+                                                    uint32_t* __restrict__ items, float4* __restrict__ cone) {
   __shared__ float4 s_rec[4][64 * (kRecF4 + 1)];  // per wave: 64 records, padded against bank conflicts
   const int q8 = (int)(blockIdx.x >> 3);
   const int v = q8 % n_views;
@@ -109,7 +109,10 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
     }
   }
 
-  if (live) depth_key[out] = __float_as_uint(depth_key_f32(mu[0], mu[1], mu[2], c.of[0], c.of[1], c.of[2]));
+  if (live) {
+    depth_key[out] = __float_as_uint(depth_key_f32(mu[0], mu[1], mu[2], c.of[0], c.of[1], c.of[2]));
+    items[out] = (uint32_t)out;  // the item indices that the depth sort permutes
+  }
 
   // Influence cone.  If T >= alpha_min then q^T A^{-1} q <= L = 2 ln(sigma_b /
   // alpha_min) (sigma_b = sigma_eff times the backbone's largest factor), and
@@ -219,11 +222,12 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
 }
 
 hipError_t launch_preprocess(const GaussPtrs& g, const DevCamera* cams, int n_views, const float* view_cmax,
-                             const Opts& o, Record* rec, uint32_t* depth_key, float4* cone, hipStream_t s) {
+                             const Opts& o, Record* rec, uint32_t* depth_key, uint32_t* items, float4* cone,
+                             hipStream_t s) {
   if (g.n == 0 || n_views == 0) return hipSuccess;
   const int64_t chunks8 = (g.n + 8 * 256 - 1) / (8 * 256);  // groups of 8 chunks of 256 Gaussians
   const dim3 grid((unsigned)(chunks8 * 8 * n_views));
-  k_preprocess<<<grid, dim3(256), 0, s>>>(g, cams, n_views, view_cmax, o, rec, depth_key, cone);
+  k_preprocess<<<grid, dim3(256), 0, s>>>(g, cams, n_views, view_cmax, o, rec, depth_key, items, cone);
   return hipGetLastError();
 }
 

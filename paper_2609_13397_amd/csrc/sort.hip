@@ -1,8 +1,10 @@
-// Device exclusive scan (uint32) and stable LSD radix sort of (uint64 key, uint32
+// Device exclusive scan (uint32) and stable LSD radix sort of (uint32 key, uint32
 // value) pairs, 8 bits per pass.
 //
-// Radix pass = histogram kernel (per-block digit counts, LDS atomics) + exclusive scan
-// of the digit-major count table + scatter kernel.  The scatter is stable: each
+// Radix pass = histogram kernel (per-block digit counts, LDS atomics) + row scan (one
+// workgroup per digit: the exclusive prefix of the digit's counts over the blocks, and
+// the digit's total) + scatter kernel, which adds the exclusive prefix of the 256 digit
+// totals that it forms itself: three launches per pass.  The scatter is stable: each
 // wavefront owns a contiguous run of 1024 items, walks it in rounds of 64, and ranks
 // items of equal digit with 8 ballots (a wave-wide digit match); per-wave digit
 // counters in LDS carry the running offsets between rounds and are prefixed across
@@ -120,6 +122,43 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// One workgroup per digit d: hist[d * nblocks + b] becomes the exclusive prefix of the
+// digit's counts over blocks b' < b (in place), and totals[d] the digit's count.
+__global__ __launch_bounds__(kScanBlock) void k_radix_rowscan(uint32_t* __restrict__ hist, int nblocks,
+                                                              uint32_t* __restrict__ totals) {
+  __shared__ uint32_t wsum[4];
+  uint32_t* __restrict__ row = hist + (int64_t)blockIdx.x * nblocks;
+  const int w = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int base = 0; base < nblocks; base += kScanTile) {
+    const int b0 = base + (int)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t local = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] = b0 + k < nblocks ? row[b0 + k] : 0u;
+      local += v[k];
+    }
+    const uint32_t incl = wave_incl_scan(local);
+    if ((threadIdx.x & 63) == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t woff = 0, tile = 0;
+    for (int k = 0; k < 4; ++k) {
+      woff += k < w ? wsum[k] : 0u;
+      tile += wsum[k];
+    }
+    uint32_t run = carry + woff + incl - local;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (b0 + k < nblocks) row[b0 + k] = run;
+      run += v[k];
+    }
+    carry += tile;
+    __syncthreads();  // wsum is rewritten by the next tile
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
 // Scatter of one pass.  The block first ranks its 4096 items by digit (stable) into
 // LDS, in digit order, then writes them out linearly: consecutive threads write
 // consecutive positions of a digit's run, so the global writes come in contiguous
@@ -129,10 +168,11 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
                                                               const uint32_t* __restrict__ vin,
                                                               K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                               int64_t n, int shift,
-                                                              const uint32_t* __restrict__ offsets, int nblocks) {
+                                                              const uint32_t* __restrict__ offsets,
+                                                              const uint32_t* __restrict__ totals, int nblocks) {
   __shared__ uint32_t wcnt[4][kRadix];
   __shared__ int64_t gdelta[kRadix];  // global position of a digit's run minus its LDS start
-  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t wsum[4], tsum[4];
   __shared__ K skey[kSortTile];
   __shared__ uint32_t sval[kSortTile];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -165,7 +205,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
     rank[r] = ok ? base + before : 0xffffffffu;
   }
   __syncthreads();
-  {  // per digit: exclusive prefix over the block's waves, then over the digits
+  {  // per digit: exclusive prefix over the block's waves, then over the digits; the
+     // digit's global start is the exclusive prefix of the digit totals plus the counts
+     // of the digit in the blocks before this one (the row scan)
     const int d = threadIdx.x;
     uint32_t run = 0;
     for (int w = 0; w < 4; ++w) {
@@ -173,13 +215,21 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
       wcnt[w][d] = run;
       run += t;
     }
+    const uint32_t tot = totals[d];
     const uint32_t incl = wave_incl_scan(run);
-    if (lane == 63) wsum[wave] = incl;
+    const uint32_t tincl = wave_incl_scan(tot);
+    if (lane == 63) {
+      wsum[wave] = incl;
+      tsum[wave] = tincl;
+    }
     __syncthreads();
-    uint32_t start = incl - run;
-    for (int w = 0; w < wave; ++w) start += wsum[w];
+    uint32_t start = incl - run, dstart = tincl - tot;
+    for (int w = 0; w < wave; ++w) {
+      start += wsum[w];
+      dstart += tsum[w];
+    }
     for (int w = 0; w < 4; ++w) wcnt[w][d] += start;
-    gdelta[d] = (int64_t)offsets[(int64_t)d * nblocks + blockIdx.x] - (int64_t)start;
+    gdelta[d] = (int64_t)dstart + (int64_t)offsets[(int64_t)d * nblocks + blockIdx.x] - (int64_t)start;
   }
   __syncthreads();
 #pragma unroll
@@ -204,7 +254,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
 size_t radix_temp_bytes(int64_t n) {
   const int64_t nblocks = ceil_div(n > 0 ? n : 1, kSortTile);
   const int64_t m = nblocks * kRadix;
-  return (size_t)m * sizeof(uint32_t) * 2 + scan_temp_bytes(m) + 256;
+  return (size_t)(m + kRadix) * sizeof(uint32_t) + 256;
 }
 
 template <class K>
@@ -214,9 +264,8 @@ static hipError_t radix_sort_t(K* keys, uint32_t* vals, K* keys_alt, uint32_t* v
   if (n <= 1) return hipSuccess;
   const int nblocks = (int)ceil_div(n, kSortTile);
   const int64_t m = (int64_t)nblocks * kRadix;
-  uint32_t* hist = static_cast<uint32_t*>(temp);
-  uint32_t* offs = hist + m;
-  void* stemp = offs + m;
+  uint32_t* hist = static_cast<uint32_t*>(temp);  // becomes the row-scanned offsets
+  uint32_t* totals = hist + m;
   K* kin = keys;
   uint32_t* vin = vals;
   K* kout = keys_alt;
@@ -226,9 +275,11 @@ static hipError_t radix_sort_t(K* keys, uint32_t* vals, K* keys_alt, uint32_t* v
     k_radix_hist<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, n, shift, hist, nblocks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_exclusive_scan(hist, offs, m, stemp, s);
+    k_radix_rowscan<<<dim3(kRadix), dim3(kScanBlock), 0, s>>>(hist, nblocks, totals);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_radix_scatter<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, vin, kout, vout, n, shift, offs, nblocks);
+    k_radix_scatter<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, vin, kout, vout, n, shift, hist, totals,
+                                                                    nblocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* tk = kin; kin = kout; kout = tk;
