@@ -254,7 +254,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       c.add(&hit_n, nv1);
       if (state_out) {
         c.add(&slot_offs, nv1);
-        c.add(&st->bwd_mismatch, 1);
+        c.add(&st->bwd_mismatch, std::max<int64_t>(total_tiles, 1));
       }
       c.add(&hit_list, nv1 * kBinHitList);
       c.add(&offsets, nv1);

@@ -28,7 +28,7 @@ struct cg_fwd_state {
   cg_allocator alloc{nullptr, nullptr, nullptr};
   hipStream_t stream = nullptr;
   std::vector<void*> blocks;          // scratch owned by the state
-  uint32_t* bwd_mismatch = nullptr;   // device counter the backward replay adds to
+  uint32_t* bwd_mismatch = nullptr;   // per tile: the backward replay's mismatched pixels
   hipStream_t bwd_stream = nullptr;   // stream of the last backward call
   bool bwd_ran = false;               // a backward call was enqueued on this state
 };

@@ -39,7 +39,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                     const float* __restrict__ out_rgba,
                                                     const float* __restrict__ final_T,
                                                     const float* __restrict__ grad_rgba, float* __restrict__ partial,
-                                                    unsigned int* __restrict__ mismatch) {
+                                                    unsigned int* __restrict__ mismatch,
+                                                    uint32_t* __restrict__ n_long) {
   __shared__ Record srec[64];
   __shared__ float gacc[4][64][kGradLen + 1];
   // per-pixel constants read only where a pair contributes, kept in LDS (each thread its
@@ -49,6 +50,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int v = view_of_tile(cams, n_views, t);
   const DevCamera& c = cams[v];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_long = 0u;  // the slot sums' long-item counter
   int i, j;
   tile_pixel(c, t - c.tile_offset, threadIdx.x, i, j);
   const bool inside = i < c.crop_w && j < c.crop_h;
@@ -168,8 +170,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // pairs after the point where every pixel of the tile had terminated get no gradient
   for (int64_t e = threadIdx.x; e < (int64_t)(rg.y - stop_at) * kGradLen; e += 256)
     partial[(int64_t)sorted_slots[stop_at + e / kGradLen] * kGradLen + e % kGradLen] = 0.f;
-  // pixels that ran to the end of their list must have reached the stored transmittance
-  if (valid && !done && Ttr != (inside ? final_T[p] : 1.f)) atomicAdd(mismatch, 1u);
+  // pixels that ran to the end of their list must have reached the stored transmittance;
+  // the tile's count of those that did not (every entry written: no zeroing needed)
+  const int bad = __syncthreads_count(valid && !done && Ttr != (inside ? final_T[p] : 1.f));
+  if (threadIdx.x == 0) mismatch[blockIdx.x] = (unsigned int)bad;
 }
 
 // Per (view, Gaussian) item: sum of its pairs' partials, gradient slots [off, off + cnt),
@@ -482,20 +486,21 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
 
 template <int FILTER, bool MARGINAL, bool GEER>
 static void launch_bwd_g(const cg_fwd_state* st, const float* grad_rgba, float* partial, unsigned int* mismatch,
-                         hipStream_t s) {
+                         uint32_t* n_long, hipStream_t s) {
   k_render_bwd<FILTER, MARGINAL, GEER><<<dim3((unsigned)st->total_tiles), dim3(256), 0, s>>>(
       st->dcams, st->n_views, (int)st->total_tiles, st->opts, st->rec, st->g.n, st->ranges, st->tile_order,
       st->sorted_gid,
-      st->sorted_slots, st->pix, st->wmask, st->mask_words, st->out_rgba, st->final_T, grad_rgba, partial, mismatch);
+      st->sorted_slots, st->pix, st->wmask, st->mask_words, st->out_rgba, st->final_T, grad_rgba, partial, mismatch,
+      n_long);
 }
 
 template <int FILTER, bool MARGINAL>
 static void launch_bwd_t(const cg_fwd_state* st, const float* grad_rgba, float* partial, unsigned int* mismatch,
-                         hipStream_t s) {
+                         uint32_t* n_long, hipStream_t s) {
   if (st->opts.backbone == CG_BACKBONE_RAY_INTEGRAL)
-    launch_bwd_g<FILTER, MARGINAL, true>(st, grad_rgba, partial, mismatch, s);
+    launch_bwd_g<FILTER, MARGINAL, true>(st, grad_rgba, partial, mismatch, n_long, s);
   else
-    launch_bwd_g<FILTER, MARGINAL, false>(st, grad_rgba, partial, mismatch, s);
+    launch_bwd_g<FILTER, MARGINAL, false>(st, grad_rgba, partial, mismatch, n_long, s);
 }
 
 void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, float* d_log_scales, float* d_quats,
@@ -520,20 +525,22 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
     c.add(&n_long, 1);
     sc.get(c);
   }
-  CG_HIP(launch_fill_u32(mismatch, 0u, 1, s));
+  // k_render_bwd zeroes n_long (and writes every tile's mismatch count); without pairs
+  // it does not run
+  if (st->P == 0) CG_HIP(launch_fill_u32(n_long, 0u, 1, s));
   if (st->P > 0) {
     ProfScope ps(ST_BWD_RENDER, s);
     const Opts& o = st->opts;
     const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
     switch (o.filter_mode) {
-      case CG_FILTER_CENTER_RAY: launch_bwd_t<0, false>(st, grad_rgba, partial, mismatch, s); break;
+      case CG_FILTER_CENTER_RAY: launch_bwd_t<0, false>(st, grad_rgba, partial, mismatch, n_long, s); break;
       case CG_FILTER_ISOTROPIC:
-        if (marginal) launch_bwd_t<2, true>(st, grad_rgba, partial, mismatch, s);
-        else launch_bwd_t<2, false>(st, grad_rgba, partial, mismatch, s);
+        if (marginal) launch_bwd_t<2, true>(st, grad_rgba, partial, mismatch, n_long, s);
+        else launch_bwd_t<2, false>(st, grad_rgba, partial, mismatch, n_long, s);
         break;
       default:
-        if (marginal) launch_bwd_t<1, true>(st, grad_rgba, partial, mismatch, s);
-        else launch_bwd_t<1, false>(st, grad_rgba, partial, mismatch, s);
+        if (marginal) launch_bwd_t<1, true>(st, grad_rgba, partial, mismatch, n_long, s);
+        else launch_bwd_t<1, false>(st, grad_rgba, partial, mismatch, n_long, s);
     }
     CG_HIP(hipGetLastError());
   }
@@ -541,7 +548,6 @@ void run_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, floa
     ProfScope ps(ST_BWD_REDUCE, s);
     const int64_t waves = (nv + kReduceChunk - 1) / kReduceChunk;
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, kReduceBlocks);
-    CG_HIP(launch_fill_u32(n_long, 0u, 1, s));
     k_reduce_items<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(st->counts, st->offsets, nv,
                                                                 partial, item_grad, long_items, n_long);
     CG_HIP(hipGetLastError());
@@ -580,9 +586,13 @@ extern "C" cg_status cg_render_backward(cg_fwd_state* st, const float* grad_rgba
 
 extern "C" int64_t cg_bwd_replay_mismatches(const cg_fwd_state* st) {
   if (!st || !st->bwd_ran) return -1;
-  unsigned int host = 0;
-  if (hipMemcpyAsync(&host, st->bwd_mismatch, 4, hipMemcpyDeviceToHost, st->bwd_stream) != hipSuccess ||
+  if (st->P == 0) return 0;  // nothing was replayed
+  std::vector<uint32_t> host((size_t)st->total_tiles);
+  if (hipMemcpyAsync(host.data(), st->bwd_mismatch, host.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                     st->bwd_stream) != hipSuccess ||
       hipStreamSynchronize(st->bwd_stream) != hipSuccess)
     return -1;
-  return host;
+  int64_t total = 0;
+  for (uint32_t x : host) total += x;
+  return total;
 }
