@@ -343,11 +343,16 @@ __global__ __launch_bounds__(256) void k_reduce_long(const uint32_t* __restrict_
 
 // Preprocess backward: per Gaussian, the per-view record gradients back to the raw
 // parameters (activations of Sec. 3, the floor of Eq. 10, the colour).  Views are
-// summed in index order; outputs are overwritten.
+// summed in index order; outputs are overwritten.  Each view's gradient row is read
+// once, as five 16-byte loads; the colour gradients of the first kBwdKeepViews views
+// wait in LDS for the colour passes (a strided 4-byte re-read of the rows there, after
+// they have left the caches, fetched whole lines for one word each).
+constexpr int kBwdKeepViews = 4;
 __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCamera* __restrict__ cams, int n_views, Opts o,
                                  const float* __restrict__ item_grad, float* __restrict__ d_means,
                                  float* __restrict__ d_log_scales, float* __restrict__ d_quats,
                                  float* __restrict__ d_logits, float* __restrict__ d_color) {
+  __shared__ float s_dc[kBwdKeepViews][3][256];  // each thread its own column
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = g.n;
   if (i >= n) return;
@@ -378,7 +383,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
   for (int k = 0; k < 9; ++k) dR[k] = 0.f;
 #pragma unroll 1
   for (int v = 0; v < n_views; ++v) {
-    const float* gr = item_grad + ((int64_t)v * n + i) * kGradLen;
+    static_assert(kGradLen == 20, "a gradient row is five float4");
+    const float4* r4 = reinterpret_cast<const float4*>(item_grad + ((int64_t)v * n + i) * kGradLen);
+    const float4 r0 = r4[0], r1 = r4[1], r2 = r4[2], r3 = r4[3], r4v = r4[4];
+    const float gr[19] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y,
+                          r2.z, r2.w, r3.x, r3.y, r3.z, r3.w, r4v.x, r4v.y, r4v.z};
+    if (v < kBwdKeepViews) {
+      s_dc[v][0][threadIdx.x] = gr[16];
+      s_dc[v][1][threadIdx.x] = gr[17];
+      s_dc[v][2][threadIdx.x] = gr[18];
+    }
     // W[a][b] = R[b][a] / s'_a
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -406,7 +420,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
     for (int ch = 0; ch < 3; ++ch) {
       float acc = 0.f;
 #pragma unroll 1
-      for (int v = 0; v < n_views; ++v) acc += item_grad[((int64_t)v * n + i) * kGradLen + 16 + ch];
+      for (int v = 0; v < n_views; ++v)
+        acc += v < kBwdKeepViews ? s_dc[v][ch][threadIdx.x] : item_grad[((int64_t)v * n + i) * kGradLen + 16 + ch];
       d_color[(int64_t)ch * n + i] = acc;
     }
   } else {
@@ -420,7 +435,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(GaussPtrs g, const DevCa
       }
 #pragma unroll 1
       for (int v = 0; v < n_views; ++v) {
-        const float drgb = item_grad[((int64_t)v * n + i) * kGradLen + 16 + ch];
+        const float drgb =
+            v < kBwdKeepViews ? s_dc[v][ch][threadIdx.x] : item_grad[((int64_t)v * n + i) * kGradLen + 16 + ch];
         const DevCamera& c = cams[v];
         const double vd[3] = {(double)mu[0] - c.o[0], (double)mu[1] - c.o[1], (double)mu[2] - c.o[2]};
         const double dist = sqrt(vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]);
