@@ -231,6 +231,9 @@ cg_status cg_render_forward_noalloc(const cg_gaussians* g /* host struct, device
 cg_status cg_render_backward(cg_fwd_state* st, const float* grad_rgba, float* d_means, float* d_log_scales,
                              float* d_quats, float* d_opacity_logits, float* d_color, hipStream_t stream);
 
+/* Releases a forward state: its blocks go back to the allocator in the order of the
+ * forward's stream, after waiting for the last backward on it if that ran on another
+ * stream.  NULL is a no-op. */
 void cg_fwd_state_release(cg_fwd_state* st);
 
 /* Diagnostic of the last cg_render_backward on `st`: the number of pixels whose

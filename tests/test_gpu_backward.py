@@ -139,6 +139,43 @@ def test_backward_deterministic_and_autograd():
         assert np.array_equal(p.grad.cpu().numpy().astype(np.float64), g1[k]), k
 
 
+def test_backward_repeated_and_on_a_side_stream():
+    """The backward returns without a host synchronisation, and its counters live in the
+    forward state or its own scratch: two backward calls on one state, the second on
+    another stream, give identical gradients and exact replays, and the state can be
+    released after a backward on another stream."""
+    import torch
+    from paper_2609_13397_amd import render as R
+    scene = grad_scene(seed=5)
+    scene["rho2"] = O.bake_rho2(scene, grad_cameras(2.0)).astype(np.float32)
+    cams = grad_cameras()
+    opts = R.RenderOpts(use_floor=True)
+    _say("backward twice on one state, the second on a side stream")
+    sc = R.Scene.from_numpy(scene)
+    _, _, state = R.render_forward(sc, cams, opts, need_state=True)
+    G = torch.from_numpy(np.concatenate([synth.seeded_image((c["crop"][3], c["crop"][2], 4), seed=31 + v).reshape(-1, 4)
+                                         for v, c in enumerate(cams)]).astype(np.float32)).cuda()
+    g1 = R.render_backward(state, G, sc)
+    m1 = R.replay_mismatches(state)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g2 = R.render_backward(state, G, sc)
+    state.release()  # waits for the side stream's backward before the blocks go back
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert m1 == 0
+    for k in GROUPS:
+        assert torch.equal(g1[k], g2[k]), k
+    _, _, state = R.render_forward(sc, cams, opts, need_state=True)
+    with torch.cuda.stream(side):
+        side.wait_stream(torch.cuda.default_stream())
+        R.render_backward(state, G, sc)
+    assert R.replay_mismatches(state) == 0  # read after the side stream's backward
+    state.release()
+    torch.cuda.synchronize()
+
+
 def test_autograd_refuses_inputs_changed_in_place():
     """The backward reads the forward image and the parameters: changing either in
     place between the forward and the backward makes autograd raise instead of giving
