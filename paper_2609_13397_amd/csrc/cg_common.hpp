@@ -193,8 +193,9 @@ hipError_t launch_view_stats(const DevCamera* cams, int n_views, const uint2* ra
 size_t scan_temp_bytes(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s);
 size_t radix_temp_bytes(int64_t n);
-// Sorts (keys, vals) stably on bits [0, end_bit); returns 0 if the result is in
-// (keys, vals) and 1 if it is in (keys_alt, vals_alt).
+// Sorts (keys, vals) stably on bits [0, end_bit) (bits from end_bit up ride along and
+// need not be zero); returns 0 if the result is in (keys, vals) and 1 if it is in
+// (keys_alt, vals_alt).
 hipError_t launch_radix_sort32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
                                int end_bit, void* temp, int* result_in_alt, hipStream_t s);
 

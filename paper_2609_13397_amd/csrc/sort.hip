@@ -108,7 +108,7 @@ constexpr int kSortTile = kSortBlock * kSortRounds;             // 4096 items pe
 constexpr int kWaveItems = 64 * kSortRounds;                    // 1024 items per wave
 
 template <class K>
-__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t n, int shift,
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__ keys, int64_t n, int shift, uint32_t dmask,
                                                            uint32_t* __restrict__ hist, int nblocks) {
   __shared__ uint32_t cnt[kRadix];
   cnt[threadIdx.x] = 0;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* __restrict__
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int k = 0; k < kSortRounds; ++k) {
     const int64_t idx = base + (int64_t)k * kSortBlock + threadIdx.x;
-    if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & (kRadix - 1)], 1u);
+    if (idx < n) atomicAdd(&cnt[(uint32_t)(keys[idx] >> shift) & dmask], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
@@ -167,7 +167,7 @@ template <class K>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restrict__ kin,
                                                               const uint32_t* __restrict__ vin,
                                                               K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                              int64_t n, int shift,
+                                                              int64_t n, int shift, uint32_t dmask,
                                                               const uint32_t* __restrict__ offsets,
                                                               const uint32_t* __restrict__ totals, int nblocks) {
   __shared__ uint32_t wcnt[4][kRadix];
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
     const bool ok = idx < n;
     key[r] = ok ? kin[idx] : K(0);
     val[r] = ok ? vin[idx] : 0u;
-    const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
     uint64_t peers = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     if (rank[r] == 0xffffffffu) continue;
-    const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
     const uint32_t lpos = wcnt[wave][d] + rank[r];
     skey[lpos] = key[r];
     sval[lpos] = val[r];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* __restric
   const int cnt = (int)min((int64_t)kSortTile, n - bbase);
   for (int i = threadIdx.x; i < cnt; i += kSortBlock) {
     const K k = skey[i];
-    const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+    const uint32_t d = (uint32_t)(k >> shift) & dmask;
     const int64_t pos = gdelta[d] + i;
     kout[pos] = k;
     vout[pos] = sval[i];
@@ -272,13 +272,15 @@ static hipError_t radix_sort_t(K* keys, uint32_t* vals, K* keys_alt, uint32_t* v
   uint32_t* vout = vals_alt;
   int alt = 0;
   for (int shift = 0; shift < end_bit; shift += kRadixBits) {
-    k_radix_hist<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, n, shift, hist, nblocks);
+    // the last pass's digit stops at end_bit: bits above it may hold other data
+    const uint32_t dmask = end_bit - shift >= kRadixBits ? (uint32_t)(kRadix - 1) : (1u << (end_bit - shift)) - 1u;
+    k_radix_hist<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, n, shift, dmask, hist, nblocks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_radix_rowscan<<<dim3(kRadix), dim3(kScanBlock), 0, s>>>(hist, nblocks, totals);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_radix_scatter<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, vin, kout, vout, n, shift, hist, totals,
+    k_radix_scatter<K><<<dim3(nblocks), dim3(kSortBlock), 0, s>>>(kin, vin, kout, vout, n, shift, dmask, hist, totals,
                                                                     nblocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
