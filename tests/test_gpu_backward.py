@@ -260,3 +260,9 @@ def test_backward_degenerate_inputs():
     assert m1 == 0 and m2 == 0
     for k in GROUPS:
         np.testing.assert_allclose(g2[k], g1[k], rtol=1e-6, atol=1e-9, err_msg=k)
+    _say("backward of a call whose views are all empty")
+    c0 = synth.with_crop(cam, 0, 0, 0, 0)
+    g, _, info, mism = run_gpu(scene, [c0, c0], R.RenderOpts(), [np.zeros((0, 0, 4), np.float32)] * 2)
+    assert info["n_pairs"] == 0 and mism == 0
+    for k in GROUPS:
+        assert g[k].size > 0 and np.all(g[k] == 0.0), k

@@ -293,6 +293,9 @@ def test_empty_and_degenerate_inputs():
     imgs, info = gpu_render(scene, [c0, cam], R.RenderOpts())
     assert imgs[0].shape == (0, 0, 4)
     check_view(imgs[1], scene, cam, O.Opts())
+    # every view empty: a call without a single tile
+    imgs, info = gpu_render(scene, [c0, c0], R.RenderOpts())
+    assert all(im.shape == (0, 0, 4) for im in imgs) and info["n_pairs"] == 0
 
 
 def test_large_gaussians_cover_many_tile_groups():
