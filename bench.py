@@ -587,8 +587,8 @@ def main():
         summarize_valu(*args.summarize_valu, args.command, args.kernel, sq2_csv=args.sq2)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
-              "is described in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path is not "
+              "built for more than one GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -93,12 +93,12 @@ def test_eq9_on_axis_isotropic_closed_form(f):
     alpha = math.atan(1.0 / (2.0 * f))
     expect = sig / (1.0 + (t / s32) ** 2 * math.sin(alpha) ** 2 / 3.0)
     assert res[0, 0] == pytest.approx(expect, rel=1e-12)
-    if f == 60.0:  # the survey-time worked value T / sigma for f = 60, t = 3, s = e^-3
+    if f == 60.0:  # T / sigma for f = 60, t = 3, s = e^-3, worked out by hand from Eq. 9
         assert expect / sig == pytest.approx(0.922474, abs=5e-7)
 
 
 def test_eq9_off_axis_isotropic_closed_form_pinhole_and_kb():
-    """Off-axis pixels (spec check c): the same isotropic Gaussian on the centre ray of
+    """Off-axis pixels (camera-model check): the same isotropic Gaussian on the centre ray of
     pixel (u, v) gives T = sigma / sqrt(det(I + E^T E/3)) with E from each camera's own
     rays.  The rays here come from the camera formulas written out in this test."""
     t, s = 4.0, math.exp(-3.5)
@@ -204,7 +204,7 @@ def test_eq9_eq12_whitened_route_equals_world_route(use_floor):
 
 
 def test_zero_footprint_limit_is_centre_ray_and_quadratic():
-    """North-star check (b): footprint_scale = 0 gives the centre-ray response of Eq. 3
+    """Zero-footprint limit: footprint_scale = 0 gives the centre-ray response of Eq. 3
     (C = 1) exactly, and T(eps) - T(0) = O(eps^2)."""
     scene = synth.make_scene(40, seed=12, layout="uniform", color="rgb")
     cam = pinhole(24, 18, 20.0, origin=(0.0, 0.0, -3.0))
@@ -315,7 +315,7 @@ def test_marginal_clamp_is_directionwise():
 # ----------------------------------------------------------------------------- compositing (Eq. 4)
 
 def test_compositing_invariants():
-    """North-star check (d): transmittance monotone, total alpha in [0, 1], colour bounded
+    """Compositing invariants: transmittance monotone, total alpha in [0, 1], colour bounded
     by alpha times the largest colour; alpha = 1 - prod(1 - alpha_k)."""
     scene, cam = synth.tiny_config()
     out = O.render(scene, cam)
@@ -474,7 +474,7 @@ def test_equirect_longitude_and_latitude_at_known_pixels():
 
 
 def test_pinhole_vs_zero_distortion_fisheye_paraxial():
-    """North-star check (c): a pinhole and a zero-distortion fisheye with the same focal
+    """Camera-model check: a pinhole and a zero-distortion fisheye with the same focal
     length see the same rays near the axis (they differ by f |tan(theta) - theta| pixels),
     so their renders agree there."""
     scene, _ = synth.tiny_config()
