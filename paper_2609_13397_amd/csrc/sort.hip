@@ -64,6 +64,51 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ 
     if (base + k < n) out[base + k] += add;
 }
 
+// Two-launch scan for up to kScanTile tiles (reduce, then scan): the first launch sums
+// each tile, the second has every block add the sums of the tiles before its own (at
+// most kScanTile of them, eight per thread) to its tile's local scan.
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                            uint32_t* __restrict__ partials) {
+  __shared__ uint32_t wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) local += (base + k < n) ? in[base + k] : 0u;
+  for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_final(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                           int64_t n, const uint32_t* __restrict__ partials) {
+  __shared__ uint32_t wsum[4], psum[4];
+  // the sum of the tiles before this one
+  uint32_t before = 0;
+  for (int t = (int)threadIdx.x; t < (int)blockIdx.x; t += kScanBlock) before += partials[t];
+  for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    local += v[k];
+  }
+  const uint32_t incl = wave_incl_scan(local);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) wsum[w] = incl;
+  if ((threadIdx.x & 63) == 0) psum[w] = before;
+  __syncthreads();
+  uint32_t run = psum[0] + psum[1] + psum[2] + psum[3] + incl - local;
+  for (int k = 0; k < w; ++k) run += wsum[k];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+}
+
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 size_t scan_temp_bytes(int64_t n) {
@@ -95,6 +140,15 @@ static hipError_t scan_rec(const uint32_t* in, uint32_t* out, int64_t n, uint32_
 
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  const int64_t blocks = ceil_div(n, kScanTile);
+  if (blocks > 1 && blocks <= kScanTile) {  // reduce, then scan: two launches
+    uint32_t* part = static_cast<uint32_t*>(temp);
+    k_scan_reduce<<<dim3((unsigned)blocks), dim3(kScanBlock), 0, s>>>(in, n, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_scan_final<<<dim3((unsigned)blocks), dim3(kScanBlock), 0, s>>>(in, out, n, part);
+    return hipGetLastError();
+  }
   return scan_rec(in, out, n, static_cast<uint32_t*>(temp), s);
 }
 
