@@ -301,9 +301,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       sorted_items = d_alt ? items_alt : items;
       {
         ProfScope ps(ST_SCAN, s);
-        CG_HIP(launch_gather_total(counts, sorted_items, nv, counts_sorted, pair_total, s));
-        CG_HIP(launch_exclusive_scan(counts_sorted, offs_sorted, nv, scan_tmp, s));
-        CG_HIP(launch_scatter_u32(offs_sorted, sorted_items, nv, offsets, s));
+        CG_HIP(launch_permuted_scan(counts, sorted_items, nv, counts_sorted, offs_sorted, offsets, pair_total, scan_tmp,
+                                    s));
         // training: the pairs' gradient slots are laid out item by item (each item's
         // slots contiguous, items in index order), so that the backward's per-item sums
         // read and write in one front-to-back sweep

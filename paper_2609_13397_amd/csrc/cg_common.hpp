@@ -192,6 +192,13 @@ hipError_t launch_view_stats(const DevCamera* cams, int n_views, const uint2* ra
 // sort.hip
 size_t scan_temp_bytes(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s);
+// out[perm[k]] = sum of vals[perm[k']] over k' < k (the exclusive scan in the order perm
+// gives, written back in vals' order), vals_perm[k] = vals[perm[k]], and the sum of all
+// added to *total (64 bits, zeroed beforehand).  vals_perm_scan: scratch of n words for
+// the many-tile path; temp: scan_temp_bytes(n).
+hipError_t launch_permuted_scan(const uint32_t* vals, const uint32_t* perm, int64_t n, uint32_t* vals_perm,
+                                uint32_t* vals_perm_scan, uint32_t* out, unsigned long long* total, void* temp,
+                                hipStream_t s);
 size_t radix_temp_bytes(int64_t n);
 // Sorts (keys, vals) stably on bits [0, end_bit) (bits from end_bit up ride along and
 // need not be zero); returns 0 if the result is in (keys, vals) and 1 if it is in

@@ -109,6 +109,65 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_final(const uint32_t* __res
   }
 }
 
+// The same two launches for a scan in a permuted order, scattered back: the first
+// gathers vals[perm[k]] (kept in vals_perm), sums each tile and adds the tile's sum to
+// *total (64 bits); the second scans vals_perm and writes each prefix to out[perm[k]].
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce_perm(const uint32_t* __restrict__ vals,
+                                                                 const uint32_t* __restrict__ perm, int64_t n,
+                                                                 uint32_t* __restrict__ vals_perm,
+                                                                 uint32_t* __restrict__ partials,
+                                                                 unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? vals[perm[base + k]] : 0u;
+  unsigned long long local = 0;  // the exact total in 64 bits: 32-bit sums may wrap
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) vals_perm[base + k] = v[k];
+    local += v[k];
+  }
+  for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    partials[blockIdx.x] = (uint32_t)t;  // wraps only where the 64-bit total rejects the call
+    atomicAdd(total, t);
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_final_perm(const uint32_t* __restrict__ vals_perm,
+                                                                const uint32_t* __restrict__ perm, int64_t n,
+                                                                const uint32_t* __restrict__ partials,
+                                                                uint32_t* __restrict__ out) {
+  __shared__ uint32_t wsum[4], psum[4];
+  uint32_t before = 0;
+  for (int t = (int)threadIdx.x; t < (int)blockIdx.x; t += kScanBlock) before += partials[t];
+  for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? vals_perm[base + k] : 0u;
+    local += v[k];
+  }
+  const uint32_t incl = wave_incl_scan(local);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) wsum[w] = incl;
+  if ((threadIdx.x & 63) == 0) psum[w] = before;
+  __syncthreads();
+  uint32_t run = psum[0] + psum[1] + psum[2] + psum[3] + incl - local;
+  for (int k = 0; k < w; ++k) run += wsum[k];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[perm[base + k]] = run;
+    run += v[k];
+  }
+}
+
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 size_t scan_temp_bytes(int64_t n) {
@@ -136,6 +195,26 @@ static hipError_t scan_rec(const uint32_t* in, uint32_t* out, int64_t n, uint32_
   if (e != hipSuccess) return e;
   k_scan_add<<<dim3((unsigned)blocks), dim3(kScanBlock), 0, s>>>(out, n, part_scan);
   return hipGetLastError();
+}
+
+hipError_t launch_permuted_scan(const uint32_t* vals, const uint32_t* perm, int64_t n, uint32_t* vals_perm,
+                                uint32_t* vals_perm_scan, uint32_t* out, unsigned long long* total, void* temp,
+                                hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = ceil_div(n, kScanTile);
+  if (blocks <= kScanTile) {
+    uint32_t* part = static_cast<uint32_t*>(temp);
+    k_scan_reduce_perm<<<dim3((unsigned)blocks), dim3(kScanBlock), 0, s>>>(vals, perm, n, vals_perm, part, total);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_scan_final_perm<<<dim3((unsigned)blocks), dim3(kScanBlock), 0, s>>>(vals_perm, perm, n, part, out);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_gather_total(vals, perm, n, vals_perm, total, s);
+  if (e != hipSuccess) return e;
+  e = launch_exclusive_scan(vals_perm, vals_perm_scan, n, temp, s);
+  if (e != hipSuccess) return e;
+  return launch_scatter_u32(vals_perm_scan, perm, n, out, s);
 }
 
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s) {
