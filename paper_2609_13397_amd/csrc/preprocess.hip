@@ -202,8 +202,8 @@ __global__ __launch_bounds__(256) void k_preprocess(GaussPtrs g, const DevCamera
   else r.lim = 2.f * sinf(0.5f * gamma) + 1e-5f;
   if (live) cone[out] = make_float4(ux, uy, uz, chord_radius(gamma));
   // The wave's 64 records are consecutive in rec: staged in LDS and written back as 1 KiB
-  // contiguous stores (a direct 128-byte store per lane writes 16 bytes of 64 different
-  // lines per instruction, which reached HBM as 1.6 times the record bytes).
+  // contiguous stores (a direct 128-byte store per lane writes 16 bytes into each of 64
+  // different lines per instruction; a staged one, 1 KiB into 8 whole lines).
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float4* __restrict__ stage = s_rec[wave];
   const float4* rv = reinterpret_cast<const float4*>(&r);
