@@ -18,7 +18,7 @@ namespace cg {
 
 constexpr int kMaxGroupHits = kBinHitList;
 constexpr int kPhase1Unroll = 8;
-constexpr int kPhase2Depth = 4;
+constexpr int kPhase2Depth = 2;
 
 __device__ __forceinline__ float readlane_f(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
