@@ -194,7 +194,12 @@ void cg_default_opts(cg_render_opts* opts /* host */);
  *              view: premultiplied RGB plus the background term, and alpha = 1 - T_final.
  *   state_out  NULL for inference; otherwise receives a state for cg_render_backward.
  *   stats_out  host, may be NULL.
- * The call synchronises `stream` once, to read back the number of pairs. */
+ * The call waits once for the work queued on `stream`, to read back the number of
+ * pairs.  A call shaped like the calling thread's previous one (same Gaussian count,
+ * views, tiles and pixels, and both with or both without state_out) sizes its pair
+ * buffers from that call's pair count and queues the pair emission before it waits;
+ * if its own count is larger, it emits again into buffers of the right size.  Images,
+ * counts and states do not depend on this. */
 cg_status cg_render_forward(const cg_gaussians* g /* host struct, device arrays */, const cg_camera* cams,
                             int32_t n_views, const cg_render_opts* opts /* host */, const cg_allocator* alloc,
                             float* out_rgba, cg_fwd_state** state_out, cg_fwd_stats* stats_out,

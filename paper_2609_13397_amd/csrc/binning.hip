@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
                                              const uint32_t* __restrict__ slot_offs, uint32_t* __restrict__ keys,
                                              uint32_t* __restrict__ vals, uint32_t* __restrict__ slot_gid,
                                              uint8_t* __restrict__ hit_n, uint16_t* __restrict__ hit_list,
-                                             uint2* __restrict__ clear_ranges, int64_t n_ranges) {
+                                             uint2* __restrict__ clear_ranges, int64_t n_ranges, uint32_t cap) {
   __shared__ __align__(16) uint16_t hitbuf[4][64 * kMaxGroupHits];  // per wave: the lanes' hit groups
   __shared__ uint32_t flat[4][64 * kMaxGroupHits];
   const int v = blockIdx.y;
@@ -136,13 +136,13 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const DevCamera* __restr
       const int gy = (int)(((float)gi + 0.5f) * inv_gx), gx = gi - gy * c.groups_x;
       const int tx = gx * kGroup + (lane % kGroup), ty = gy * kGroup + lane / kGroup;
       const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63) + l);
-      keys[pos] = (uint32_t)(c.tile_offset + ty * c.tiles_x + tx);
-      if (slot_gid) {
-        vals[pos] = slot0 + j;
-        slot_gid[slot0 + j] = gid;
-      } else {
-        vals[pos] = gid;
+      // pairs at or past cap are dropped (buffers sized before the pair count was known
+      // and found too small: the host emits again)
+      if (pos < cap) {
+        keys[pos] = (uint32_t)(c.tile_offset + ty * c.tiles_x + tx);
+        vals[pos] = slot_gid ? slot0 + j : gid;
       }
+      if (slot_gid && slot0 + j < cap) slot_gid[slot0 + j] = gid;
     }
     cnt += (uint32_t)__popcll(m);
   };
@@ -211,18 +211,19 @@ hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const
   if (n == 0 || n_views == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
   k_bin<false><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, counts, nullptr, nullptr, nullptr, nullptr,
-                                          nullptr, hit_n, hit_list, nullptr, 0);
+                                          nullptr, hit_n, hit_list, nullptr, 0, 0u);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
                            const float4* members, const uint32_t* offsets, const uint32_t* slot_offs,
                            uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, uint8_t* hit_n,
-                           uint16_t* hit_list, uint2* ranges, int64_t total_tiles, hipStream_t s) {
+                           uint16_t* hit_list, uint2* ranges, int64_t total_tiles, int64_t cap, hipStream_t s) {
   if (n == 0 || n_views == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s);
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_views);
   k_bin<true><<<grid, dim3(256), 0, s>>>(n, cams, cone, groups, members, nullptr, offsets, slot_offs, keys, vals,
-                                         slot_gid, hit_n, hit_list, ranges, total_tiles);
+                                         slot_gid, hit_n, hit_list, ranges, total_tiles,
+                                         (uint32_t)std::min<int64_t>(cap, 0xffffffffll));
   return hipGetLastError();
 }
 

@@ -174,6 +174,54 @@ int bits_for(int64_t v) {
   return b;
 }
 
+// A pinned host word per thread for the pair count's read-back (a copy into pageable
+// memory would not return before it completed); freed when the thread ends.
+struct PinnedWord {
+  unsigned long long* p = nullptr;
+  ~PinnedWord() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+unsigned long long* host_word() {
+  thread_local PinnedWord w;
+  if (!w.p) {
+    void* p = nullptr;
+    CG_HIP(hipHostMalloc(&p, 64, hipHostMallocPortable));
+    w.p = static_cast<unsigned long long*>(p);
+  }
+  return w.p;
+}
+
+// An event the host waits on: the pair count's copy, not the work queued after it.
+struct ReadEvent {
+  hipEvent_t e = nullptr;
+  ReadEvent() { CG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+  ~ReadEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  ReadEvent(const ReadEvent&) = delete;
+  ReadEvent& operator=(const ReadEvent&) = delete;
+};
+
+// The shape of a forward call and its pair count (-1: none), per thread.
+struct CallShape {
+  int64_t n = -1;
+  int n_views = 0;
+  int64_t total_tiles = 0, total_px = 0;
+  bool train = false;
+  int64_t pairs = -1;
+  bool same(const CallShape& o) const {
+    return n == o.n && n_views == o.n_views && total_tiles == o.total_tiles && total_px == o.total_px &&
+           train == o.train;
+  }
+};
+
+CallShape& last_call_shape() {
+  thread_local CallShape s;
+  return s;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------- forward
@@ -290,7 +338,6 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     // alone (it is consumed here): a tile holds pairs of one view only, so each tile's
     // list comes out in its view's depth order, equal keys in Gaussian index order,
     // whatever the order between views.
-    unsigned long long host_total = 0;
     const uint32_t* sorted_items = items;
     if (nv > 0) {
       int d_alt = 0;
@@ -308,30 +355,24 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
         // read and write in one front-to-back sweep
         if (slot_offs) CG_HIP(launch_exclusive_scan(counts, slot_offs, nv, scan_tmp, s));
       }
-      CG_HIP(hipMemcpyAsync(&host_total, pair_total, sizeof(host_total), hipMemcpyDeviceToHost, s));
+      CG_HIP(hipMemcpyAsync(host_word(), pair_total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     }
-    CG_HIP(hipStreamSynchronize(s));
-    // the exact 64-bit total: below the limit, the 32-bit offsets of the scan did not wrap
-    check_pair_total(host_total);
-    const int64_t P = (int64_t)host_total;
+    ReadEvent ev;
+    CG_HIP(hipEventRecord(ev.e, s));
 
     // phase 2 (sizes from the pair count): pairs emitted in compositing order, then
     // sorted stably by tile, per-tile ranges and the render's state
-    const int64_t P1 = std::max<int64_t>(P, 1);
     const bool ray_order = o.order_mode == CG_ORDER_RAY;
     // long lists on views with few tiles: each such view's longest list and pair count,
     // read back after the tile sort, decide whether its lists are cut into segments on
     // separate workgroups (per view, so that a view renders the same alone or fused)
     const SplitPolicy pol = split_policy();
-    bool may_split = false;
-    if (!st && !opts_in->count_pairs && !ray_order && P > 0)
-      for (int v = 0; v < n_views; ++v) {
-        const int64_t tv = (int64_t)hc[v].tiles_x * hc[v].tiles_y;
-        may_split = may_split || (tv > 0 && tv < pol.max_tiles);
-      }
-    // training: per wave, the pairs at which some pixel had alpha >= alpha_min (4 waves
-    // per tile; two words of slack so the backward can read the word after a batch)
-    const int64_t mask_words = P / 64 + 2;
+    bool small_views = false;
+    for (int v = 0; v < n_views; ++v) {
+      const int64_t tv = (int64_t)hc[v].tiles_x * hc[v].tiles_y;
+      small_views = small_views || (tv > 0 && tv < pol.max_tiles);
+    }
+    const bool split_candidate = !st && !opts_in->count_pairs && !ray_order && small_views;
     uint32_t *keys, *vals, *keys_alt, *vals_alt, *tile_order;
     uint32_t *slot_gid = nullptr, *sorted_gid_buf = nullptr, *n_last = nullptr;
     uint2* ranges;
@@ -339,7 +380,14 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
     unsigned long long *wmask = nullptr, *counters = nullptr;
     float *final_T = nullptr, *tlo_suffix = nullptr;
     uint32_t* view_stats = nullptr;
-    {
+    // training: per wave, the pairs at which some pixel had alpha >= alpha_min (4 waves
+    // per tile; two words of slack so the backward can read the word after a batch)
+    int64_t mask_words = 0, cap = -1;
+    // the phase-2 block for up to `pairs` pairs
+    auto carve_phase2 = [&](int64_t pairs) {
+      const int64_t P1 = std::max<int64_t>(pairs, 1);
+      cap = pairs;
+      mask_words = pairs / 64 + 2;
       Carve c;
       c.add(&keys, P1);
       c.add(&vals, P1);
@@ -347,7 +395,7 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       c.add(&vals_alt, P1);
       c.add(&ranges, std::max<int64_t>(total_tiles, 1));
       c.add(&tile_order, std::max<int64_t>(total_tiles, 1));
-      c.add_bytes(&sort_tmp, radix_temp_bytes(P));
+      c.add_bytes(&sort_tmp, radix_temp_bytes(pairs));
       if (st) {
         c.add(&slot_gid, P1);
         c.add(&sorted_gid_buf, P1);
@@ -358,18 +406,46 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       // counters [0..2]: pair counts (count_pairs); [3]: early composites (order_mode RAY)
       if (opts_in->count_pairs || ray_order) c.add(&counters, 4);
       if (ray_order) c.add(&tlo_suffix, P1);
-      if (may_split) c.add(&view_stats, 2 * (int64_t)n_views);
+      if (split_candidate) c.add(&view_stats, 2 * (int64_t)n_views);
       sc.get(c);
+    };
+    auto emit = [&]() {
+      ProfScope ps(ST_BIN_EMIT, s);
+      CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, offsets, slot_offs, keys, vals, slot_gid,
+                             hit_n, hit_list, ranges, total_tiles, cap, s));
+    };
+    // A call shaped like this thread's previous one (same Gaussian count, views, tiles
+    // and pixels, and both training or both not: a render or training loop) sizes
+    // phase 2 from that call's pair count, with a margin, and queues the emit pass
+    // before it waits for its own count: the GPU emits while the host reads the count
+    // back.  If the count exceeds the guess, the emit dropped the pairs past it; the
+    // block is carved again and the pass queued again.  Calls on a fixed scratch region
+    // do not guess.
+    const CallShape shape{n, n_views, total_tiles, total_px, st != nullptr, -1};
+    CallShape& last = last_call_shape();
+    const bool guess = !fixed && nv > 0 && last.pairs >= 0 && last.same(shape);
+    if (guess) {
+      carve_phase2(last.pairs + last.pairs / 16 + 4096);
+      emit();
     }
+    CG_HIP(hipEventSynchronize(ev.e));
+    const unsigned long long host_total = nv > 0 ? *host_word() : 0ull;
+    last.pairs = -1;  // (a failing call leaves no guess behind)
+    // the exact 64-bit total: below the limit, the 32-bit offsets of the scan did not wrap
+    check_pair_total(host_total);
+    const int64_t P = (int64_t)host_total;
+    if (!guess || P > cap) {
+      if (guess) sc.release_last();
+      carve_phase2(P);
+      if (P > 0) emit();
+    }
+    last = shape;
+    last.pairs = P;
+    const bool may_split = split_candidate && P > 0;
 
     const int tile_bits = bits_for(std::max<int64_t>(total_tiles - 1, 1));
     int in_alt = 0;
     if (P > 0) {
-      {
-        ProfScope ps(ST_BIN_EMIT, s);
-        CG_HIP(launch_bin_emit(n, n_views, dcams, cone, groups, members, offsets, slot_offs, keys, vals, slot_gid,
-                               hit_n, hit_list, ranges, total_tiles, s));
-      }
       {
         ProfScope ps(ST_SORT, s);
         CG_HIP(launch_radix_sort32(keys, vals, keys_alt, vals_alt, P, tile_bits, sort_tmp, &in_alt, s));

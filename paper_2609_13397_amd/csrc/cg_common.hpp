@@ -170,10 +170,11 @@ hipError_t launch_bin_count(int64_t n, int n_views, const DevCamera* cams, const
 // order).  Inference: vals = Gaussian index.  Training (slot_offs, slot_gid non-null):
 // vals = the pair's gradient slot slot_offs[gv] + j, and slot_gid[slot] = Gaussian.
 // The per-tile ranges (total_tiles entries) are zeroed on the side for k_tile_ranges.
+// Pairs at positions (and slots) from cap on are dropped: the buffers hold cap entries.
 hipError_t launch_bin_emit(int64_t n, int n_views, const DevCamera* cams, const float4* cone, const float4* groups,
                            const float4* members, const uint32_t* offsets, const uint32_t* slot_offs,
                            uint32_t* keys, uint32_t* vals, uint32_t* slot_gid, uint8_t* hit_n,
-                           uint16_t* hit_list, uint2* ranges, int64_t total_tiles, hipStream_t s);
+                           uint16_t* hit_list, uint2* ranges, int64_t total_tiles, int64_t cap, hipStream_t s);
 hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
 // The gather above that also adds the sum of the gathered values to *total (64 bits,
 // zeroed beforehand): the exact pair count, which 32-bit offsets cannot hold.

@@ -147,6 +147,7 @@ void free_block(const cg_allocator& a, void* p, hipStream_t s) {
 void Scratch::get(const Carve& c) {
   char* base = static_cast<char*>(get(c.bytes()));
   c.place(base);
+  last_guards_ = guards_.size();
   for (size_t off : c.guards()) {
     uint32_t* g = reinterpret_cast<uint32_t*>(base + off);
     CG_HIP(launch_fill_u32(g, kGuardWord, kGuardBytes / 4, s_));
@@ -168,6 +169,13 @@ void Scratch::check_guards() {
     throw Error(CG_ERR_STATE, "scratch guard bands overwritten: " + std::to_string(host_bad) + " word(s) in " +
                                   std::to_string(guards_.size()) + " guard bands");
   }
+}
+
+void Scratch::release_last() {
+  if (fixed_.base || blocks_.empty()) throw Error(CG_ERR_STATE, "no block to release");
+  free_block(user_, blocks_.back(), s_);
+  blocks_.pop_back();
+  guards_.resize(last_guards_);
 }
 
 void Scratch::release() {

@@ -110,6 +110,9 @@ class Scratch {
   // One block for every buffer of `c` (one allocator call per phase); writes the
   // guard bands, if any.
   void get(const Carve& c);
+  // Frees, in stream order, the block of the last get(const Carve&); its guard bands
+  // are no longer checked.  Not with a FixedRegion.
+  void release_last();
   // Compares every guard band written so far with its pattern (synchronises the
   // stream); throws CG_ERR_STATE if a word changed.  No-op without guard bands.
   void check_guards();
@@ -130,6 +133,7 @@ class Scratch {
   size_t fixed_used_ = 0;
   std::vector<void*> blocks_;
   std::vector<uint32_t*> guards_;
+  size_t last_guards_ = 0;  // guards_ before the last get(const Carve&)
 };
 
 void free_block(const cg_allocator& a, void* p, hipStream_t s);

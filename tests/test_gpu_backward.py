@@ -176,6 +176,31 @@ def test_backward_repeated_and_on_a_side_stream():
     torch.cuda.synchronize()
 
 
+def test_backward_after_pair_buffers_guessed_too_small():
+    """A training forward shaped like the previous one sizes its pair buffers from that
+    call's pair count; one with far more pairs emits again into buffers of the right
+    size.  Its gradients equal those of the same forward without a guess."""
+    import torch
+    from paper_2609_13397_amd import render as R
+    cams = grad_cameras()[:2]
+    opts = R.RenderOpts()
+    small = synth.make_scene(512, seed=6, layout="uniform", color="rgb", log_scale_mean=-4.0, log_scale_std=0.3)
+    big = dict(small)
+    big["log_scales"] = small["log_scales"] + 2.0
+    other = synth.subset_scene(small, np.arange(100))
+    G = [synth.seeded_image((c["crop"][3], c["crop"][2], 4), seed=51 + v) for v, c in enumerate(cams)]
+    _say("training forward + backward: big scene without a guess, then after the small one")
+    run_gpu(other, cams, opts, G)
+    g_ref, img_ref, info_ref, m_ref = run_gpu(big, cams, opts, G)
+    _, _, info_small, _ = run_gpu(small, cams, opts, G)
+    assert info_small["n_pairs"] + info_small["n_pairs"] // 16 + 4096 < info_ref["n_pairs"]
+    g, img, info, m = run_gpu(big, cams, opts, G)
+    assert m == 0 and m_ref == 0 and info["n_pairs"] == info_ref["n_pairs"]
+    assert torch.equal(img, img_ref)
+    for k in GROUPS:
+        assert np.array_equal(g[k], g_ref[k]), k
+
+
 def test_autograd_refuses_inputs_changed_in_place():
     """The backward reads the forward image and the parameters: changing either in
     place between the forward and the backward makes autograd raise instead of giving

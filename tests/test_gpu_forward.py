@@ -385,3 +385,46 @@ def test_contributing_pair_count_matches_oracle():
     _say(f"   gpu {info['n_contrib']} oracle {int(ref['n_contrib'].sum())} slack {slack}")
     assert abs(info["n_contrib"] - int(ref["n_contrib"].sum())) <= slack
     assert info["n_evaluated"] >= info["n_full"] >= info["n_contrib"] > 0
+
+
+def _two_pinholes():
+    cams = []
+    for phi in (0.3, 2.2):
+        o = (3.5 * math.cos(phi), 3.5 * math.sin(phi), 0.8)
+        cams.append(synth.camera(synth.PINHOLE, 128, 96, fx=90.0, fy=90.0, cx=64.0, cy=48.0,
+                                 R_c2w=synth.look_at(o, (0, 0, 0)), origin=o))
+    return cams
+
+
+def test_pair_buffers_sized_from_the_previous_call():
+    """A forward call shaped like the thread's previous one (same Gaussian count, views,
+    tiles and pixels) sizes its pair buffers from that call's pair count and queues the
+    emit pass before reading its own count back; when its count exceeds that guess, the
+    emit pass drops the pairs past it and the call emits again into buffers of the right
+    size.  Images and pair counts do not depend on the path taken."""
+    torch, R = _gpu()
+    cams = _two_pinholes()
+    opts = R.RenderOpts()
+    small = synth.make_scene(512, seed=5, layout="uniform", color="rgb", log_scale_mean=-4.0, log_scale_std=0.3)
+    big = dict(small)
+    big["log_scales"] = small["log_scales"] + 2.0
+    other = synth.subset_scene(small, np.arange(100))
+    _say("pair buffers: big scene after a call of another shape (no guess)")
+    gpu_render(other, cams, opts)
+    ref_big, info_big = gpu_render(big, cams, opts)
+    _say("small scene, guess from the big one (oversized)")
+    img_small, info_small = gpu_render(small, cams, opts)
+    assert info_small["n_pairs"] + info_small["n_pairs"] // 16 + 4096 < info_big["n_pairs"], (info_small, info_big)
+    _say("big scene, guess from the small one (too small: emitted again)")
+    img_big, info = gpu_render(big, cams, opts)
+    assert info["n_pairs"] == info_big["n_pairs"]
+    for a, b in zip(img_big, ref_big):
+        assert np.array_equal(a, b)
+    _say("small scene without a guess")
+    gpu_render(other, cams, opts)
+    ref_small, info = gpu_render(small, cams, opts)
+    assert info["n_pairs"] == info_small["n_pairs"]
+    for a, b in zip(img_small, ref_small):
+        assert np.array_equal(a, b)
+    for img, c in zip(ref_big, cams):
+        check_view(img, big, c, O.Opts())
