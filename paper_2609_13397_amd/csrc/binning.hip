@@ -282,8 +282,9 @@ hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t 
 }
 
 // Per-tile [start, end) ranges of the tile-sorted pair list.  `ranges` must be zeroed
-// beforehand (empty tiles keep (0, 0)).  With slot_gid, the sorted values are
-// emission slots and the Gaussian index of each sorted pair is gathered into sorted_gid.
+// beforehand (empty tiles keep (0, 0)).  With sorted_gid, each sorted pair's Gaussian
+// is gathered into it through slot_gid (the sorted values being slots), or, without
+// slot_gid, set to 0 (a valid index, for pairs whose Gaussian is filled in later).
 __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                               const uint32_t* __restrict__ slot_gid, int64_t n, uint2* __restrict__ ranges,
                               uint32_t* __restrict__ sorted_gid) {
@@ -295,7 +296,7 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const uint32_t*
   const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t tile = keys[i];
-  if (slot_gid) sorted_gid[i] = slot_gid[vals[i]];
+  if (sorted_gid) sorted_gid[i] = slot_gid ? slot_gid[vals[i]] : 0u;
   if (i == 0 || keys[i - 1] != tile) ranges[tile].x = (uint32_t)i;
   if (i == n - 1 || keys[i + 1] != tile) ranges[tile].y = (uint32_t)(i + 1);
 }

@@ -461,7 +461,11 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       ProfScope ps(ST_RANGES, s);
       // (the emit pass zeroed the ranges; with no pairs it did not run)
       if (P == 0) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
-      CG_HIP(launch_tile_ranges(skeys, svals, slot_gid, P, ranges, st ? sorted_gid : nullptr, s));
+      // training: each sorted pair's Gaussian is found through the slot table by the
+      // forward render when it stages the pair (it walks only the pairs before its
+      // tiles' termination, and its other loads hide the gather); here the entries get
+      // a valid index first
+      CG_HIP(launch_tile_ranges(skeys, svals, nullptr, P, ranges, st ? sorted_gid : nullptr, s));
       CG_HIP(launch_tile_order(ranges, (int)total_tiles, tile_order, s));
     }
     int64_t max_tile_pairs = -1;
@@ -512,7 +516,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       // the views rendered in whole tiles (the kernel skips the split views' tiles)
       if (n_split < n_views)
         CG_HIP(launch_render_fwd(dcams, n_views, (int)total_tiles, o, rec, n, ranges, tile_order, sorted_gid, pix,
-                                 tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, s));
+                                 tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters,
+                                 st ? SlotGather{svals, slot_gid, sorted_gid_buf} : SlotGather{}, s));
     }
     unsigned long long host_counters[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (counters && (opts_in->count_pairs || stats)) {

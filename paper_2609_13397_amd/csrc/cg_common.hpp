@@ -96,6 +96,31 @@ __device__ __forceinline__ void stage_records(Record* srec, const Record* __rest
   }
 }
 
+// Training forward: the sorted values are gradient slots.  The render kernel that
+// stages a pair finds its Gaussian in the slot table and stores it in gid_out, for the
+// backward (entries of pairs the forward never staged keep the value they had).
+struct SlotGather {
+  const uint32_t* slots = nullptr;
+  const uint32_t* slot_gid = nullptr;
+  uint32_t* gid_out = nullptr;
+};
+
+// stage_records for the training forward (TPR = 4): the Gaussian of each pair through
+// the slot table, also stored for the backward.
+__device__ __forceinline__ void stage_records_slots(Record* srec, const Record* __restrict__ vrec,
+                                                    const SlotGather& sg, uint32_t first, int count) {
+  constexpr int kTPR = 4, kVec = 8 / kTPR;
+  const int r = (int)(threadIdx.x / kTPR), part = (int)(threadIdx.x % kTPR);
+  if (r < count) {
+    const uint32_t gid = sg.slot_gid[sg.slots[first + (uint32_t)r]];
+    if (part == 0) sg.gid_out[first + (uint32_t)r] = gid;
+    const float4* src = reinterpret_cast<const float4*>(vrec + gid) + kVec * part;
+    float4* dst = reinterpret_cast<float4*>(srec + r) + kVec * part;
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) dst[k] = src[k];
+  }
+}
+
 // Hardware square root, reciprocal square root and reciprocal (about 1 ulp, no
 // correctly-rounded expansion): for per-pair arithmetic whose tolerance is far above
 // float32 rounding, and for conservative bounds that carry relative margins.
@@ -215,12 +240,13 @@ hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_til
                                hipStream_t s);
 // tile_order: the launch's tile sequence (launch_tile_order).  wmask (training forward,
 // else NULL): 4 bitsets of mask_words 64-bit words, zeroed beforehand; bit p of bitset
-// w is set when some pixel of wave w had alpha >= alpha_min at sorted pair p.
+// w is set when some pixel of wave w had alpha >= alpha_min at sorted pair p.  The
+// training forward finds each pair's Gaussian through sg (sorted_gid unused).
 hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
                              int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order,
                              const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix, float* out_rgba,
                              float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
-                             unsigned long long* counters, hipStream_t s);
+                             unsigned long long* counters, const SlotGather& sg, hipStream_t s);
 
 // Split tile render (long lists on views with few tiles; render_fwd.hip).  The tiles of
 // views with DevCamera::seg_len > 0 are cut into segments of that many pairs; the

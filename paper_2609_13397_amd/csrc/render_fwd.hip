@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                                                 const float4* __restrict__ pix, float* __restrict__ out_rgba,
                                                 float* __restrict__ final_T, uint32_t* __restrict__ n_last,
                                                 unsigned long long* __restrict__ wmask, int64_t mask_words,
-                                                unsigned long long* __restrict__ counters) {
+                                                unsigned long long* __restrict__ counters, SlotGather sg) {
   __shared__ Record srec[kFwdBatch];
   __shared__ unsigned int scount[3];
   uint32_t c_eval = 0, c_full = 0, c_contrib = 0;
@@ -58,7 +58,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   for (uint32_t base = rg.x; base < rg.y; base += kFwdBatch) {
     if (__syncthreads_count(!done) == 0) break;
     const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - base);
-    stage_records(srec, vrec, sorted_gid, base, cnt);
+    if (MASK)
+      stage_records_slots(srec, vrec, sg, base, cnt);
+    else
+      stage_records(srec, vrec, sorted_gid, base, cnt);
     __syncthreads();
     if (wc.live && __ballot(!done) != 0) {
       for (int sub = 0; sub < cnt; sub += 64) {
@@ -647,16 +650,16 @@ template <int FILTER, bool MARGINAL, bool GEER, bool COUNT>
 static void launch_key(const DevCamera* cams, int n_views, int total_tiles, const Opts& o, const Record* rec,
                        int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid,
                        const float4* pix, float* out_rgba, float* final_T, uint32_t* n_last, unsigned long long* wmask,
-                       int64_t mask_words, unsigned long long* counters, hipStream_t s) {
+                       int64_t mask_words, unsigned long long* counters, const SlotGather& sg, hipStream_t s) {
   const dim3 grid(total_tiles), block(256);
   if (wmask)
     k_render<FILTER, MARGINAL, COUNT, GEER, true><<<grid, block, 0, s>>>(
-        cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last,
-        wmask, mask_words, counters);
+        cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, nullptr, pix, out_rgba, final_T, n_last,
+        wmask, mask_words, counters, sg);
   else
     k_render<FILTER, MARGINAL, COUNT, GEER, false><<<grid, block, 0, s>>>(
         cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, out_rgba, final_T, n_last,
-        nullptr, 0, counters);
+        nullptr, 0, counters, SlotGather{});
 }
 
 template <int FILTER, bool MARGINAL, bool GEER>
@@ -664,7 +667,7 @@ static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, 
                            int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order, const uint32_t* sorted_gid,
                            const float4* pix, const float* tlo_suffix, float* out_rgba, float* final_T,
                            uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
-                           unsigned long long* counters, hipStream_t s) {
+                           unsigned long long* counters, const SlotGather& sg, hipStream_t s) {
   const dim3 grid(total_tiles), block(256);
   if (o.order_mode == CG_ORDER_RAY) {
     if (o.count_pairs)
@@ -676,11 +679,11 @@ static hipError_t launch_t(const DevCamera* cams, int n_views, int total_tiles, 
   } else if (o.count_pairs) {
     launch_key<FILTER, MARGINAL, GEER, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order,
                                             sorted_gid, pix, out_rgba, final_T, n_last, wmask, mask_words, counters,
-                                            s);
+                                            sg, s);
   } else {
     launch_key<FILTER, MARGINAL, GEER, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order,
                                              sorted_gid, pix, out_rgba, final_T, n_last, wmask, mask_words, nullptr,
-                                             s);
+                                             sg, s);
   }
   return hipGetLastError();
 }
@@ -690,13 +693,14 @@ static hipError_t launch_fm(const DevCamera* cams, int n_views, int total_tiles,
                             int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order,
                             const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix, float* out_rgba,
                             float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
-                            unsigned long long* counters, hipStream_t s) {
+                            unsigned long long* counters, const SlotGather& sg, hipStream_t s) {
   if (o.backbone == CG_BACKBONE_RAY_INTEGRAL)
     return launch_t<FILTER, MARGINAL, true>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order,
                                             sorted_gid, pix, tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words,
-                                            counters, s);
+                                            counters, sg, s);
   return launch_t<FILTER, MARGINAL, false>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid,
-                                           pix, tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, s);
+                                           pix, tlo_suffix, out_rgba, final_T, n_last, wmask, mask_words, counters, sg,
+                                           s);
 }
 
 hipError_t launch_order_bounds(const DevCamera* cams, int n_views, int total_tiles, const Record* rec,
@@ -711,12 +715,12 @@ hipError_t launch_render_fwd(const DevCamera* cams, int n_views, int total_tiles
                              int64_t n_gauss, const uint2* ranges, const uint32_t* tile_order,
                              const uint32_t* sorted_gid, const float4* pix, const float* tlo_suffix, float* out_rgba,
                              float* final_T, uint32_t* n_last, unsigned long long* wmask, int64_t mask_words,
-                             unsigned long long* counters, hipStream_t s) {
+                             unsigned long long* counters, const SlotGather& sg, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
   const bool marginal = o.use_floor && o.composition == CG_COMPOSE_MARGINAL;
 #define CG_FM(F, M)                                                                                                  \
   launch_fm<F, M>(cams, n_views, total_tiles, o, rec, n_gauss, ranges, tile_order, sorted_gid, pix, tlo_suffix,     \
-                  out_rgba, final_T, n_last, wmask, mask_words, counters, s)
+                  out_rgba, final_T, n_last, wmask, mask_words, counters, sg, s)
   switch (o.filter_mode) {
     case CG_FILTER_CENTER_RAY:
       return CG_FM(0, false);
