@@ -428,3 +428,25 @@ def test_pair_buffers_sized_from_the_previous_call():
         assert np.array_equal(a, b)
     for img, c in zip(ref_big, cams):
         check_view(img, big, c, O.Opts())
+
+
+def test_many_items_take_the_general_scans():
+    """Over 2048 x 2048 (view, Gaussian) items the counts scan in compositing order and
+    the plain scans fall back from their two-launch form to the general one: 1.1M
+    Gaussians in four small views (4.4M items) render bit for bit as each view does
+    alone (1.1M items, the two-launch form)."""
+    torch, R = _gpu()
+    scene = synth.make_scene(1_100_000, seed=19, layout="clusters", color="rgb", log_scale_mean=-4.5,
+                             log_scale_std=0.5)
+    cams = []
+    for phi in (0.0, 1.6, 3.1, 4.7):
+        o = (12.0 * math.cos(phi), 12.0 * math.sin(phi), 1.0)
+        cams.append(synth.camera(synth.PINHOLE, 160, 120, fx=120.0, fy=120.0, cx=80.0, cy=60.0,
+                                 R_c2w=synth.look_at(o, (0, 0, 0)), origin=o))
+    opts = R.RenderOpts()
+    _say("4 views of 1.1M Gaussians in one call (4.4M items)")
+    fused, info = gpu_render(scene, cams, opts)
+    assert info["n_pairs"] > 0
+    for v, c in enumerate(cams):
+        alone, _ = gpu_render(scene, [c], opts)
+        assert np.array_equal(alone[0], fused[v]), v
