@@ -282,29 +282,18 @@ hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t 
 }
 
 // Per-tile [start, end) ranges of the tile-sorted pair list.  `ranges` must be zeroed
-// beforehand (empty tiles keep (0, 0)).  With sorted_gid, each sorted pair's Gaussian
-// is gathered into it through slot_gid (the sorted values being slots), or, without
-// slot_gid, set to 0 (a valid index, for pairs whose Gaussian is filled in later).
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                              const uint32_t* __restrict__ slot_gid, int64_t n, uint2* __restrict__ ranges,
-                              uint32_t* __restrict__ sorted_gid) {
-  // Workgroup b runs on XCD b mod 8: each XCD takes one contiguous run of the blocks, so
-  // the neighbouring tiles of a row, which share most of their Gaussians, read the
-  // slot-to-Gaussian table through the same L2.
-  const unsigned nb = gridDim.x, q = nb / 8, r = nb % 8, x = blockIdx.x % 8;
-  const unsigned blk = x * q + min(x, r) + blockIdx.x / 8;
-  const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
+// beforehand (empty tiles keep (0, 0)).
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t n, uint2* __restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t tile = keys[i];
-  if (sorted_gid) sorted_gid[i] = slot_gid ? slot_gid[vals[i]] : 0u;
   if (i == 0 || keys[i - 1] != tile) ranges[tile].x = (uint32_t)i;
   if (i == n - 1 || keys[i + 1] != tile) ranges[tile].y = (uint32_t)(i + 1);
 }
 
-hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const uint32_t* slot_gid, int64_t n,
-                              uint2* ranges, uint32_t* sorted_gid, hipStream_t s) {
+hipError_t launch_tile_ranges(const uint32_t* keys, int64_t n, uint2* ranges, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_tile_ranges<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(keys, vals, slot_gid, n, ranges, sorted_gid);
+  k_tile_ranges<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(keys, n, ranges);
   return hipGetLastError();
 }
 

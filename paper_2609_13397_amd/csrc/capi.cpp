@@ -463,9 +463,8 @@ void run_forward(const cg_gaussians* g_in, const cg_camera* cams, int n_views, c
       if (P == 0) CG_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * total_tiles, s));
       // training: each sorted pair's Gaussian is found through the slot table by the
       // forward render when it stages the pair (it walks only the pairs before its
-      // tiles' termination, and its other loads hide the gather); here the entries get
-      // a valid index first
-      CG_HIP(launch_tile_ranges(skeys, svals, nullptr, P, ranges, st ? sorted_gid : nullptr, s));
+      // tiles' termination, and its other loads hide the gather)
+      CG_HIP(launch_tile_ranges(skeys, P, ranges, s));
       CG_HIP(launch_tile_order(ranges, (int)total_tiles, tile_order, s));
     }
     int64_t max_tile_pairs = -1;

@@ -206,8 +206,7 @@ hipError_t launch_gather_u32(const uint32_t* src, const uint32_t* idx, int64_t m
 hipError_t launch_gather_total(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst,
                                unsigned long long* total, hipStream_t s);
 hipError_t launch_scatter_u32(const uint32_t* src, const uint32_t* idx, int64_t m, uint32_t* dst, hipStream_t s);
-hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* vals, const uint32_t* slot_gid, int64_t n,
-                              uint2* ranges, uint32_t* sorted_gid, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* keys, int64_t n, uint2* ranges, hipStream_t s);
 // order: a permutation of the tiles, heaviest (most pairs) first, for the render launches
 hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
 // Per view v with fewer than max_tiles tiles: stats[2v] = its longest tile list,

@@ -24,6 +24,24 @@ namespace cg {
 
 constexpr int kGradLen = 20;  // dW[9] dmu[3] dsigma dsp2[3] drgb[3] pad (zero)
 
+// stage_records with each Gaussian index clamped into the records: the training
+// forward writes the indices of the pairs it stages, the same batches as an exact
+// replay, so only a replay that walks further than the forward (which the mismatch
+// diagnostic reports) reads entries it never wrote.
+__device__ __forceinline__ void stage_replay_records(Record* srec, const Record* __restrict__ vrec,
+                                                     const uint32_t* __restrict__ sorted_gid, int64_t n_gauss,
+                                                     uint32_t first, int count) {
+  constexpr int kTPR = 4, kVec = 8 / kTPR;
+  const int r = (int)(threadIdx.x / kTPR), part = (int)(threadIdx.x % kTPR);
+  if (r < count) {
+    const uint32_t gid = min(sorted_gid[first + (uint32_t)r], (uint32_t)(n_gauss - 1));
+    const float4* src = reinterpret_cast<const float4*>(vrec + gid) + kVec * part;
+    float4* dst = reinterpret_cast<float4*>(srec + r) + kVec * part;
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) dst[k] = src[k];
+  }
+}
+
 // Four waves per SIMD: the register budget (128 VGPRs) that pair_grad fits in without
 // spilling.
 template <int FILTER, bool MARGINAL, bool GEER>
@@ -89,7 +107,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       break;
     }
     const int cnt = (int)min(64u, rg.y - base);
-    stage_records(srec, vrec, sorted_gid, base, cnt);
+    stage_replay_records(srec, vrec, sorted_gid, n_gauss, base, cnt);
     for (int k = lane; k < 64 * (kGradLen + 1); k += 64) (&gacc[wave][0][0])[k] = 0.f;
     __syncthreads();
     if (__ballot(!done) != 0) {
