@@ -193,12 +193,17 @@ unsigned long long* host_word() {
   return w.p;
 }
 
-// An event the host waits on: the pair count's copy, not the work queued after it.
+// An event the host waits on: the pair count's copy, not the work queued after it.  A
+// call that leaves early (an error) still waits for the copy before it returns, so that
+// it cannot land in the thread's pinned word during a later call on another stream.
 struct ReadEvent {
   hipEvent_t e = nullptr;
   ReadEvent() { CG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
   ~ReadEvent() {
-    if (e) (void)hipEventDestroy(e);
+    if (e) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
   }
   ReadEvent(const ReadEvent&) = delete;
   ReadEvent& operator=(const ReadEvent&) = delete;
