@@ -103,6 +103,7 @@ struct PairFoot {
   float ex0, ex1, ex2, ey0, ey1, ey2;  // e_x, e_y
   float K11, K12, K22;                 // E^T E / 3
   float h1, h2;                        // E^T q / sqrt 3
+  float bxa, bya;                      // (W (d_x - d)) . a, (W (d_y - d)) . a
 };
 
 // e_x and e_y of Eq. 6 in whitened space.
@@ -114,8 +115,10 @@ __device__ __forceinline__ void pair_edges(const Record& R, const PairPixel& p, 
   const float by0 = W[0] * p.y0 + W[1] * p.y1 + W[2] * p.y2;
   const float by1 = W[3] * p.y0 + W[4] * p.y1 + W[5] * p.y2;
   const float by2 = W[6] * p.y0 + W[7] * p.y1 + W[8] * p.y2;
-  const float px = (bx0 * g.ax + bx1 * g.ay + bx2 * g.az) * g.rn;
-  const float py = (by0 * g.ax + by1 * g.ay + by2 * g.az) * g.rn;
+  f.bxa = bx0 * g.ax + bx1 * g.ay + bx2 * g.az;
+  f.bya = by0 * g.ax + by1 * g.ay + by2 * g.az;
+  const float px = f.bxa * g.rn;
+  const float py = f.bya * g.rn;
   const float t = g.tstar;
   f.ex0 = t * (bx0 - px * g.ax); f.ex1 = t * (bx1 - px * g.ay); f.ex2 = t * (bx2 - px * g.az);
   f.ey0 = t * (by0 - py * g.ax); f.ey1 = t * (by1 - py * g.ay); f.ey2 = t * (by2 - py * g.az);
@@ -315,260 +318,6 @@ __device__ __forceinline__ bool pair_response(const Record& R, const PairPixel& 
   if (!pair_cheap<FILTER>(R, p, O, o, g)) return false;
   T = pair_full<FILTER, MARGINAL, GEER>(R, p, g);
   return true;
-}
-
-}  // namespace cg
-
-namespace cg {
-
-// ---------------------------------------------------------------------------- backward
-// Gradient of one pair's response T with respect to its record: dL/dT = dT is given;
-// the result is written to g[0..15] = (dW[9], dmu[3], dsigma, dsp2[3]).  gm, ft, fl
-// and filt are the forward intermediates left by pair_cheap and pair_full_keep for this
-// pair; every step is differentiated in reverse order.  G = g(Phi) (the marginal
-// composition) is differentiated in closed form: with both eigenvalues above rho^2,
-// G = I - rho^2 Phi^{-1}; with one, G = g+ u u^T (u the leading eigenvector); at the
-// clamp kink the clamped branch's (zero) derivative is used.
-template <int FILTER, bool MARGINAL, bool GEER>
-__device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, const PairGeom& gm, const PairFoot& ft,
-                                          const PairFloor& fl, bool filt, float dT, float T,
-                                          float* __restrict__ g) {
-  const float* W = R.W;
-  const float wx = gm.wx, wy = gm.wy, wz = gm.wz;
-  const float yx = gm.yx, yy = gm.yy, yz = gm.yz;
-  const float ya = gm.ya;
-  const float f = ya * gm.rn;
-
-  // adjoints
-  // reverse mode only: hardware reciprocals are accurate enough for the gradients
-  float dsig = dT * T * fast_rcp(R.sigma);
-  const float dlogT = dT * T;
-  float dD2 = 0.f;
-  float dq0 = 0.f, dq1 = 0.f, dq2 = 0.f;
-  float dts = 0.f;
-  float da0 = 0.f, da1 = 0.f, da2 = 0.f, drn = 0.f;
-  float dW[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) dW[k] = 0.f;
-  float dsp0 = 0.f, dsp1 = 0.f, dsp2 = 0.f;
-  // ray-integral backbone: T carries sqrt(rn) = 1 / |a|
-  if (GEER) drn += 0.5f * dlogT * fast_rcp(gm.rn);
-
-  if (FILTER == 0) {
-    dD2 = -0.5f * dlogT;
-  } else {
-    const float G11 = fl.G11, G12 = fl.G12, G22 = fl.G22;
-    const float P11 = fl.P11, P12 = fl.P12, P22 = fl.P22, lp = fl.lp, rr = fl.rr, gp = fl.gp;
-    float c2 = 0.f, s2 = 0.f, detP = 0.f;
-    int gcase = 0;  // 0: no floor; 1: G = I - rho^2 Phi^-1; 2: G = g+ u u^T; 3: G = 0
-    const bool floor_on = MARGINAL && R.rho2 > 0.f;
-    if (floor_on) {
-      if (!filt) {
-        gcase = 3;
-      } else if (fl.lm > R.rho2) {
-        gcase = 1;
-        detP = P11 * P22 - P12 * P12;
-      } else {
-        gcase = 2;
-        const float irr = fast_rcp(rr);
-        c2 = fl.dd * irr;
-        s2 = P12 * irr;
-      }
-    }
-    float dK11 = 0.f, dK12 = 0.f, dK22 = 0.f, dh1 = 0.f, dh2 = 0.f;
-    float dG11 = 0.f, dG12 = 0.f, dG22 = 0.f;
-    if (!filt) {
-      dD2 = -0.5f * dlogT;
-    } else if (FILTER == 2) {
-      const float tau = floor_on ? (G11 * ft.K11 + 2.f * G12 * ft.K12 + G22 * ft.K22) : (ft.K11 + ft.K22);
-      const float s = 1.f + 0.5f * tau;
-      const float is = fast_rcp(s);
-      dD2 = -0.5f * is * dlogT;
-      const float ds = dlogT * (-is + 0.5f * gm.D2 * is * is);
-      const float dtau = 0.5f * ds;
-      if (floor_on) {
-        dK11 += dtau * G11; dK12 += 2.f * dtau * G12; dK22 += dtau * G22;
-        dG11 += dtau * ft.K11; dG12 += 2.f * dtau * ft.K12; dG22 += dtau * ft.K22;
-      } else {
-        dK11 += dtau; dK22 += dtau;
-      }
-    } else {
-      const float dQ = -0.5f * dlogT;
-      dD2 = dQ;
-      const float dquad = -dQ;
-      if (floor_on) {
-        const float M11 = 1.f + ft.K11 * G11 + ft.K12 * G12, M12 = ft.K11 * G12 + ft.K12 * G22;
-        const float M21 = ft.K12 * G11 + ft.K22 * G12, M22 = 1.f + ft.K12 * G12 + ft.K22 * G22;
-        const float det = M11 * M22 - M12 * M21;
-        const float idet = fast_rcp(det);
-        const float N11 = G11 * M22 - G12 * M21, N12 = G12 * M11 - G11 * M12;
-        const float N21 = G12 * M22 - G22 * M21, N22 = G22 * M11 - G12 * M12;
-        const float num = ft.h1 * (N11 * ft.h1 + N12 * ft.h2) + ft.h2 * (N21 * ft.h1 + N22 * ft.h2);
-        const float quad = num * idet;
-        // T carries det^{-1/2}: d log T / d det = -1/(2 det)
-        const float ddet = -0.5f * dlogT * idet - dquad * quad * idet;
-        const float dnum = dquad * idet;
-        const float dN11 = dnum * ft.h1 * ft.h1, dN12 = dnum * ft.h1 * ft.h2;
-        const float dN21 = dN12, dN22 = dnum * ft.h2 * ft.h2;
-        dh1 += dnum * (2.f * N11 * ft.h1 + (N12 + N21) * ft.h2);
-        dh2 += dnum * ((N12 + N21) * ft.h1 + 2.f * N22 * ft.h2);
-        float dM11 = 0.f, dM12 = 0.f, dM21 = 0.f, dM22 = 0.f;
-        dG11 += dN11 * M22 - dN12 * M12;
-        dG12 += -dN11 * M21 + dN12 * M11 + dN21 * M22 - dN22 * M12;
-        dG22 += -dN21 * M21 + dN22 * M11;
-        dM11 += dN12 * G12 + dN22 * G22 + ddet * M22;
-        dM12 += -dN12 * G11 - dN22 * G12 - ddet * M21;
-        dM21 += -dN11 * G12 - dN21 * G22 - ddet * M12;
-        dM22 += dN11 * G11 + dN21 * G12 + ddet * M11;
-        dK11 += dM11 * G11 + dM12 * G12;
-        dK12 += dM11 * G12 + dM12 * G22 + dM21 * G11 + dM22 * G12;
-        dK22 += dM21 * G12 + dM22 * G22;
-        dG11 += dM11 * ft.K11 + dM21 * ft.K12;
-        dG12 += dM11 * ft.K12 + dM12 * ft.K11 + dM21 * ft.K22 + dM22 * ft.K12;
-        dG22 += dM12 * ft.K12 + dM22 * ft.K22;
-      } else {
-        const float Q11 = 1.f + ft.K11, Q22 = 1.f + ft.K22, Q12 = ft.K12;
-        const float det = Q11 * Q22 - Q12 * Q12;
-        const float idet = fast_rcp(det);
-        const float num = Q22 * ft.h1 * ft.h1 - 2.f * Q12 * ft.h1 * ft.h2 + Q11 * ft.h2 * ft.h2;
-        const float quad = num * idet;
-        const float ddet = -0.5f * dlogT * idet - dquad * quad * idet;
-        const float dnum = dquad * idet;
-        dh1 += dnum * (2.f * Q22 * ft.h1 - 2.f * Q12 * ft.h2);
-        dh2 += dnum * (2.f * Q11 * ft.h2 - 2.f * Q12 * ft.h1);
-        dK22 += dnum * ft.h1 * ft.h1 + ddet * Q11;
-        dK11 += dnum * ft.h2 * ft.h2 + ddet * Q22;
-        dK12 += -2.f * dnum * ft.h1 * ft.h2 - 2.f * ddet * Q12;
-      }
-    }
-    // G = g(Phi) -> Phi
-    float dP11 = 0.f, dP12 = 0.f, dP22 = 0.f;
-    if (gcase == 1) {
-      // G11 = 1 - rho2 P22/det, G22 = 1 - rho2 P11/det, G12 = rho2 P12/det
-      const float r2 = R.rho2, id = fast_rcp(detP);
-      const float Gp11 = -r2 * P22 * id, Gp22 = -r2 * P11 * id, Gp12 = r2 * P12 * id;  // G - I
-      // d(1/det) = -(P22 dP11 + P11 dP22 - 2 P12 dP12) / det^2
-      const float s = dG11 * Gp11 + dG22 * Gp22 + dG12 * Gp12;  // sum dG * (G - I)
-      dP11 += -dG22 * r2 * id - s * P22 * id;
-      dP22 += -dG11 * r2 * id - s * P11 * id;
-      dP12 += dG12 * r2 * id + 2.f * s * P12 * id;
-    } else if (gcase == 2) {
-      const float dgp = 0.5f * (dG11 * (1.f + c2) + dG22 * (1.f - c2) + dG12 * s2);
-      const float dc2 = 0.5f * gp * (dG11 - dG22), ds2 = 0.5f * gp * dG12;
-      const float ilp = fast_rcp(lp), irr = fast_rcp(rr);
-      const float dlp = dgp * R.rho2 * ilp * ilp;
-      float dm = dlp, drr = dlp;
-      float ddd = dc2 * irr;
-      drr += (-dc2 * c2 - ds2 * s2) * irr;
-      float dpq = ds2 * irr;
-      ddd += drr * c2;
-      dpq += drr * s2;
-      dP11 += 0.5f * (dm + ddd);
-      dP22 += 0.5f * (dm - ddd);
-      dP12 += dpq;
-    }
-    // Phi, K, h -> e_x, e_y, s'^2, q
-    constexpr float third = 1.f / 3.f;
-    constexpr float isq3 = 0.57735026918962576f;
-    float dex0 = (2.f * dK11 * ft.ex0 + dK12 * ft.ey0) * third + dh1 * gm.qx * isq3;
-    float dex1 = (2.f * dK11 * ft.ex1 + dK12 * ft.ey1) * third + dh1 * gm.qy * isq3;
-    float dex2 = (2.f * dK11 * ft.ex2 + dK12 * ft.ey2) * third + dh1 * gm.qz * isq3;
-    float dey0 = (2.f * dK22 * ft.ey0 + dK12 * ft.ex0) * third + dh2 * gm.qx * isq3;
-    float dey1 = (2.f * dK22 * ft.ey1 + dK12 * ft.ex1) * third + dh2 * gm.qy * isq3;
-    float dey2 = (2.f * dK22 * ft.ey2 + dK12 * ft.ex2) * third + dh2 * gm.qz * isq3;
-    dq0 += (dh1 * ft.ex0 + dh2 * ft.ey0) * isq3;
-    dq1 += (dh1 * ft.ex1 + dh2 * ft.ey1) * isq3;
-    dq2 += (dh1 * ft.ex2 + dh2 * ft.ey2) * isq3;
-    if (gcase == 1 || gcase == 2) {
-      dex0 += (2.f * dP11 * ft.ex0 + dP12 * ft.ey0) * R.sp2[0] * third;
-      dex1 += (2.f * dP11 * ft.ex1 + dP12 * ft.ey1) * R.sp2[1] * third;
-      dex2 += (2.f * dP11 * ft.ex2 + dP12 * ft.ey2) * R.sp2[2] * third;
-      dey0 += (2.f * dP22 * ft.ey0 + dP12 * ft.ex0) * R.sp2[0] * third;
-      dey1 += (2.f * dP22 * ft.ey1 + dP12 * ft.ex1) * R.sp2[1] * third;
-      dey2 += (2.f * dP22 * ft.ey2 + dP12 * ft.ex2) * R.sp2[2] * third;
-      dsp0 += (dP11 * ft.ex0 * ft.ex0 + dP12 * ft.ex0 * ft.ey0 + dP22 * ft.ey0 * ft.ey0) * third;
-      dsp1 += (dP11 * ft.ex1 * ft.ex1 + dP12 * ft.ex1 * ft.ey1 + dP22 * ft.ey1 * ft.ey1) * third;
-      dsp2 += (dP11 * ft.ex2 * ft.ex2 + dP12 * ft.ex2 * ft.ey2 + dP22 * ft.ey2 * ft.ey2) * third;
-    }
-    // e_i = t* (b_i - p_i a), p_i = (b_i . a) rn, b_i = W delta_i
-    const float bx0 = W[0] * p.x0 + W[1] * p.x1 + W[2] * p.x2;
-    const float bx1 = W[3] * p.x0 + W[4] * p.x1 + W[5] * p.x2;
-    const float bx2 = W[6] * p.x0 + W[7] * p.x1 + W[8] * p.x2;
-    const float by0 = W[0] * p.y0 + W[1] * p.y1 + W[2] * p.y2;
-    const float by1 = W[3] * p.y0 + W[4] * p.y1 + W[5] * p.y2;
-    const float by2 = W[6] * p.y0 + W[7] * p.y1 + W[8] * p.y2;
-    const float bxa = bx0 * gm.ax + bx1 * gm.ay + bx2 * gm.az;
-    const float bya = by0 * gm.ax + by1 * gm.ay + by2 * gm.az;
-    const float px_ = bxa * gm.rn, py_ = bya * gm.rn;
-    const float ux0 = bx0 - px_ * gm.ax, ux1 = bx1 - px_ * gm.ay, ux2 = bx2 - px_ * gm.az;
-    const float uy0 = by0 - py_ * gm.ax, uy1 = by1 - py_ * gm.ay, uy2 = by2 - py_ * gm.az;
-    const float t = gm.tstar;
-    dts += dex0 * ux0 + dex1 * ux1 + dex2 * ux2 + dey0 * uy0 + dey1 * uy1 + dey2 * uy2;
-    const float dux0 = t * dex0, dux1 = t * dex1, dux2 = t * dex2;
-    const float duy0 = t * dey0, duy1 = t * dey1, duy2 = t * dey2;
-    const float dpx = -(dux0 * gm.ax + dux1 * gm.ay + dux2 * gm.az);
-    const float dpy = -(duy0 * gm.ax + duy1 * gm.ay + duy2 * gm.az);
-    da0 += -px_ * dux0 - py_ * duy0 + (dpx * bx0 + dpy * by0) * gm.rn;
-    da1 += -px_ * dux1 - py_ * duy1 + (dpx * bx1 + dpy * by1) * gm.rn;
-    da2 += -px_ * dux2 - py_ * duy2 + (dpx * bx2 + dpy * by2) * gm.rn;
-    drn += dpx * bxa + dpy * bya;
-    const float dbx0 = dux0 + dpx * gm.rn * gm.ax, dbx1 = dux1 + dpx * gm.rn * gm.ay, dbx2 = dux2 + dpx * gm.rn * gm.az;
-    const float dby0 = duy0 + dpy * gm.rn * gm.ax, dby1 = duy1 + dpy * gm.rn * gm.ay, dby2 = duy2 + dpy * gm.rn * gm.az;
-    dW[0] += dbx0 * p.x0 + dby0 * p.y0; dW[1] += dbx0 * p.x1 + dby0 * p.y1; dW[2] += dbx0 * p.x2 + dby0 * p.y2;
-    dW[3] += dbx1 * p.x0 + dby1 * p.y0; dW[4] += dbx1 * p.x1 + dby1 * p.y1; dW[5] += dbx1 * p.x2 + dby1 * p.y2;
-    dW[6] += dbx2 * p.x0 + dby2 * p.y0; dW[7] += dbx2 * p.x1 + dby2 * p.y1; dW[8] += dbx2 * p.x2 + dby2 * p.y2;
-  }
-  // D^2 = |q|^2
-  dq0 += 2.f * dD2 * gm.qx;
-  dq1 += 2.f * dD2 * gm.qy;
-  dq2 += 2.f * dD2 * gm.qz;
-  // q = y - f a
-  float dy0 = dq0, dy1 = dq1, dy2 = dq2;
-  float df = -(dq0 * gm.ax + dq1 * gm.ay + dq2 * gm.az);
-  da0 += -f * dq0;
-  da1 += -f * dq1;
-  da2 += -f * dq2;
-  // t* = t_e - f
-  const float dte = dts;
-  df += -dts;
-  // f = (y . a) rn
-  dy0 += df * gm.rn * gm.ax;
-  dy1 += df * gm.rn * gm.ay;
-  dy2 += df * gm.rn * gm.az;
-  da0 += df * gm.rn * yx;
-  da1 += df * gm.rn * yy;
-  da2 += df * gm.rn * yz;
-  drn += df * ya;
-  // rn = 1 / |a|^2
-  const float dn = -drn * gm.rn * gm.rn;
-  da0 += 2.f * dn * gm.ax;
-  da1 += 2.f * dn * gm.ay;
-  da2 += 2.f * dn * gm.az;
-  // y = -W w
-  dW[0] -= dy0 * wx; dW[1] -= dy0 * wy; dW[2] -= dy0 * wz;
-  dW[3] -= dy1 * wx; dW[4] -= dy1 * wy; dW[5] -= dy1 * wz;
-  dW[6] -= dy2 * wx; dW[7] -= dy2 * wy; dW[8] -= dy2 * wz;
-  const float dw0 = -(W[0] * dy0 + W[3] * dy1 + W[6] * dy2);
-  const float dw1 = -(W[1] * dy0 + W[4] * dy1 + W[7] * dy2);
-  const float dw2 = -(W[2] * dy0 + W[5] * dy1 + W[8] * dy2);
-  // a = W d
-  dW[0] += da0 * p.a0; dW[1] += da0 * p.a1; dW[2] += da0 * p.a2;
-  dW[3] += da1 * p.a0; dW[4] += da1 * p.a1; dW[5] += da1 * p.a2;
-  dW[6] += da2 * p.a0; dW[7] += da2 * p.a1; dW[8] += da2 * p.a2;
-  // w = (I - d d^T)(mu - o), t_e = d . (mu - o)
-  const float dwd = dw0 * p.a0 + dw1 * p.a1 + dw2 * p.a2;
-  const float dmu0 = dw0 - dwd * p.a0 + dte * p.a0;
-  const float dmu1 = dw1 - dwd * p.a1 + dte * p.a1;
-  const float dmu2 = dw2 - dwd * p.a2 + dte * p.a2;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) g[k] = dW[k];
-  g[9] = dmu0;
-  g[10] = dmu1;
-  g[11] = dmu2;
-  g[12] = dsig;
-  g[13] = dsp0;
-  g[14] = dsp1;
-  g[15] = dsp2;
 }
 
 }  // namespace cg

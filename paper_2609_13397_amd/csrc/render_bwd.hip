@@ -17,6 +17,7 @@
 #include <algorithm>
 
 #include "fwd_state.hpp"
+#include "pair_grad.hpp"
 #include "pixel_buf.hpp"
 #include "sh.hpp"
 
