@@ -138,46 +138,48 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
       dP22 += 0.5f * (dm - ddd);
       dP12 += dpq;
     }
-    // Phi, K, h -> e_x, e_y, s'^2, q
-    constexpr float third = 1.f / 3.f;
+    // Phi, K, h -> e_x, e_y, s'^2, q, with the factors 2/3, 1/3 and 1/sqrt 3 applied to
+    // the coefficients once
+    constexpr float third = 1.f / 3.f, two_thirds = 2.f / 3.f;
     constexpr float isq3 = 0.57735026918962576f;
-    float dex0 = (2.f * dK11 * ft.ex0 + dK12 * ft.ey0) * third + dh1 * gm.qx * isq3;
-    float dex1 = (2.f * dK11 * ft.ex1 + dK12 * ft.ey1) * third + dh1 * gm.qy * isq3;
-    float dex2 = (2.f * dK11 * ft.ex2 + dK12 * ft.ey2) * third + dh1 * gm.qz * isq3;
-    float dey0 = (2.f * dK22 * ft.ey0 + dK12 * ft.ex0) * third + dh2 * gm.qx * isq3;
-    float dey1 = (2.f * dK22 * ft.ey1 + dK12 * ft.ex1) * third + dh2 * gm.qy * isq3;
-    float dey2 = (2.f * dK22 * ft.ey2 + dK12 * ft.ex2) * third + dh2 * gm.qz * isq3;
-    dq0 += (dh1 * ft.ex0 + dh2 * ft.ey0) * isq3;
-    dq1 += (dh1 * ft.ex1 + dh2 * ft.ey1) * isq3;
-    dq2 += (dh1 * ft.ex2 + dh2 * ft.ey2) * isq3;
+    const float hx = dh1 * isq3, hy = dh2 * isq3;
+    float cxx0 = dK11 * two_thirds, cxy0 = dK12 * third, cyy0 = dK22 * two_thirds;
+    float cxx1 = cxx0, cxx2 = cxx0, cxy1 = cxy0, cxy2 = cxy0, cyy1 = cyy0, cyy2 = cyy0;
     if (gcase == 1 || gcase == 2) {
-      dex0 += (2.f * dP11 * ft.ex0 + dP12 * ft.ey0) * R.sp2[0] * third;
-      dex1 += (2.f * dP11 * ft.ex1 + dP12 * ft.ey1) * R.sp2[1] * third;
-      dex2 += (2.f * dP11 * ft.ex2 + dP12 * ft.ey2) * R.sp2[2] * third;
-      dey0 += (2.f * dP22 * ft.ey0 + dP12 * ft.ex0) * R.sp2[0] * third;
-      dey1 += (2.f * dP22 * ft.ey1 + dP12 * ft.ex1) * R.sp2[1] * third;
-      dey2 += (2.f * dP22 * ft.ey2 + dP12 * ft.ex2) * R.sp2[2] * third;
-      dsp0 += (dP11 * ft.ex0 * ft.ex0 + dP12 * ft.ex0 * ft.ey0 + dP22 * ft.ey0 * ft.ey0) * third;
-      dsp1 += (dP11 * ft.ex1 * ft.ex1 + dP12 * ft.ex1 * ft.ey1 + dP22 * ft.ey1 * ft.ey1) * third;
-      dsp2 += (dP11 * ft.ex2 * ft.ex2 + dP12 * ft.ex2 * ft.ey2 + dP22 * ft.ey2 * ft.ey2) * third;
+      // Phi = E^T S'^2 E / 3 adds the same terms, weighted by s'^2 per component
+      const float pxx = dP11 * two_thirds, pxy = dP12 * third, pyy = dP22 * two_thirds;
+      cxx0 = fmaf(pxx, R.sp2[0], cxx0); cxx1 = fmaf(pxx, R.sp2[1], cxx1); cxx2 = fmaf(pxx, R.sp2[2], cxx2);
+      cxy0 = fmaf(pxy, R.sp2[0], cxy0); cxy1 = fmaf(pxy, R.sp2[1], cxy1); cxy2 = fmaf(pxy, R.sp2[2], cxy2);
+      cyy0 = fmaf(pyy, R.sp2[0], cyy0); cyy1 = fmaf(pyy, R.sp2[1], cyy1); cyy2 = fmaf(pyy, R.sp2[2], cyy2);
+      const float qxx = dP11 * third, qyy = dP22 * third;
+      dsp0 += ft.ex0 * (qxx * ft.ex0 + pxy * ft.ey0) + qyy * ft.ey0 * ft.ey0;
+      dsp1 += ft.ex1 * (qxx * ft.ex1 + pxy * ft.ey1) + qyy * ft.ey1 * ft.ey1;
+      dsp2 += ft.ex2 * (qxx * ft.ex2 + pxy * ft.ey2) + qyy * ft.ey2 * ft.ey2;
     }
+    const float dex0 = cxx0 * ft.ex0 + cxy0 * ft.ey0 + hx * gm.qx;
+    const float dex1 = cxx1 * ft.ex1 + cxy1 * ft.ey1 + hx * gm.qy;
+    const float dex2 = cxx2 * ft.ex2 + cxy2 * ft.ey2 + hx * gm.qz;
+    const float dey0 = cyy0 * ft.ey0 + cxy0 * ft.ex0 + hy * gm.qx;
+    const float dey1 = cyy1 * ft.ey1 + cxy1 * ft.ex1 + hy * gm.qy;
+    const float dey2 = cyy2 * ft.ey2 + cxy2 * ft.ex2 + hy * gm.qz;
+    dq0 += hx * ft.ex0 + hy * ft.ey0;
+    dq1 += hx * ft.ex1 + hy * ft.ey1;
+    dq2 += hx * ft.ex2 + hy * ft.ey2;
     // e_i = t* u_i with u_i = b_i - p_i a, p_i = (b_i . a) rn and b_i = W delta_i; the
     // forward recompute leaves e_i and b_i . a, so u_i = e_i / t* and b_i = u_i + p_i a
     const float t = gm.tstar, it = fast_rcp(t);
     const float bxa = ft.bxa, bya = ft.bya;
     const float px_ = bxa * gm.rn, py_ = bya * gm.rn;
-    const float ux0 = ft.ex0 * it, ux1 = ft.ex1 * it, ux2 = ft.ex2 * it;
-    const float uy0 = ft.ey0 * it, uy1 = ft.ey1 * it, uy2 = ft.ey2 * it;
-    dts += dex0 * ux0 + dex1 * ux1 + dex2 * ux2 + dey0 * uy0 + dey1 * uy1 + dey2 * uy2;
+    dts += (dex0 * ft.ex0 + dex1 * ft.ex1 + dex2 * ft.ex2 + dey0 * ft.ey0 + dey1 * ft.ey1 + dey2 * ft.ey2) * it;
     const float dux0 = t * dex0, dux1 = t * dex1, dux2 = t * dex2;
     const float duy0 = t * dey0, duy1 = t * dey1, duy2 = t * dey2;
     const float dpx = -(dux0 * gm.ax + dux1 * gm.ay + dux2 * gm.az);
     const float dpy = -(duy0 * gm.ax + duy1 * gm.ay + duy2 * gm.az);
-    // (dpx b_x + dpy b_y) rn, with b_i = u_i + p_i a
-    const float sa = (dpx * px_ + dpy * py_) * gm.rn;
-    da0 += -px_ * dux0 - py_ * duy0 + (dpx * ux0 + dpy * uy0) * gm.rn + sa * gm.ax;
-    da1 += -px_ * dux1 - py_ * duy1 + (dpx * ux1 + dpy * uy1) * gm.rn + sa * gm.ay;
-    da2 += -px_ * dux2 - py_ * duy2 + (dpx * ux2 + dpy * uy2) * gm.rn + sa * gm.az;
+    // (dpx b_x + dpy b_y) rn, with b_i = e_i / t* + p_i a
+    const float ir = it * gm.rn, sa = (dpx * px_ + dpy * py_) * gm.rn;
+    da0 += -px_ * dux0 - py_ * duy0 + (dpx * ft.ex0 + dpy * ft.ey0) * ir + sa * gm.ax;
+    da1 += -px_ * dux1 - py_ * duy1 + (dpx * ft.ex1 + dpy * ft.ey1) * ir + sa * gm.ay;
+    da2 += -px_ * dux2 - py_ * duy2 + (dpx * ft.ex2 + dpy * ft.ey2) * ir + sa * gm.az;
     drn += dpx * bxa + dpy * bya;
     const float dbx0 = dux0 + dpx * gm.rn * gm.ax, dbx1 = dux1 + dpx * gm.rn * gm.ay, dbx2 = dux2 + dpx * gm.rn * gm.az;
     const float dby0 = duy0 + dpy * gm.rn * gm.ax, dby1 = duy1 + dpy * gm.rn * gm.ay, dby2 = duy2 + dpy * gm.rn * gm.az;

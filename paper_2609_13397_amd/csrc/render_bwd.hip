@@ -156,12 +156,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 gv[16] = G0 * w;
                 gv[17] = G1 * w;
                 gv[18] = G2 * w;
-                if (T < o.alpha_max) {
-                  pair_grad<FILTER, MARGINAL, GEER>(R, px, gm, ft, fl, filt, dalpha, T, gv);
-                } else {  // alpha clamped at alpha_max: no gradient through T
-#pragma unroll
-                  for (int q = 0; q < 16; ++q) gv[q] = 0.f;
-                }
+                // alpha clamped at alpha_max: no gradient through T (every adjoint of
+                // pair_grad is a multiple of dL/dT, so dL/dT = 0 gives exact zeros)
+                pair_grad<FILTER, MARGINAL, GEER>(R, px, gm, ft, fl, filt, T < o.alpha_max ? dalpha : 0.f, T, gv);
                 Ttr = test;
               }
             }
