@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       while (m) {
         const int k = (int)__builtin_ctzll(m);
         m &= m - 1;
-        float gv[kGradLen];  // written by the contributing lanes, zeroed for the others below
+        float gv[kGradLen];  // written by the contributing lanes only (the reduction adds zeros for the others)
         bool contrib = false;
         if (!done) {
           const Record& R = srec[k];
@@ -165,12 +165,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
           }
         }
         if (__ballot(contrib) != 0) {
-          if (!contrib) {
-#pragma unroll
-            for (int q = 0; q < kGradLen; ++q) gv[q] = 0.f;
-          }
-          gv[kGradLen - 1] = 0.f;  // padding component
-          const float s = wave_sum20(gv, lane);
+          // the lanes that did not contribute add zeros; gv[19] is the padding component
+          const float s = wave_sum20(gv, contrib, lane);
           if (red_idx >= 0) gacc[wave][k][red_idx] = s;
         }
       }

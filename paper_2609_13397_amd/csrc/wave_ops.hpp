@@ -70,11 +70,13 @@ __device__ __forceinline__ float wave_max(float v) {
 // halves the number of values a lane carries (20 -> 10 -> 5 -> 3 -> 2 -> 1, odd counts
 // padded with a zero), so the whole reduction costs 22 lane moves instead of 120.
 // Lane l ends with the total of value wave_sum20_index(l), or of a padding slot when
-// that index is negative; each of the 20 values ends in exactly one even lane.
-__device__ __forceinline__ float wave_sum20(const float v[20], int lane) {
+// that index is negative; each of the 20 values ends in exactly one even lane.  Lanes
+// with keep false add zeros (their v is not read), and v[19] is taken as zero: the
+// selections feed the first swaps directly, so no lane needs to clear its values first.
+__device__ __forceinline__ float wave_sum20(const float v[20], bool keep, int lane) {
   float w[10], u[5], n3[3], n2[2];
 #pragma unroll
-  for (int i = 0; i < 10; ++i) w[i] = swap_add32(v[i], v[i + 10]);
+  for (int i = 0; i < 10; ++i) w[i] = swap_add32(keep ? v[i] : 0.f, (keep && i < 9) ? v[i + 10] : 0.f);
 #pragma unroll
   for (int i = 0; i < 5; ++i) u[i] = swap_add16(w[i], w[i + 5]);
   const bool h3 = (lane >> 3) & 1, h2 = (lane >> 2) & 1, h1 = (lane >> 1) & 1;
