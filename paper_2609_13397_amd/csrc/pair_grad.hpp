@@ -143,19 +143,17 @@ __device__ __forceinline__ void pair_grad(const Record& R, const PairPixel& p, c
     constexpr float third = 1.f / 3.f, two_thirds = 2.f / 3.f;
     constexpr float isq3 = 0.57735026918962576f;
     const float hx = dh1 * isq3, hy = dh2 * isq3;
-    float cxx0 = dK11 * two_thirds, cxy0 = dK12 * third, cyy0 = dK22 * two_thirds;
-    float cxx1 = cxx0, cxx2 = cxx0, cxy1 = cxy0, cxy2 = cxy0, cyy1 = cyy0, cyy2 = cyy0;
-    if (gcase == 1 || gcase == 2) {
-      // Phi = E^T S'^2 E / 3 adds the same terms, weighted by s'^2 per component
-      const float pxx = dP11 * two_thirds, pxy = dP12 * third, pyy = dP22 * two_thirds;
-      cxx0 = fmaf(pxx, R.sp2[0], cxx0); cxx1 = fmaf(pxx, R.sp2[1], cxx1); cxx2 = fmaf(pxx, R.sp2[2], cxx2);
-      cxy0 = fmaf(pxy, R.sp2[0], cxy0); cxy1 = fmaf(pxy, R.sp2[1], cxy1); cxy2 = fmaf(pxy, R.sp2[2], cxy2);
-      cyy0 = fmaf(pyy, R.sp2[0], cyy0); cyy1 = fmaf(pyy, R.sp2[1], cyy1); cyy2 = fmaf(pyy, R.sp2[2], cyy2);
-      const float qxx = dP11 * third, qyy = dP22 * third;
-      dsp0 += ft.ex0 * (qxx * ft.ex0 + pxy * ft.ey0) + qyy * ft.ey0 * ft.ey0;
-      dsp1 += ft.ex1 * (qxx * ft.ex1 + pxy * ft.ey1) + qyy * ft.ey1 * ft.ey1;
-      dsp2 += ft.ex2 * (qxx * ft.ex2 + pxy * ft.ey2) + qyy * ft.ey2 * ft.ey2;
-    }
+    const float kxx = dK11 * two_thirds, kxy = dK12 * third, kyy = dK22 * two_thirds;
+    // Phi = E^T S'^2 E / 3 adds the same terms weighted by s'^2 per component (dPhi is
+    // zero unless the floor clamps, so these need no branch)
+    const float pxx = dP11 * two_thirds, pxy = dP12 * third, pyy = dP22 * two_thirds;
+    const float cxx0 = fmaf(pxx, R.sp2[0], kxx), cxx1 = fmaf(pxx, R.sp2[1], kxx), cxx2 = fmaf(pxx, R.sp2[2], kxx);
+    const float cxy0 = fmaf(pxy, R.sp2[0], kxy), cxy1 = fmaf(pxy, R.sp2[1], kxy), cxy2 = fmaf(pxy, R.sp2[2], kxy);
+    const float cyy0 = fmaf(pyy, R.sp2[0], kyy), cyy1 = fmaf(pyy, R.sp2[1], kyy), cyy2 = fmaf(pyy, R.sp2[2], kyy);
+    const float qxx = dP11 * third, qyy = dP22 * third;
+    dsp0 += ft.ex0 * (qxx * ft.ex0 + pxy * ft.ey0) + qyy * ft.ey0 * ft.ey0;
+    dsp1 += ft.ex1 * (qxx * ft.ex1 + pxy * ft.ey1) + qyy * ft.ey1 * ft.ey1;
+    dsp2 += ft.ex2 * (qxx * ft.ex2 + pxy * ft.ey2) + qyy * ft.ey2 * ft.ey2;
     const float dex0 = cxx0 * ft.ex0 + cxy0 * ft.ey0 + hx * gm.qx;
     const float dex1 = cxx1 * ft.ex1 + cxy1 * ft.ey1 + hx * gm.qy;
     const float dex2 = cxx2 * ft.ex2 + cxy2 * ft.ey2 + hx * gm.qz;
