@@ -117,6 +117,54 @@ def test_backward_matches_oracle_gradient(case):
         assert nbad == 0, (k, el, nbad)
 
 
+def test_backward_with_cutoffs_matches_oracle_gradient():
+    """Pairs clamped at alpha_max pass no gradient through T, and pixels stop before the
+    pair that would take transmittance below T_min.  Ten SH Gaussians before a 96x72
+    pinhole (several tiles and a ragged last tile row): Gaussian 0 near the camera is
+    clamped at alpha_max = 0.95 on the central pixels, and the opaque Gaussian 1 behind
+    it stops pixels at T_min = 3e-3.  The GPU gradient is held to the oracle's, whose
+    cut-off branches are pinned to finite differences of whole renders.  Pixels where a
+    pair's response lies within 1e-4 of alpha_max get no upstream gradient: there the
+    FP32 and FP64 responses may fall on either side of the clamp."""
+    from paper_2609_13397_amd import render as R
+    sc = synth.make_scene(10, seed=23, layout="uniform", color="sh3", log_scale_mean=-2.0, log_scale_std=0.3)
+    sc["means"] *= 0.6
+    sc["means"][:, 0] = (0.02, -0.03, -1.8)
+    sc["log_scales"][:, 0] = np.log([0.3, 0.25, 0.2])
+    sc["opacity_logits"][0] = 9.0
+    sc["means"][:, 1] = (0.1, 0.05, 0.9)
+    sc["log_scales"][:, 1] = np.log([0.6, 0.5, 0.55])
+    sc["opacity_logits"][1] = 6.0
+    sc["rho2"] = np.full(10, 4e-4, np.float32)
+    w, h = 96, 72
+    cam = synth.camera(synth.PINHOLE, w, h, fx=80.0, fy=80.0, cx=w / 2, cy=h / 2, R_c2w=np.eye(3),
+                       origin=(0.0, 0.0, -3.0))
+    kw = dict(use_floor=True, alpha_max=0.95, T_min=3e-3)
+    oopts = O.Opts(use_floor=1, alpha_max=0.95, T_min=3e-3)
+    _say("backward with cut-offs")
+    ref_img = O.render(sc, cam, oopts, with_alt=True)
+    rays, _ = O.pixel_rays(cam)
+    T = np.stack([O.pair_batch(sc, i, np.array(cam["origin"]), rays.reshape(-1, 9), oopts)[:, 0]
+                  for i in range(sc["n"])])
+    clamped = (T >= oopts.alpha_max).sum()
+    stopped = int((ref_img["n_contrib"] < (T >= oopts.alpha_min).sum(0).reshape(h, w)).sum())
+    _say(f"   clamped pairs {clamped} stopped pixels {stopped}")
+    assert clamped >= 50 and stopped >= 20
+    G = upstream([cam], [ref_img])
+    near_clamp = (np.abs(T - oopts.alpha_max) < 1e-4).any(0).reshape(h, w)
+    G[0][near_clamp] = 0.0
+    ref = O.grad(sc, [cam], G, oopts)
+    g, rgba, info, mism = run_gpu(sc, [cam], R.RenderOpts(**kw), G)
+    _say(f"   pairs {info['n_pairs']} replay mismatches {mism} near-clamp pixels {int(near_clamp.sum())}")
+    assert mism == 0
+    worst = compare_grads(g, ref)
+    for k, (rel, el, nbad) in worst.items():
+        _say(f"   {k:15s} rel {rel:.2e} worst elem {el:.2e} bad {nbad}")
+    for k, (rel, el, nbad) in worst.items():
+        assert rel <= 1e-3, (k, rel)
+        assert nbad == 0, (k, el, nbad)
+
+
 def test_backward_deterministic_and_autograd():
     import torch
     from paper_2609_13397_amd import render as R
